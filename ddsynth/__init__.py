@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs for the DD projection workloads.
+
+Input generation only: a counter-based generator (Philox4x32-10) and the recipes
+that turn it into material data points, query states and initial assignments.
+Nothing here computes the DD metric, a projection or a finite-element quantity;
+the CPU oracle and the GPU library both consume the arrays produced here.
+
+Workload recipe (every configuration):
+  * strain components i.i.d. uniform in [-1e-3, 1e-3] (6 Voigt components,
+    engineering shear order 11, 22, 33, 23, 13, 12);
+  * stress = C0 strain + N(0, 2^2) MPa per component, C0 isotropic with
+    E = 200000 MPa, nu = 0.3 (1 % of the stress scale E * 1e-3 = 200 MPa);
+  * queries: a uniformly drawn data point plus N(0, (5e-5)^2) on each strain
+    component and N(0, 10^2) MPa on each stress component (5 % of the scales).
+
+The C core (gen.c) is compiled with gcc on first use; `build()` forces it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB_PATH = os.path.join(_HERE, "libddsynth.so")
+_lib = None
+
+E_MODULUS = 200000.0
+POISSON = 0.3
+EPS_AMP = 1.0e-3
+STRESS_SCALE = E_MODULUS * EPS_AMP          # 200 MPa
+DATA_NOISE_STD = 0.01 * STRESS_SCALE         # 2 MPa
+QUERY_EPS_STD = 0.05 * EPS_AMP               # 5e-5
+QUERY_SIG_STD = 0.05 * STRESS_SCALE          # 10 MPa
+
+
+def build(force: bool = True) -> str:
+    """Compile gen.c into libddsynth.so next to it (gcc, OpenMP)."""
+    global _lib
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+        _lib = None
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        u64, i64, u32, dbl = ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+        vp = ctypes.c_void_p
+        lib.ddsynth_philox.argtypes = [u64, u64, u32, vp]
+        lib.ddsynth_philox_many.argtypes = [u64, u32, vp, i64, vp]
+        lib.ddsynth_points.argtypes = [u64, i64, i64, dbl, vp, dbl, vp, vp]
+        lib.ddsynth_queries.argtypes = [u64, i64, vp, vp, i64, dbl, dbl, vp, vp, vp]
+        lib.ddsynth_indices.argtypes = [u64, i64, i64, vp]
+        lib.ddsynth_uniform.argtypes = [u64, i64, dbl, dbl, vp]
+        for f in ("ddsynth_philox", "ddsynth_philox_many", "ddsynth_points",
+                  "ddsynth_queries", "ddsynth_indices", "ddsynth_uniform"):
+            getattr(lib, f).restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 in numpy (used to cross-check the C core and device copies).
+# --------------------------------------------------------------------------
+_M0, _M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+_W0, _W1 = np.uint32(0x9E3779B9), np.uint32(0xBB67AE85)
+
+
+def philox_np(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 on counters ctr[..., 4] (uint32) with key[2] (uint32)."""
+    c = [ctr[..., i].astype(np.uint64) for i in range(4)]
+    k0, k1 = np.uint32(key[0]), np.uint32(key[1])
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = _M0 * c[0]
+        p1 = _M1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        n0 = hi1 ^ c[1] ^ np.uint64(k0)
+        n2 = hi0 ^ c[3] ^ np.uint64(k1)
+        c = [n0, lo1, n2, lo0]
+        k0 = np.uint32((int(k0) + int(_W0)) & 0xFFFFFFFF)
+        k1 = np.uint32((int(k1) + int(_W1)) & 0xFFFFFFFF)
+    return np.stack([x.astype(np.uint32) for x in c], axis=-1)
+
+
+def philox(seed: int, items: np.ndarray, stream: int) -> np.ndarray:
+    """C-core Philox blocks [n][4] for (item, stream) under seed."""
+    items = np.ascontiguousarray(items, dtype=np.uint64)
+    out = np.empty((items.size, 4), dtype=np.uint32)
+    _load().ddsynth_philox_many(seed, stream, _ptr(items), items.size, _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Recipes
+# --------------------------------------------------------------------------
+def isotropic_stiffness(E: float = E_MODULUS, nu: float = POISSON) -> np.ndarray:
+    """Isotropic 6x6 stiffness in Voigt order (11,22,33,23,13,12), engineering shear."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    for i in range(3):
+        C[i, i] = lam + 2.0 * mu
+        C[3 + i, 3 + i] = mu
+    return C
+
+
+def data_points(n: int, seed: int, first: int = 0, S0: np.ndarray | None = None,
+                eps_amp: float = EPS_AMP, noise_std: float = DATA_NOISE_STD):
+    """(strain[n][6], stress[n][6]) float64 for items first..first+n-1."""
+    S0 = isotropic_stiffness() if S0 is None else np.ascontiguousarray(S0, dtype=np.float64)
+    strain = np.empty((n, 6), dtype=np.float64)
+    stress = np.empty((n, 6), dtype=np.float64)
+    _load().ddsynth_points(seed, first, n, eps_amp, _ptr(S0), noise_std, _ptr(strain),
+                           _ptr(stress))
+    return strain, stress
+
+
+def queries(strain: np.ndarray, stress: np.ndarray, m: int, seed: int,
+            eps_std: float = QUERY_EPS_STD, sig_std: float = QUERY_SIG_STD):
+    """(q_strain[m][6], q_stress[m][6], base[m]) around uniformly drawn data points."""
+    strain = np.ascontiguousarray(strain, dtype=np.float64)
+    stress = np.ascontiguousarray(stress, dtype=np.float64)
+    qe = np.empty((m, 6), dtype=np.float64)
+    qs = np.empty((m, 6), dtype=np.float64)
+    base = np.empty(m, dtype=np.int64)
+    _load().ddsynth_queries(seed, m, _ptr(strain), _ptr(stress), strain.shape[0], eps_std,
+                            sig_std, _ptr(qe), _ptr(qs), _ptr(base))
+    return qe, qs, base
+
+
+def indices(n: int, n_data: int, seed: int) -> np.ndarray:
+    """Uniform random indices in [0, n_data) (e.g. a random initial DD assignment)."""
+    out = np.empty(n, dtype=np.int64)
+    _load().ddsynth_indices(seed, n, n_data, _ptr(out))
+    return out
+
+
+def uniform(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float64)
+    _load().ddsynth_uniform(seed, n, lo, hi, _ptr(out))
+    return out
+
+
+def states(strain: np.ndarray, stress: np.ndarray) -> np.ndarray:
+    """Pack (strain, stress) into phase-space states [n][12]."""
+    return np.ascontiguousarray(np.concatenate([strain, stress], axis=1))
+
+
+# Workload configurations (sizes of the measured cases).
+CONFIGS = {
+    0: dict(name="exact-fp64 N=65536 m=4096", N=65536, m=4096, data_seed=1000, query_seed=2000),
+    1: dict(name="dd-solve 8^3 hex N=1e6 traction 100 MPa", N=1_000_000, mesh=8,
+            traction=100.0, data_seed=1001),
+    2: dict(name="mixed-precision N=2^27 m=65536", N=1 << 27, m=65536, data_seed=1002,
+            query_seed=2002),
+    3: dict(name="ann N=1e9 16^3 hex", N=1_000_000_000, mesh=16, traction=100.0,
+            data_seed=1003),
+    4: dict(name="serving N=2^26 hex 4^3/8^3/16^3/24^3", N=1 << 26, meshes=(4, 8, 16, 24),
+            traction=(50.0, 200.0), data_seed=1004),
+}
