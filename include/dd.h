@@ -1,0 +1,180 @@
+/*
+ * dd.h — C ABI of libdd, the MI355X (gfx950) library for the nearest-neighbour
+ * projection at the heart of model-free data-driven (DD) solid mechanics.
+ *
+ * Problem statement (Eggersmann, Stainier, Ortiz, Reese, "Efficient data
+ * structures for model-free data-driven computational mechanics", Section 2):
+ * a material data set D = {(eps'_j, sig'_j)}, j = 0..N-1, of 12-component
+ * phase-space points (6 Voigt strains, 6 stresses); a constant symmetric
+ * positive definite metric C (6x6); for each admissible state y = (eps, sig)
+ * the projection P_D returns the data point minimising the local distance of
+ * eq. "distmetric",
+ *
+ *     dist = 1/2 (eps - eps').C(eps - eps') + 1/2 (sig - sig').C^-1(sig - sig'),
+ *
+ * (the factor 1/2 is the one of the global distance d^2 = sum_e 1/2 w_e d_e^2,
+ * so that sum_e w_e dist_e is the paper's global squared distance).  The DD
+ * solver alternates P_D with the constraint-set projection P_C (eqs. "KuE",
+ * "KeS") until the association stops changing.
+ *
+ * Conventions shared by every entry point
+ *   Layout     states, strains and stresses are row-major float64; a state is
+ *              (eps11, eps22, eps33, gamma23, gamma13, gamma12,
+ *               sig11, sig22, sig33, sig23, sig13, sig12), engineering shear
+ *              strains.  C is row-major 6x6 in the same Voigt order.
+ *   Memory     array arguments named *_dev are DEVICE pointers on the current
+ *              HIP device; small parameter arrays (C, options) are host memory.
+ *              Inputs are borrowed for the duration of the call; outputs are
+ *              caller-allocated.  A dataset owns the device memory it creates
+ *              until dd_dataset_destroy.
+ *   Streams    hip_stream is a hipStream_t (NULL = default stream).  Calls are
+ *              stream-ordered: device outputs are valid once that stream has
+ *              completed the work.  dd_dataset_create and dd_solve synchronise
+ *              the stream before returning; dd_project does not.
+ *   Indices    int64 at the ABI, always in the caller's original data order.
+ *   Ties       equal distances resolve to the lowest original index.
+ *   Errors     status codes only; dd_last_error() gives a thread-local message
+ *              for the last non-OK status of the calling thread.
+ *   Threads    a dataset is immutable after creation; concurrent dd_project
+ *              calls on different streams are safe.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dd_status {
+  DD_OK = 0,
+  DD_ERR_ARG = 1,            /* invalid argument (sizes, pointers, options, non-finite C) */
+  DD_ERR_NOT_SPD = 2,        /* metric C not symmetric positive definite */
+  DD_ERR_OOM = 3,            /* device allocation failed */
+  DD_ERR_DEVICE = 4,         /* a HIP runtime call failed */
+  DD_ERR_NOT_CONVERGED = 5,  /* dd_solve hit max_iter (results are still written) */
+  DD_ERR_TOO_LARGE = 6,      /* request exceeds a documented capacity */
+  DD_ERR_CANCELLED = 7,      /* serving request cancelled */
+  DD_ERR_UNSUPPORTED = 8,    /* the dataset lacks the pack a mode needs */
+  DD_ERR_TIMEOUT = 9         /* serving wait timed out */
+} dd_status;
+
+/* Projection algorithms (dd_project_opts.mode). */
+typedef enum dd_mode {
+  /* FP64 MFMA scan of the whole data set in whitened coordinates (expanded
+   * form), candidates inside a proven FP64 error margin reranked in the direct
+   * FP64 form.  Exact (indices of the FP64 nearest neighbour). */
+  DD_EXACT_FP64 = 0,
+  /* FP32 MFMA scan + FP64 rerank of the certified candidates.  Exact. */
+  DD_MIXED_FP32 = 1,
+  /* BF16 MFMA scan with FP32 accumulation on tile-centred coordinates, every
+   * candidate inside the proven BF16 error margin reranked in FP64; queries
+   * whose candidate list overflows are rescanned in FP64.  Exact. */
+  DD_MIXED_BF16 = 2,
+  /* Approximate search: warm-started walk over spatial cells (budgeted). */
+  DD_ANN = 3,
+  /* Plain FP64 direct-form scan (VALU), the simplest exact kernel. */
+  DD_DIRECT_FP64 = 4,
+  /* As DD_MIXED_BF16 with IEEE half precision instead of bfloat16. */
+  DD_MIXED_FP16 = 5
+} dd_mode;
+
+/* Packs a dataset can hold (dd_dataset_opts.packs bit mask). */
+#define DD_PACK_FP64 0x1u   /* whitened FP64 [N][12] + norms: DD_EXACT_FP64, DD_DIRECT_FP64, rerank */
+#define DD_PACK_FP32 0x2u   /* whitened FP32 [N][12] + norms: DD_MIXED_FP32 */
+#define DD_PACK_BF16 0x4u   /* tile-centred BF16 [N][16] + tile centres/radii: DD_MIXED_BF16 */
+#define DD_PACK_FP16 0x8u   /* tile-centred FP16 [N][16]: DD_MIXED_FP16 */
+#define DD_PACK_ANN 0x10u   /* cell index over the FP32 pack: DD_ANN */
+#define DD_PACK_DEFAULT (DD_PACK_FP64 | DD_PACK_BF16)
+
+typedef struct dd_dataset dd_dataset;
+
+typedef struct dd_dataset_opts {
+  uint32_t packs;      /* DD_PACK_* mask; 0 = DD_PACK_DEFAULT */
+  int32_t tile;        /* points per centring tile of the 16-bit packs; 0 = 256 (multiple of 32) */
+  int32_t ann_bits;    /* cell grid bits per principal axis for DD_PACK_ANN; 0 = default */
+} dd_dataset_opts;
+
+/* Per-call statistics (optional output of dd_project). */
+typedef struct dd_project_stats {
+  int64_t candidates;       /* candidates reranked in FP64 (mixed modes) */
+  int64_t overflowed;       /* queries rescanned by the FP64 fallback */
+  int64_t visited;          /* data points visited (DD_ANN) */
+  double scan_ms;           /* device time of the main scan kernel (HIP events on the call's stream) */
+  double total_ms;          /* device time from the first to the last kernel of the call */
+} dd_project_stats;
+
+typedef struct dd_project_opts {
+  int32_t mode;             /* dd_mode; default DD_EXACT_FP64 */
+  int32_t splits;           /* data splits per query block; 0 = automatic */
+  int32_t ann_budget;       /* DD_ANN: max cells visited per query (0 = unlimited, exact) */
+  int32_t reserved;
+  dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
+} dd_project_opts;
+
+/*
+ * Create a dataset from N material data points (Section 2: D = {(eps'_j,
+ * sig'_j)}) and the metric C (eq. "distmetric").
+ *   strain_dev, stress_dev  device float64 [N][6] each (borrowed)
+ *   N                        1 <= N <= 2^31 - 1
+ *   C                        host float64 [36], symmetric positive definite
+ *   opts                     NULL for defaults
+ * Whitens every point to (C^1/2 eps, C^-1/2 sig) (Section 3.2; C^1/2 = L^T of
+ * the Cholesky factor C = L L^T), orders the points spatially (principal-axis
+ * cell keys, stable radix sort) and builds the requested packs.
+ * Errors: DD_ERR_ARG (null pointers, N out of range, non-finite C or data),
+ * DD_ERR_NOT_SPD, DD_ERR_OOM, DD_ERR_DEVICE.  Synchronises hip_stream.
+ */
+dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev, int64_t N,
+                            const double* C, const dd_dataset_opts* opts, void* hip_stream,
+                            dd_dataset** out);
+
+/* Release a dataset's device memory (NULL is a no-op). */
+dd_status dd_dataset_destroy(dd_dataset* ds);
+
+/* Number of points, and bytes of device memory the dataset holds. */
+dd_status dd_dataset_info(const dd_dataset* ds, int64_t* n_points, int64_t* device_bytes);
+
+/*
+ * P_D (Section 2): for each of m states find the data point nearest under the
+ * metric, ties to the lowest original index.
+ *   states_dev          device float64 [m][12]
+ *   warm_start_idx_dev  device int64 [m] or NULL: a previous association used
+ *                       to seed the search bound (any valid index is allowed;
+ *                       results do not depend on it in the exact modes)
+ *   idx_out_dev         device int64 [m]: original index of the nearest point
+ *   dist_out_dev        device float64 [m] or NULL: the local distance
+ *                       1/2 d_e^2 of that point, evaluated in FP64
+ * m = 0 is a no-op.  A non-finite state yields idx -1 and dist NaN.
+ * Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED (mode needs a pack the dataset lacks),
+ * DD_ERR_OOM, DD_ERR_DEVICE.  Asynchronous on hip_stream unless opts->stats.
+ */
+dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
+                     const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                     int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream);
+
+/*
+ * Diagnostic: multiply small HOST matrices with one wavefront of the matrix
+ * instructions the scans use, with the operand/result lane layouts the scans
+ * assume (so a correct layout reproduces the plain product A B exactly for
+ * small-integer inputs).
+ *   kind 0: bf16 32x32x16 (A [32][16], B [16][32], D [32][32]), FP32 accumulate
+ *   kind 1: fp16 32x32x16 (same shapes)
+ *   kind 2: fp64 16x16x4  (A [16][4], B [4][16], D [16][16])
+ * Arrays are row-major float64 host memory; D is written.  Synchronous.
+ */
+dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D);
+
+/* Thread-local message for the calling thread's last non-OK status. */
+const char* dd_last_error(void);
+
+/* Library version string. */
+const char* dd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_H */

@@ -1,0 +1,196 @@
+"""ctypes binding of libdd.so: the C-ABI entry points under the same names.
+
+Only argument marshalling happens here (torch tensors -> device pointers and
+the current HIP stream).  Every step of the computation runs in the library's
+HIP kernels; if libdd.so is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+DD_OK = 0
+STATUS = {0: "DD_OK", 1: "DD_ERR_ARG", 2: "DD_ERR_NOT_SPD", 3: "DD_ERR_OOM", 4: "DD_ERR_DEVICE",
+          5: "DD_ERR_NOT_CONVERGED", 6: "DD_ERR_TOO_LARGE", 7: "DD_ERR_CANCELLED",
+          8: "DD_ERR_UNSUPPORTED", 9: "DD_ERR_TIMEOUT"}
+
+DD_EXACT_FP64, DD_MIXED_FP32, DD_MIXED_BF16, DD_ANN, DD_DIRECT_FP64, DD_MIXED_FP16 = range(6)
+MODES = {"fp64": DD_EXACT_FP64, "fp32": DD_MIXED_FP32, "bf16": DD_MIXED_BF16, "ann": DD_ANN,
+         "direct": DD_DIRECT_FP64, "fp16": DD_MIXED_FP16}
+
+DD_PACK_FP64, DD_PACK_FP32, DD_PACK_BF16, DD_PACK_FP16, DD_PACK_ANN = 0x1, 0x2, 0x4, 0x8, 0x10
+
+
+class DDError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {message}")
+
+
+class dd_dataset_opts(ctypes.Structure):
+    _fields_ = [("packs", ctypes.c_uint32), ("tile", ctypes.c_int32), ("ann_bits", ctypes.c_int32)]
+
+
+class dd_project_stats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("overflowed", ctypes.c_int64),
+                ("visited", ctypes.c_int64), ("scan_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+
+class dd_project_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("splits", ctypes.c_int32), ("ann_budget", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats))]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2012_00357_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.dd_dataset_create.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_dataset_opts), vp,
+                                      ctypes.POINTER(vp)]
+    lib.dd_dataset_destroy.argtypes = [vp]
+    lib.dd_dataset_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.dd_project.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_project_opts), vp, vp, vp]
+    lib.dd_selftest_mfma.argtypes = [i32, vp, vp, vp]
+    for f in ("dd_dataset_create", "dd_dataset_destroy", "dd_dataset_info", "dd_project",
+              "dd_selftest_mfma"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.dd_last_error.restype = ctypes.c_char_p
+    lib.dd_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def dd_last_error() -> str:
+    return _lib.dd_last_error().decode()
+
+
+def dd_version() -> str:
+    return _lib.dd_version().decode()
+
+
+def _check(status: int, where: str):
+    if status != DD_OK:
+        raise DDError(status, where, dd_last_error())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape_tail=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n]{list(shape_tail)}, got {list(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Dataset:
+    """Owning handle of a dd_dataset (released by dd_dataset_destroy)."""
+
+    def __init__(self, handle: int, n: int):
+        self._h = ctypes.c_void_p(handle)
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.dd_dataset_info(self._h, ctypes.byref(n), ctypes.byref(b)), "dd_dataset_info")
+        return n.value, b.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.dd_dataset_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dd_dataset_create(strain, stress, C, packs: int = 0, tile: int = 0, ann_bits: int = 0,
+                      stream=None) -> Dataset:
+    """dd_dataset_create: strain/stress are device float64 [N][6] tensors, C a 6x6 host array."""
+    import torch
+    n = int(strain.shape[0])
+    ps = _dev_ptr(strain, torch.float64, (6,), "strain")
+    pt = _dev_ptr(stress, torch.float64, (6,), "stress")
+    Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(36))
+    opts = dd_dataset_opts(packs, tile, ann_bits)
+    out = ctypes.c_void_p()
+    _check(_lib.dd_dataset_create(ps, pt, n, Cm.ctypes.data, ctypes.byref(opts), _stream(stream),
+                                  ctypes.byref(out)), "dd_dataset_create")
+    return Dataset(out.value, n)
+
+
+def dd_dataset_destroy(ds: Dataset):
+    ds.close()
+
+
+def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: int = 0,
+               ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False):
+    """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats])."""
+    import torch
+    m = int(states.shape[0])
+    ps = _dev_ptr(states, torch.float64, (12,), "states")
+    if idx_out is None:
+        idx_out = torch.empty(m, dtype=torch.int64, device=states.device)
+    if dist_out is None:
+        dist_out = torch.empty(m, dtype=torch.float64, device=states.device)
+    pi = _dev_ptr(idx_out, torch.int64, None, "idx_out")
+    pd = _dev_ptr(dist_out, torch.float64, None, "dist_out")
+    pw = None
+    if warm_start_idx is not None:
+        pw = _dev_ptr(warm_start_idx, torch.int64, None, "warm_start_idx")
+    st = dd_project_stats()
+    opts = dd_project_opts(MODES[mode] if isinstance(mode, str) else int(mode), splits, ann_budget,
+                           0, ctypes.pointer(st) if stats else None)
+    _check(_lib.dd_project(ds.handle, ps, m, pw, ctypes.byref(opts), pi, pd, _stream(stream)),
+           "dd_project")
+    if stats:
+        return idx_out, dist_out, {"candidates": st.candidates, "overflowed": st.overflowed,
+                                   "visited": st.visited, "scan_ms": st.scan_ms,
+                                   "total_ms": st.total_ms}
+    return idx_out, dist_out
+
+
+def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    shape = (16, 16) if kind == 2 else (32, 32)
+    D = np.zeros(shape, dtype=np.float64)
+    _check(_lib.dd_selftest_mfma(kind, A.ctypes.data, B.ctypes.data, D.ctypes.data),
+           "dd_selftest_mfma")
+    return D
+
+
+def dd_dataset_info(ds: Dataset):
+    """dd_dataset_info: (number of points, device bytes held)."""
+    return ds.info()

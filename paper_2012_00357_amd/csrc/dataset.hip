@@ -1,0 +1,458 @@
+// Dataset creation: whitening (Section 3.2), spatial order, FP64 / FP32 /
+// tile-centred 16-bit packs.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dd_internal.h"
+#include "pack16.h"
+#include "sort.h"
+
+namespace dd {
+
+struct Mat6x2 {
+  double F[36];
+  double G[36];
+};
+
+// w = (F eps, G sig) for every point; flags non-finite input.
+__global__ void whiten_kernel(const double* __restrict__ strain, const double* __restrict__ stress,
+                              int64_t n, Mat6x2 M, double* __restrict__ w,
+                              int* __restrict__ bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double e[6], s[6];
+  bool ok = true;
+  for (int k = 0; k < 6; ++k) {
+    e[k] = strain[6 * i + k];
+    s[k] = stress[6 * i + k];
+    ok = ok && isfinite(e[k]) && isfinite(s[k]);
+  }
+  if (!ok) atomicOr(bad, 1);
+  for (int r = 0; r < 6; ++r) {
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      a = fma(M.F[6 * r + c], e[c], a);
+      b = fma(M.G[6 * r + c], s[c], b);
+    }
+    w[12 * i + r] = a;
+    w[12 * i + 6 + r] = b;
+  }
+}
+
+__global__ void sample_kernel(const double* __restrict__ w, int64_t n, int64_t stride, int64_t ns,
+                              double* __restrict__ out) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  int64_t i = s * stride;
+  if (i >= n) i = n - 1;
+  for (int k = 0; k < 12; ++k) out[12 * s + k] = w[12 * i + k];
+}
+
+struct KeyParams {
+  double axes[kKeyAxes * kDim];
+  double mean[kDim];
+  double lo[kKeyAxes];
+  double scale[kKeyAxes];
+  int bits;
+};
+
+// Morton key of the point's cell in the principal-axis grid.
+__global__ void key_kernel(const double* __restrict__ w, int64_t n, KeyParams P,
+                           uint32_t* __restrict__ keys) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x[kDim];
+  for (int k = 0; k < kDim; ++k) x[k] = w[12 * i + k] - P.mean[k];
+  const int maxc = (1 << P.bits) - 1;
+  uint32_t key = 0;
+  int q[kKeyAxes];
+  for (int a = 0; a < kKeyAxes; ++a) {
+    double p = 0.0;
+    for (int k = 0; k < kDim; ++k) p = fma(P.axes[kDim * a + k], x[k], p);
+    double c = floor((p - P.lo[a]) * P.scale[a]);
+    q[a] = c < 0.0 ? 0 : (c > (double)maxc ? maxc : (int)c);
+  }
+  for (int b = 0; b < P.bits; ++b)
+    for (int a = 0; a < kKeyAxes; ++a) key |= (uint32_t)((q[a] >> b) & 1) << (b * kKeyAxes + a);
+  keys[i] = key;
+}
+
+__global__ void invert_perm_kernel(const uint32_t* __restrict__ perm, int64_t n,
+                                   uint32_t* __restrict__ iperm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) iperm[perm[i]] = (uint32_t)i;
+}
+
+// Sorted FP64 pack and squared norms; padding rows are zero with norm +inf.
+__global__ void gather64_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
+                                int64_t n, int64_t n_pad, double* __restrict__ w64,
+                                double* __restrict__ n64) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  if (i < n) {
+    const double* src = w + 12 * (int64_t)perm[i];
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      double v = src[k];
+      w64[12 * i + k] = v;
+      s = fma(v, v, s);
+    }
+    n64[i] = s;
+  } else {
+    for (int k = 0; k < 12; ++k) w64[12 * i + k] = 0.0;
+    n64[i] = INFINITY;
+  }
+}
+
+// Sorted FP32 pack (round to nearest) and the exact-in-FP64 squared norm of the
+// stored values rounded to FP32; padding rows are zero with norm +inf.
+__global__ void gather32_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
+                                int64_t n, int64_t n_pad, float* __restrict__ w32,
+                                float* __restrict__ n32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  if (i < n) {
+    const double* src = w + 12 * (int64_t)perm[i];
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      float v = (float)src[k];
+      w32[12 * i + k] = v;
+      s = fma((double)v, (double)v, s);
+    }
+    n32[i] = (float)s;
+  } else {
+    for (int k = 0; k < 12; ++k) w32[12 * i + k] = 0.0f;
+    n32[i] = INFINITY;
+  }
+}
+
+// max_i |x_i| over the rows (non-negative doubles order like their bit patterns).
+__global__ void max_norm_kernel(const double* __restrict__ w, int64_t n,
+                                unsigned long long* __restrict__ out) {
+  __shared__ double red[256];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) s = fma(w[12 * i + k], w[12 * i + k], s);
+    v = sqrt(s);
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// Per tile: centre = mean of its points (rounded to FP32), radius = max distance
+// of its points to that FP32 centre, rounded up.  One block of 256 per tile.
+__global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restrict__ w,
+                                                         const uint32_t* __restrict__ perm,
+                                                         int64_t n, int tile,
+                                                         float* __restrict__ centre,
+                                                         float* __restrict__ radius) {
+  __shared__ double red[256];
+  __shared__ float cen[12];
+  int64_t t = blockIdx.x;
+  int64_t first = t * tile;
+  int64_t last = min(first + (int64_t)tile, n);
+  int cnt = (int)(last - first);
+  for (int k = 0; k < 12; ++k) {
+    double s = 0.0;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) s += w[12 * (int64_t)perm[i] + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cen[k] = (float)(red[0] / (double)cnt);
+    __syncthreads();
+  }
+  double r = 0.0;
+  for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+    const double* x = w + 12 * (int64_t)perm[i];
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      double d = x[k] - (double)cen[k];
+      s = fma(d, d, s);
+    }
+    r = fmax(r, sqrt(s));
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 12; ++k) centre[12 * t + k] = cen[k];
+    // round up with a relative margin far above the rounding of the sums above
+    radius[t] = __double2float_ru(red[0] * (1.0 + 1e-12) + 1e-30);
+  }
+}
+
+// 16-bit tile-centred pack: row j of tile T holds
+//   (-2 x'_0 .. -2 x'_11, n_hi, n_mid, n_lo, 0),  x' = round16(x_j - c_T),
+//   n = |x'|^2 (exact in FP64) split into three 16-bit terms.
+// Padding rows: zeros with n_hi = kPadNorm (never a candidate).
+template <class T16>
+__global__ void pack16_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
+                              int64_t n, int64_t n_rows, int tile,
+                              const float* __restrict__ centre, uint16_t* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_rows) return;
+  uint16_t row[16];
+  if (i < n) {
+    const double* x = w + 12 * (int64_t)perm[i];
+    const float* c = centre + 12 * (i / tile);
+    double nn = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      float xf = (float)(x[k] - (double)c[k]);
+      uint16_t b = T16::from_float(xf);
+      double v = (double)T16::to_float(b);
+      nn = fma(v, v, nn);
+      row[k] = T16::from_float(-2.0f * T16::to_float(b));   // exact scaling by -2
+    }
+    uint16_t hi = T16::from_float((float)nn);
+    double r1 = nn - (double)T16::to_float(hi);
+    uint16_t mid = T16::from_float((float)r1);
+    double r2 = r1 - (double)T16::to_float(mid);
+    uint16_t lo = T16::from_float((float)r2);
+    row[12] = hi;
+    row[13] = mid;
+    row[14] = lo;
+    row[15] = 0;
+  } else {
+    for (int k = 0; k < 16; ++k) row[k] = 0;
+    row[12] = T16::from_float(kPadNorm);
+  }
+  uint4 a, b;
+  a.x = row[0] | ((uint32_t)row[1] << 16);
+  a.y = row[2] | ((uint32_t)row[3] << 16);
+  a.z = row[4] | ((uint32_t)row[5] << 16);
+  a.w = row[6] | ((uint32_t)row[7] << 16);
+  b.x = row[8] | ((uint32_t)row[9] << 16);
+  b.y = row[10] | ((uint32_t)row[11] << 16);
+  b.z = row[12] | ((uint32_t)row[13] << 16);
+  b.w = row[14] | ((uint32_t)row[15] << 16);
+  uint4* o = reinterpret_cast<uint4*>(out + 16 * i);
+  o[0] = a;
+  o[1] = b;
+}
+
+static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+static dd_status create_impl(const double* strain, const double* stress, int64_t N, const double* C,
+                             const dd_dataset_opts* opts, hipStream_t st, Dataset& D) {
+  uint32_t packs = (opts && opts->packs) ? opts->packs : DD_PACK_DEFAULT;
+  int tile = (opts && opts->tile) ? opts->tile : 256;
+  if (tile < 32 || tile > 4096 || tile % 32)
+    return set_error(DD_ERR_ARG, "tile must be a multiple of 32 in [32, 4096]");
+  if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN))
+    return set_error(DD_ERR_ARG, "unknown pack bits");
+  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP32;
+  // the FP64 rerank reads the FP64 pack, or the FP32 pack promoted exactly
+  if (!(packs & (DD_PACK_FP64 | DD_PACK_FP32))) packs |= DD_PACK_FP64;
+  D.N = N;
+  D.packs = packs;
+  D.tile = tile;
+  DD_HIP(hipGetDevice(&D.device));
+
+  // metric: symmetric positive definite, whitening factors from its Cholesky factor
+  double cnorm = 0.0, asym = 0.0;
+  for (int i = 0; i < 36; ++i) {
+    if (!std::isfinite(C[i])) return set_error(DD_ERR_ARG, "metric C has a non-finite entry");
+    cnorm = std::max(cnorm, std::fabs(C[i]));
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) asym = std::max(asym, std::fabs(C[6 * i + j] - C[6 * j + i]));
+  if (asym > 1e-12 * cnorm) return set_error(DD_ERR_NOT_SPD, "metric C is not symmetric");
+  double L[36], Li[36];
+  if (!cholesky6(C, L)) return set_error(DD_ERR_NOT_SPD, "metric C is not positive definite");
+  lower_inverse6(L, Li);
+  std::memcpy(D.C, C, sizeof(D.C));
+  Mat6x2 M;
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) {
+      M.F[6 * r + c] = L[6 * c + r];  // F = L^T
+      M.G[6 * r + c] = Li[6 * r + c]; // G = L^-1
+    }
+  std::memcpy(D.F, M.F, sizeof(D.F));
+  std::memcpy(D.G, M.G, sizeof(D.G));
+
+  // 1. whiten (original order)
+  DevBuf wraw, flag;
+  DD_TRY(wraw.alloc(sizeof(double) * 12 * (size_t)N));
+  DD_TRY(flag.alloc(sizeof(int)));
+  DD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(whiten_kernel, dim3(grid_for(N)), dim3(256), 0, st, strain, stress, N, M,
+                     wraw.as<double>(), flag.as<int>());
+  DD_HIP(hipGetLastError());
+  int bad = 0;
+  DD_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  if (bad) return set_error(DD_ERR_ARG, "data set contains non-finite strain or stress values");
+
+  // 2. principal axes of a strided sample (host, 12x12 eigenproblem)
+  int64_t ns = std::min<int64_t>(N, 65536);
+  int64_t stride = std::max<int64_t>(1, N / ns);
+  DevBuf dsamp;
+  DD_TRY(dsamp.alloc(sizeof(double) * 12 * (size_t)ns));
+  hipLaunchKernelGGL(sample_kernel, dim3(grid_for(ns)), dim3(256), 0, st, wraw.as<double>(), N,
+                     stride, ns, dsamp.as<double>());
+  std::vector<double> samp(12 * (size_t)ns);
+  DD_HIP(hipMemcpyAsync(samp.data(), dsamp.p, sizeof(double) * samp.size(), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  KeyParams P;
+  {
+    double mean[12] = {0};
+    for (int64_t s = 0; s < ns; ++s)
+      for (int k = 0; k < 12; ++k) mean[k] += samp[12 * s + k];
+    for (int k = 0; k < 12; ++k) mean[k] /= (double)ns;
+    double cov[144] = {0};
+    for (int64_t s = 0; s < ns; ++s)
+      for (int a = 0; a < 12; ++a)
+        for (int b = 0; b < 12; ++b)
+          cov[12 * a + b] += (samp[12 * s + a] - mean[a]) * (samp[12 * s + b] - mean[b]);
+    double ev[12], V[144];
+    sym_eigen(12, cov, ev, V);
+    for (int a = 0; a < kKeyAxes; ++a)
+      for (int k = 0; k < 12; ++k) P.axes[kDim * a + k] = V[12 * k + a];
+    for (int k = 0; k < 12; ++k) P.mean[k] = mean[k];
+    for (int a = 0; a < kKeyAxes; ++a) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int64_t s = 0; s < ns; ++s) {
+        double p = 0.0;
+        for (int k = 0; k < 12; ++k) p += P.axes[kDim * a + k] * (samp[12 * s + k] - mean[k]);
+        lo = std::min(lo, p);
+        hi = std::max(hi, p);
+      }
+      double span = std::max(hi - lo, 1e-300);
+      lo -= 0.01 * span;
+      hi += 0.01 * span;
+      P.lo[a] = lo;
+      P.scale[a] = 1.0 / (hi - lo);
+      D.lo[a] = lo;
+      D.hi[a] = hi;
+    }
+    std::memcpy(D.axes, P.axes, sizeof(D.axes));
+    std::memcpy(D.mean, P.mean, sizeof(D.mean));
+  }
+  // cell resolution: about 2^bits cells per axis, 6 axes -> 6*bits key bits
+  int bits = 5;
+  P.bits = bits;
+  for (int a = 0; a < kKeyAxes; ++a) P.scale[a] *= (double)(1 << bits);
+
+  // 3. keys, stable sort -> permutation
+  DevBuf keys;
+  DD_TRY(keys.alloc(sizeof(uint32_t) * (size_t)N));
+  DD_TRY(D.perm.alloc(sizeof(uint32_t) * (size_t)N));
+  hipLaunchKernelGGL(key_kernel, dim3(grid_for(N)), dim3(256), 0, st, wraw.as<double>(), N, P,
+                     keys.as<uint32_t>());
+  DD_HIP(hipGetLastError());
+  DD_TRY(iota_u32(D.perm.as<uint32_t>(), N, st));
+  DD_TRY(radix_sort_pairs(keys.as<uint32_t>(), D.perm.as<uint32_t>(), N, kKeyAxes * bits, st));
+  keys.release();
+  DD_TRY(D.iperm.alloc(sizeof(uint32_t) * (size_t)N));
+  hipLaunchKernelGGL(invert_perm_kernel, dim3(grid_for(N)), dim3(256), 0, st,
+                     D.perm.as<uint32_t>(), N, D.iperm.as<uint32_t>());
+  DD_HIP(hipGetLastError());
+
+  // 4. packs
+  {
+    DevBuf mx;
+    DD_TRY(mx.alloc(sizeof(unsigned long long)));
+    DD_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(max_norm_kernel, dim3(grid_for(N)), dim3(256), 0, st, wraw.as<double>(), N,
+                       mx.as<unsigned long long>());
+    unsigned long long bitsx = 0;
+    DD_HIP(hipMemcpyAsync(&bitsx, mx.p, sizeof(bitsx), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    double xm;
+    std::memcpy(&xm, &bitsx, sizeof(xm));
+    D.xmax = xm;
+  }
+  if (packs & DD_PACK_FP64) {
+    D.n_pad64 = (N + kTile64 - 1) / kTile64 * kTile64;
+    DD_TRY(D.w64.alloc(sizeof(double) * 12 * (size_t)D.n_pad64));
+    DD_TRY(D.n64.alloc(sizeof(double) * (size_t)D.n_pad64));
+    hipLaunchKernelGGL(gather64_kernel, dim3(grid_for(D.n_pad64)), dim3(256), 0, st,
+                       wraw.as<double>(), D.perm.as<uint32_t>(), N, D.n_pad64, D.w64.as<double>(),
+                       D.n64.as<double>());
+    DD_HIP(hipGetLastError());
+  }
+  if (packs & DD_PACK_FP32) {
+    D.n_pad32 = (N + kTile32 - 1) / kTile32 * kTile32;
+    DD_TRY(D.w32.alloc(sizeof(float) * 12 * (size_t)D.n_pad32));
+    DD_TRY(D.n32.alloc(sizeof(float) * (size_t)D.n_pad32));
+    hipLaunchKernelGGL(gather32_kernel, dim3(grid_for(D.n_pad32)), dim3(256), 0, st,
+                       wraw.as<double>(), D.perm.as<uint32_t>(), N, D.n_pad32, D.w32.as<float>(),
+                       D.n32.as<float>());
+    DD_HIP(hipGetLastError());
+    D.xmax32 = D.xmax * (1.0 + 1e-6);
+  }
+  if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) {
+    D.n_tiles = (N + tile - 1) / tile;
+    int64_t rows = D.n_tiles * tile;
+    DD_TRY(D.centre.alloc(sizeof(float) * 12 * (size_t)D.n_tiles));
+    DD_TRY(D.radius.alloc(sizeof(float) * (size_t)D.n_tiles));
+    hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)D.n_tiles), dim3(256), 0, st,
+                       wraw.as<double>(), D.perm.as<uint32_t>(), N, tile, D.centre.as<float>(),
+                       D.radius.as<float>());
+    DD_HIP(hipGetLastError());
+    if (packs & DD_PACK_BF16) {
+      DD_TRY(D.wbf16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
+      hipLaunchKernelGGL(pack16_kernel<Bf16>, dim3(grid_for(rows)), dim3(256), 0, st,
+                         wraw.as<double>(), D.perm.as<uint32_t>(), N, rows, tile,
+                         D.centre.as<float>(), D.wbf16.as<uint16_t>());
+      DD_HIP(hipGetLastError());
+    }
+    if (packs & DD_PACK_FP16) {
+      DD_TRY(D.wfp16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
+      hipLaunchKernelGGL(pack16_kernel<Fp16>, dim3(grid_for(rows)), dim3(256), 0, st,
+                         wraw.as<double>(), D.perm.as<uint32_t>(), N, rows, tile,
+                         D.centre.as<float>(), D.wfp16.as<uint16_t>());
+      DD_HIP(hipGetLastError());
+    }
+  }
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+}  // namespace dd
+
+extern "C" dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev,
+                                       int64_t N, const double* C, const dd_dataset_opts* opts,
+                                       void* hip_stream, dd_dataset** out) {
+  if (!out) return dd::set_error(DD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!strain_dev || !stress_dev || !C) return dd::set_error(DD_ERR_ARG, "NULL input pointer");
+  if (N < 1 || N > 0x7FFFFFFFll) return dd::set_error(DD_ERR_ARG, "N must be in [1, 2^31-1]");
+  dd_dataset* ds = new (std::nothrow) dd_dataset();
+  if (!ds) return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  dd_status st = dd::create_impl(strain_dev, stress_dev, N, C, opts,
+                                 static_cast<hipStream_t>(hip_stream), ds->d);
+  if (st != DD_OK) {
+    delete ds;
+    return st;
+  }
+  *out = ds;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_dataset_destroy(dd_dataset* ds) {
+  delete ds;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_dataset_info(const dd_dataset* ds, int64_t* n_points, int64_t* device_bytes) {
+  if (!ds) return dd::set_error(DD_ERR_ARG, "dataset is NULL");
+  if (n_points) *n_points = ds->d.N;
+  if (device_bytes) *device_bytes = ds->d.device_bytes();
+  return DD_OK;
+}

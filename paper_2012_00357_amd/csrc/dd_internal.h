@@ -1,0 +1,103 @@
+// Internal declarations shared by the libdd translation units (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dd.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Error handling
+// ---------------------------------------------------------------------------
+dd_status set_error(dd_status st, const std::string& msg);
+
+#define DD_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::dd::set_error(e_ == hipErrorOutOfMemory ? DD_ERR_OOM : DD_ERR_DEVICE,      \
+                             std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define DD_TRY(expr)                  \
+  do {                                \
+    dd_status s_ = (expr);            \
+    if (s_ != DD_OK) return s_;       \
+  } while (0)
+
+// Device buffer owned by a host object; released in the destructor.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  dd_status alloc(size_t n);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Small dense linear algebra on the host (6x6 / 12x12)
+// ---------------------------------------------------------------------------
+// Cholesky C = L L^T (row-major, lower); returns false if not SPD.
+bool cholesky6(const double* C, double* L);
+// Inverse of a lower-triangular 6x6 matrix (row-major).
+void lower_inverse6(const double* L, double* Linv);
+// Symmetric eigen-decomposition (cyclic Jacobi); eigenvalues descending,
+// eigenvectors as columns of V (row-major n x n).
+void sym_eigen(int n, const double* A, double* evals, double* V);
+
+// ---------------------------------------------------------------------------
+// Dataset
+// ---------------------------------------------------------------------------
+constexpr int kDim = 12;           // phase-space dimension 2M (M = 6 Voigt components)
+constexpr int kKeyAxes = 6;        // principal axes used for the spatial order
+
+struct Dataset {
+  int device = 0;
+  int64_t N = 0;
+  uint32_t packs = 0;
+  double C[36];
+  double F[36];    // strain whitening F = L^T  (F^T F = C)
+  double G[36];    // stress whitening G = L^-1 (G^T G = C^-1)
+  // spatial order
+  DevBuf perm;     // uint32 [N]: sorted position -> original index
+  DevBuf iperm;    // uint32 [N]: original index -> sorted position
+  // FP64 pack (sorted order), padded to n_pad64 rows
+  int64_t n_pad64 = 0;
+  DevBuf w64;      // double [n_pad64][12]
+  DevBuf n64;      // double [n_pad64]  |x|^2 (padding rows: +inf)
+  double xmax = 0; // max_j |x_j|
+  // FP32 pack
+  int64_t n_pad32 = 0;
+  DevBuf w32;      // float [n_pad32][12]
+  DevBuf n32;      // float [n_pad32] |x|^2 of the FP32 values (padding: +inf)
+  double xmax32 = 0;
+  // 16-bit packs (tile-centred)
+  int tile = 256;
+  int64_t n_tiles = 0;
+  DevBuf centre;   // float [n_tiles][12]
+  DevBuf radius;   // float [n_tiles]  upper bound of |x_j - c_T| over the tile
+  DevBuf wbf16;    // uint16 [n_tiles*tile][16]
+  DevBuf wfp16;    // uint16 [n_tiles*tile][16]
+  // ANN cell index (over the FP32 pack)
+  DevBuf cell_start;     // uint32 [n_cells+1]
+  int ann_bits = 0;
+  double axes[kKeyAxes * kDim];  // principal axes (rows)
+  double mean[kDim];
+  double lo[kKeyAxes], hi[kKeyAxes];
+
+  int64_t device_bytes() const;
+};
+
+}  // namespace dd
+
+struct dd_dataset {
+  dd::Dataset d;
+};

@@ -1,0 +1,195 @@
+// dd_project: dispatch of the projection P_D (Section 2) to the scan kernels.
+#include <algorithm>
+#include <vector>
+
+#include "pack16.h"
+#include "scan.h"
+
+namespace dd {
+
+namespace {
+
+// Stream-ordered device scratch released when the call ends.
+struct Scratch {
+  hipStream_t st;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t s) : st(s) {}
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+  }
+  template <class T>
+  dd_status get(T*& out, size_t n) {
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, std::max<size_t>(n, 1) * sizeof(T), st);
+    if (e != hipSuccess)
+      return set_error(e == hipErrorOutOfMemory ? DD_ERR_OOM : DD_ERR_DEVICE,
+                       std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    ptrs.push_back(p);
+    out = static_cast<T*>(p);
+    return DD_OK;
+  }
+};
+
+dd_status alloc_cands(Scratch& sc, int64_t positions, int S, int P, int K, CandBuf& cb) {
+  cb.S = S;
+  cb.P = P;
+  cb.K = K;
+  size_t slots = (size_t)positions * S * P;
+  DD_TRY(sc.get(cb.lb, slots * K));
+  DD_TRY(sc.get(cb.j, slots * K));
+  DD_TRY(sc.get(cb.count, slots));
+  DD_TRY(sc.get(cb.U, (size_t)positions * S));
+  return DD_OK;
+}
+
+// Optional HIP events bracketing the main scan and the whole call.
+struct Timing {
+  bool on = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  dd_status init(hipStream_t st) {
+    on = true;
+    for (auto& e : ev) DD_HIP(hipEventCreate(&e));
+    DD_HIP(hipEventRecord(ev[0], st));
+    return DD_OK;
+  }
+  dd_status mark(int k, hipStream_t st) {
+    if (on) DD_HIP(hipEventRecord(ev[k], st));
+    return DD_OK;
+  }
+  ~Timing() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+struct Counters {
+  int fb1;
+  int fb2;
+  unsigned long long cand;
+};
+
+// FP64 MFMA scan over list L, merge, and the direct fallback for its overflow.
+dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max, int splits,
+                  Outputs out, Scratch& sc, int* d_counters, hipStream_t st, int64_t* n_fallback,
+                  Timing* tm) {
+  int64_t qblocks = (len_max + 255) / 256;
+  int S = choose_splits(qblocks, D.n_pad64 / kTile64, splits);
+  CandBuf cb;
+  DD_TRY(alloc_cands(sc, len_max, S, 4, 16, cb));
+  if (tm) DD_TRY(tm->mark(1, st));
+  DD_TRY(launch_scan64(D, Q, L, len_max, cb, st));
+  if (tm) DD_TRY(tm->mark(2, st));
+  int* fb = nullptr;
+  DD_TRY(sc.get(fb, (size_t)len_max));
+  int* fb_count = d_counters + 1;
+  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, false, out, fb, fb_count,
+                             reinterpret_cast<unsigned long long*>(d_counters + 2), st));
+  int h = 0;
+  DD_HIP(hipMemcpyAsync(&h, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  if (n_fallback) *n_fallback += h;
+  if (h > 0) {
+    QueryList L2{fb, fb_count, h};
+    DD_TRY(run_direct(D, Q, L2, h, 0, out, st));
+  }
+  return DD_OK;
+}
+
+}  // namespace
+
+}  // namespace dd
+
+extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
+                                const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                                int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream) {
+  using namespace dd;
+  if (!ds) return set_error(DD_ERR_ARG, "dataset is NULL");
+  if (m < 0 || m > 0x7FFFFFFFll) return set_error(DD_ERR_ARG, "m must be in [0, 2^31-1]");
+  if (m == 0) return DD_OK;
+  if (!states_dev || !idx_out_dev) return set_error(DD_ERR_ARG, "NULL states or idx_out");
+  const Dataset& D = ds->d;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int mode = opts ? opts->mode : DD_EXACT_FP64;
+  const int splits = opts ? opts->splits : 0;
+  if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
+  switch (mode) {
+    case DD_EXACT_FP64:
+    case DD_DIRECT_FP64:
+      if (!(D.packs & DD_PACK_FP64)) return set_error(DD_ERR_UNSUPPORTED, "dataset has no FP64 pack");
+      break;
+    case DD_MIXED_BF16:
+      if (!(D.packs & DD_PACK_BF16) || !(D.packs & DD_PACK_FP64))
+        return set_error(DD_ERR_UNSUPPORTED, "BF16 mode needs the BF16 and FP64 packs");
+      break;
+    case DD_MIXED_FP16:
+      if (!(D.packs & DD_PACK_FP16) || !(D.packs & DD_PACK_FP64))
+        return set_error(DD_ERR_UNSUPPORTED, "FP16 mode needs the FP16 and FP64 packs");
+      break;
+    default:
+      return set_error(DD_ERR_UNSUPPORTED, "projection mode not available");
+  }
+  int cur_dev = -1;
+  DD_HIP(hipGetDevice(&cur_dev));
+  if (cur_dev != D.device) return set_error(DD_ERR_ARG, "dataset lives on another device");
+
+  Scratch sc(st);
+  Timing timing;
+  if (opts && opts->stats) DD_TRY(timing.init(st));
+  QueryPrep Q;
+  DD_TRY(sc.get(Q.qw, (size_t)m * 12));
+  DD_TRY(sc.get(Q.qn2, (size_t)m));
+  DD_TRY(sc.get(Q.u64, (size_t)m));
+  DD_TRY(sc.get(Q.u32, (size_t)m));
+  DD_TRY(sc.get(Q.invalid, (size_t)m));
+  int* counters = nullptr;   // [0] fb1, [1] fb2, [2..3] candidate count (u64)
+  DD_TRY(sc.get(counters, 4));
+  DD_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), st));
+  DD_TRY(prepare_queries(D, states_dev, m, warm_start_idx_dev, Q, st));
+  Outputs out{idx_out_dev, dist_out_dev};
+  QueryList all{nullptr, nullptr, m};
+  int64_t n_fallback = 0;
+
+  if (mode == DD_DIRECT_FP64) {
+    DD_TRY(timing.mark(1, st));
+    DD_TRY(run_direct(D, Q, all, m, splits, out, st));
+    DD_TRY(timing.mark(2, st));
+  } else if (mode == DD_EXACT_FP64) {
+    DD_TRY(exact64(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));
+  } else {
+    const bool fp16 = (mode == DD_MIXED_FP16);
+    int64_t qblocks = (m + 255) / 256;
+    int S = choose_splits(qblocks, D.n_tiles, splits);
+    CandBuf cb;
+    DD_TRY(alloc_cands(sc, m, S, 2, 32, cb));
+    DD_TRY(timing.mark(1, st));
+    DD_TRY(launch_scan16(D, fp16, Q, all, m, cb, st));
+    DD_TRY(timing.mark(2, st));
+    int* fb = nullptr;
+    DD_TRY(sc.get(fb, (size_t)m));
+    DD_TRY(launch_merge_rerank(D, Q, all, m, cb, true, out, fb, counters,
+                               reinterpret_cast<unsigned long long*>(counters + 2), st));
+    int h = 0;
+    DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    n_fallback += h;
+    if (h > 0) {
+      QueryList L1{fb, counters, h};
+      DD_TRY(exact64(D, Q, L1, h, 0, out, sc, counters, st, nullptr, nullptr));
+    }
+  }
+  if (opts && opts->stats) {
+    unsigned long long nc = 0;
+    DD_HIP(hipMemcpyAsync(&nc, counters + 2, sizeof(nc), hipMemcpyDeviceToHost, st));
+    DD_TRY(timing.mark(3, st));
+    DD_HIP(hipStreamSynchronize(st));
+    float scan_ms = 0.0f, total_ms = 0.0f;
+    DD_HIP(hipEventElapsedTime(&scan_ms, timing.ev[1], timing.ev[2]));
+    DD_HIP(hipEventElapsedTime(&total_ms, timing.ev[0], timing.ev[3]));
+    opts->stats->candidates = (int64_t)nc;
+    opts->stats->overflowed = n_fallback;
+    opts->stats->visited = 0;
+    opts->stats->scan_ms = scan_ms;
+    opts->stats->total_ms = total_ms;
+  }
+  return DD_OK;
+}

@@ -1,0 +1,150 @@
+"""GPU parity of dd_project against the CPU oracle (through the C ABI)."""
+import sys
+
+import numpy as np
+import pytest
+
+import ddsynth
+import oracle
+from gpu_util import compare_to_oracle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["direct", "fp64", "bf16", "fp16"]
+ALL_PACKS = 0x1 | 0x4 | 0x8
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2012_00357_amd import _lib
+    return _lib
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_mfma_lane_layouts(L, kind):
+    """The matrix-instruction lane layouts the scans assume reproduce A B."""
+    _say("selftest kind", kind)
+    rng = np.random.default_rng(kind)
+    if kind == 2:
+        A = rng.integers(-8, 9, (16, 4)).astype(float)
+        B = rng.integers(-8, 9, (4, 16)).astype(float)
+    else:
+        A = rng.integers(-8, 9, (32, 16)).astype(float)
+        B = rng.integers(-8, 9, (16, 32)).astype(float)
+    D = L.dd_selftest_mfma(kind, A, B)
+    np.testing.assert_array_equal(D, A @ B)
+
+
+@pytest.fixture(scope="module")
+def config0(L, C0):
+    """N = 65536 data points, m = 4096 queries (the exact-projection workload)."""
+    e, s = ddsynth.data_points(65536, 1000)
+    qe, qs, _ = ddsynth.queries(e, s, 4096, 2000)
+    oi, od, o2 = oracle.pd_raw(e, s, C0, qe, qs)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=ALL_PACKS)
+    states = to_dev(ddsynth.states(qe, qs))
+    return dict(e=e, s=s, qe=qe, qs=qs, oi=oi, od=od, o2=o2, ds=ds, states=states)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config0_parity(L, config0, mode):
+    _say("config0 mode", mode)
+    idx, dist, st = L.dd_project(config0["ds"], config0["states"], mode=mode, stats=True)
+    ties = compare_to_oracle(idx.cpu().numpy(), dist.cpu().numpy(), config0["oi"], config0["od"],
+                             config0["o2"])
+    _say(f"  mode {mode}: near ties {ties}, stats {st}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_warm_start_and_determinism(L, config0, mode):
+    import torch
+    _say("warm/determinism mode", mode)
+    ds, states = config0["ds"], config0["states"]
+    i1, d1 = L.dd_project(ds, states, mode=mode)
+    i2, d2 = L.dd_project(ds, states, mode=mode)
+    assert torch.equal(i1, i2) and torch.equal(d1, d2)
+    rng = np.random.default_rng(4)
+    warm = to_dev(rng.integers(0, 65536, 4096).astype(np.int64))
+    i3, d3 = L.dd_project(ds, states, warm_start_idx=warm, mode=mode)
+    assert torch.equal(i1, i3) and torch.equal(d1, d3)
+    i4, d4 = L.dd_project(ds, states, warm_start_idx=i1.clone(), mode=mode)
+    assert torch.equal(i1, i4) and torch.equal(d1, d4)
+
+
+@pytest.mark.parametrize("n,m,tile", [(1, 5, 256), (31, 7, 256), (1000, 77, 128), (5003, 300, 512),
+                                      (20000, 1000, 1024)])
+@pytest.mark.parametrize("mode", MODES)
+def test_ragged_sizes(L, C0, n, m, tile, mode):
+    _say("ragged", n, m, tile, mode)
+    e, s = ddsynth.data_points(n, 3000 + n)
+    qe, qs, _ = ddsynth.queries(e, s, m, 4000 + n)
+    oi, od, o2 = oracle.pd_raw(e, s, C0, qe, qs)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=ALL_PACKS, tile=tile)
+    idx, dist = L.dd_project(ds, to_dev(ddsynth.states(qe, qs)), mode=mode)
+    compare_to_oracle(idx.cpu().numpy(), dist.cpu().numpy(), oi, od, o2)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_queries_on_data_points_and_duplicates(L, C0, mode):
+    """A query equal to a data point is at distance 0; among duplicates (more of
+    them than any candidate list holds) the lowest index wins."""
+    _say("duplicates", mode)
+    n = 6000
+    e, s = ddsynth.data_points(n, 77)
+    dup_of = 1234
+    dup_at = np.arange(2000, 2000 + 70)            # 70 copies of point 1234, all above it
+    e[dup_at], s[dup_at] = e[dup_of], s[dup_of]
+    e[10], s[10] = e[5000], s[5000]                # one copy of 5000 below it
+    picks = np.array([dup_of, 2005, 5000, 10, 0, n - 1, 3333])
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=ALL_PACKS)
+    states = to_dev(ddsynth.states(e[picks], s[picks]))
+    idx, dist = L.dd_project(ds, states, mode=mode)
+    assert idx.cpu().tolist() == [dup_of, dup_of, 10, 10, 0, n - 1, 3333]
+    assert np.all(dist.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_invalid_states_and_empty(L, config0, mode):
+    import torch
+    states = config0["states"][:9].clone()
+    states[3, 4] = float("nan")
+    states[7, 11] = float("inf")
+    idx, dist = L.dd_project(config0["ds"], states, mode=mode)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert idx[3] == -1 and idx[7] == -1 and np.isnan(dist[3]) and np.isnan(dist[7])
+    ok = [0, 1, 2, 4, 5, 6, 8]
+    assert np.array_equal(idx[ok], config0["oi"][ok])
+    empty = torch.empty((0, 12), dtype=torch.float64, device="cuda")
+    i0, d0 = L.dd_project(config0["ds"], empty, mode=mode)
+    assert i0.numel() == 0
+
+
+def test_error_paths(L, C0):
+    import torch
+    e, s = ddsynth.data_points(100, 5)
+    bad_C = C0.copy()
+    bad_C[0, 0] = -1.0
+    with pytest.raises(L.DDError) as ex:
+        L.dd_dataset_create(to_dev(e), to_dev(s), bad_C)
+    assert ex.value.status == 2
+    asym = C0.copy()
+    asym[0, 1] += 1.0
+    with pytest.raises(L.DDError) as ex:
+        L.dd_dataset_create(to_dev(e), to_dev(s), asym)
+    assert ex.value.status == 2
+    e2 = e.copy()
+    e2[50, 2] = np.nan
+    with pytest.raises(L.DDError) as ex:
+        L.dd_dataset_create(to_dev(e2), to_dev(s), C0)
+    assert ex.value.status == 1
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1)
+    with pytest.raises(L.DDError) as ex:
+        L.dd_project(ds, torch.zeros((3, 12), dtype=torch.float64, device="cuda"), mode="bf16")
+    assert ex.value.status == 8
