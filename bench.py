@@ -43,6 +43,10 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=48)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--passes", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -68,25 +72,34 @@ def main():
     packs = 0x1 | (0x8 if args.mode == "fp16" else 0x4)
     torch.cuda.synchronize()
     t = time.time()
-    ds = L.dd_dataset_create(de, dsg, C, packs=packs)
+    ds = L.dd_dataset_create(de, dsg, C, packs=packs, tile=args.tile)
     torch.cuda.synchronize()
     build_s = time.time() - t
     del de, dsg
     torch.cuda.empty_cache()
     log(f"dataset built in {build_s:.2f}s, {ds.info()[1] / 1e9:.2f} GB on device")
 
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
+        del a, b
     idx = torch.empty(m, dtype=torch.int64, device="cuda")
     dist = torch.empty(m, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
-        L.dd_project(ds, states, mode=args.mode, idx_out=idx, dist_out=dist)
+        L.dd_project(ds, states, mode=args.mode, idx_out=idx, dist_out=dist, passes=args.passes)
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    scan_ms, cand, ovf = [], 0, 0
+    scan_ms, cand, ovf, slow = [], 0, 0, 0
     torch.cuda.synchronize()
     start.record()
     for _ in range(args.steps):
-        _, _, st = L.dd_project(ds, states, mode=args.mode, idx_out=idx, dist_out=dist, stats=True)
+        _, _, st = L.dd_project(ds, states, mode=args.mode, idx_out=idx, dist_out=dist, stats=True,
+                                passes=args.passes)
         scan_ms.append(st["scan_ms"])
+        slow += st["slow_tiles"]
         cand += st["candidates"]
         ovf += st["overflowed"]
     end.record()
@@ -97,13 +110,14 @@ def main():
     idx_mixed = idx.cpu().numpy().copy()
     dist_mixed = dist.cpu().numpy().copy()
     log(f"{args.mode}: {ms:.2f} ms/step, scan {scan_avg:.2f} ms, {value:.4g} proj/s, "
-        f"cand/query {cand / (m * args.steps):.2f}, fallback/step {ovf / args.steps:.1f}")
+        f"cand/query {cand / (m * args.steps):.2f}, fallback/step {ovf / args.steps:.1f}, "
+        f"slow tiles/step {slow / args.steps:.0f}")
 
     peak = FP64_PEAK_TFLOPS if args.mode == "fp64" else BF16_PEAK_TFLOPS
     achieved = FLOPS_PER_PAIR * N * m / (scan_avg / 1e3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "scan16_kernel<Bf16,256>" if args.mode == "bf16" else args.mode,
+                "kernel": f"scan16_pass_kernel<{args.mode}, {args.tile}, mark>",
                 "flops_per_pair": FLOPS_PER_PAIR,
                 "issued_frac": round(achieved * 32.0 / FLOPS_PER_PAIR / peak, 4)}
 
@@ -152,7 +166,8 @@ def main():
                                f"m={m} queries, {args.mode.upper()} MFMA scan + FP64 rerank",
                    "N": N, "m": m, "mode": args.mode, "dataset_build_s": round(build_s, 3),
                    "candidates_per_query": round(cand / (m * args.steps), 3),
-                   "fallback_queries_per_step": ovf / args.steps},
+                   "fallback_queries_per_step": ovf / args.steps,
+                   "slow_tiles_per_step": slow / args.steps, "tile": args.tile},
         "roofline": roofline,
         "fp64_scan": fp64,
         "cpu_baseline": cpu,

@@ -93,7 +93,7 @@ typedef struct dd_dataset dd_dataset;
 
 typedef struct dd_dataset_opts {
   uint32_t packs;      /* DD_PACK_* mask; 0 = DD_PACK_DEFAULT */
-  int32_t tile;        /* points per centring tile of the 16-bit packs; 0 = 256 (multiple of 32) */
+  int32_t tile;        /* points per centring tile of the 16-bit packs: 128, 256, 512 or 1024; 0 = 1024 */
   int32_t ann_bits;    /* cell grid bits per principal axis for DD_PACK_ANN; 0 = default */
 } dd_dataset_opts;
 
@@ -104,13 +104,15 @@ typedef struct dd_project_stats {
   int64_t visited;          /* data points visited (DD_ANN) */
   double scan_ms;           /* device time of the main scan kernel (HIP events on the call's stream) */
   double total_ms;          /* device time from the first to the last kernel of the call */
+  int64_t slow_tiles;       /* 16-bit scans: (32-query group, tile) items recomputed for candidates */
 } dd_project_stats;
 
 typedef struct dd_project_opts {
   int32_t mode;             /* dd_mode; default DD_EXACT_FP64 */
   int32_t splits;           /* data splits per query block; 0 = automatic */
   int32_t ann_budget;       /* DD_ANN: max cells visited per query (0 = unlimited, exact) */
-  int32_t reserved;
+  int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
+                               every 16th tile first; 0 = automatic (2 without a warm start) */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
 } dd_project_opts;
 
@@ -163,6 +165,9 @@ dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
  *   kind 0: bf16 32x32x16 (A [32][16], B [16][32], D [32][32]), FP32 accumulate
  *   kind 1: fp16 32x32x16 (same shapes)
  *   kind 2: fp64 16x16x4  (A [16][4], B [4][16], D [16][16])
+ *   kind 3: round A[512] (taken as FP32) to bf16 with the packed conversion of
+ *           the query operands and widen back into D[512] (B unused)
+ *   kind 4: the same for IEEE half
  * Arrays are row-major float64 host memory; D is written.  Synchronous.
  */
 dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D);

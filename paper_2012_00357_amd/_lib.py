@@ -39,12 +39,12 @@ class dd_dataset_opts(ctypes.Structure):
 class dd_project_stats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("overflowed", ctypes.c_int64),
                 ("visited", ctypes.c_int64), ("scan_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("slow_tiles", ctypes.c_int64)]
 
 
 class dd_project_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("splits", ctypes.c_int32), ("ann_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats))]
+                ("passes", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats))]
 
 
 def _load():
@@ -155,7 +155,8 @@ def dd_dataset_destroy(ds: Dataset):
 
 
 def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: int = 0,
-               ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False):
+               ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False,
+               passes: int = 0):
     """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats])."""
     import torch
     m = int(states.shape[0])
@@ -171,20 +172,20 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
         pw = _dev_ptr(warm_start_idx, torch.int64, None, "warm_start_idx")
     st = dd_project_stats()
     opts = dd_project_opts(MODES[mode] if isinstance(mode, str) else int(mode), splits, ann_budget,
-                           0, ctypes.pointer(st) if stats else None)
+                           passes, ctypes.pointer(st) if stats else None)
     _check(_lib.dd_project(ds.handle, ps, m, pw, ctypes.byref(opts), pi, pd, _stream(stream)),
            "dd_project")
     if stats:
         return idx_out, dist_out, {"candidates": st.candidates, "overflowed": st.overflowed,
                                    "visited": st.visited, "scan_ms": st.scan_ms,
-                                   "total_ms": st.total_ms}
+                                   "total_ms": st.total_ms, "slow_tiles": st.slow_tiles}
     return idx_out, dist_out
 
 
 def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
     A = np.ascontiguousarray(A, dtype=np.float64)
-    B = np.ascontiguousarray(B, dtype=np.float64)
-    shape = (16, 16) if kind == 2 else (32, 32)
+    B = np.ascontiguousarray(np.zeros(1) if B is None else B, dtype=np.float64)
+    shape = (16, 16) if kind == 2 else ((512,) if kind >= 3 else (32, 32))
     D = np.zeros(shape, dtype=np.float64)
     _check(_lib.dd_selftest_mfma(kind, A.ctypes.data, B.ctypes.data, D.ctypes.data),
            "dd_selftest_mfma")

@@ -34,9 +34,16 @@ def _hipcc() -> str:
     return "hipcc"
 
 
+# Matrix-core scan kernels: inputs are finite, so IEEE mode and NaN semantics
+# are off (min reductions need no canonicalisation) and MFMA results stay in
+# ordinary VGPRs instead of round-tripping through AGPRs.
+MFMA_FLAGS = ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", src, "-o", obj]
+    extra = MFMA_FLAGS if src.endswith("_mfma.hip") else []
+    cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

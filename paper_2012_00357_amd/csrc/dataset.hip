@@ -250,9 +250,9 @@ static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 
 static dd_status create_impl(const double* strain, const double* stress, int64_t N, const double* C,
                              const dd_dataset_opts* opts, hipStream_t st, Dataset& D) {
   uint32_t packs = (opts && opts->packs) ? opts->packs : DD_PACK_DEFAULT;
-  int tile = (opts && opts->tile) ? opts->tile : 256;
-  if (tile < 32 || tile > 4096 || tile % 32)
-    return set_error(DD_ERR_ARG, "tile must be a multiple of 32 in [32, 4096]");
+  int tile = (opts && opts->tile) ? opts->tile : 1024;
+  if (tile != 128 && tile != 256 && tile != 512 && tile != 1024)
+    return set_error(DD_ERR_ARG, "tile must be 128, 256, 512 or 1024");
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN))
     return set_error(DD_ERR_ARG, "unknown pack bits");
   if (packs & DD_PACK_ANN) packs |= DD_PACK_FP32;

@@ -82,7 +82,7 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
   int* fb = nullptr;
   DD_TRY(sc.get(fb, (size_t)len_max));
   int* fb_count = d_counters + 1;
-  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, false, out, fb, fb_count,
+  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, nullptr, out, fb, fb_count,
                              reinterpret_cast<unsigned long long*>(d_counters + 2), st));
   int h = 0;
   DD_HIP(hipMemcpyAsync(&h, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -141,13 +141,14 @@ extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, 
   DD_TRY(sc.get(Q.u64, (size_t)m));
   DD_TRY(sc.get(Q.u32, (size_t)m));
   DD_TRY(sc.get(Q.invalid, (size_t)m));
-  int* counters = nullptr;   // [0] fb1, [1] fb2, [2..3] candidate count (u64)
-  DD_TRY(sc.get(counters, 4));
-  DD_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(int), st));
+  int* counters = nullptr;   // [0] fb1, [1] fb2, [2..3] candidates (u64), [4..5] slow tiles (u64)
+  DD_TRY(sc.get(counters, 6));
+  DD_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int), st));
   DD_TRY(prepare_queries(D, states_dev, m, warm_start_idx_dev, Q, st));
   Outputs out{idx_out_dev, dist_out_dev};
   QueryList all{nullptr, nullptr, m};
   int64_t n_fallback = 0;
+  int64_t n_items_host = 0;
 
   if (mode == DD_DIRECT_FP64) {
     DD_TRY(timing.mark(1, st));
@@ -158,15 +159,60 @@ extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, 
   } else {
     const bool fp16 = (mode == DD_MIXED_FP16);
     int64_t qblocks = (m + 255) / 256;
-    int S = choose_splits(qblocks, D.n_tiles, splits);
+    const int S = choose_splits(qblocks, D.n_tiles, splits);
+    Scan16Call c;
+    c.Q = &Q;
+    c.L = all;
+    c.list_len_max = m;
+    c.S = S;
+    DD_TRY(sc.get(c.U_out, (size_t)m * S));
+    unsigned* n_items = reinterpret_cast<unsigned*>(counters + 4);
+    c.n_items = n_items;
+    c.item_cap = (unsigned)std::min<int64_t>(std::max<int64_t>(32 * m, 1 << 20), 1 << 26);
+    DD_TRY(sc.get(c.items, c.item_cap));
     CandBuf cb;
-    DD_TRY(alloc_cands(sc, m, S, 2, 32, cb));
+    cb.S = 1;
+    cb.P = 2;
+    cb.K = 32;
+    DD_TRY(sc.get(cb.lb, (size_t)m * 2 * cb.K));
+    DD_TRY(sc.get(cb.j, (size_t)m * 2 * cb.K));
+    DD_TRY(sc.get(cb.count, (size_t)m * 2));
+    DD_HIP(hipMemsetAsync(cb.count, 0, sizeof(int) * (size_t)m * 2, st));
+    c.cb = cb;
+    // Without a warm start the bound starts at +inf; a streaming pass over every
+    // 16th tile seeds it, so the marking pass logs few stale work items.
+    const int passes = (opts && opts->passes) ? opts->passes : (warm_start_idx_dev ? 1 : 2);
     DD_TRY(timing.mark(1, st));
-    DD_TRY(launch_scan16(D, fp16, Q, all, m, cb, st));
+    if (passes >= 2) {
+      c.phase = Scan16Call::kBound;
+      c.stride = 16;
+      DD_TRY(launch_scan16(D, fp16, c, st));
+      DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
+    }
+    c.phase = Scan16Call::kMark;
+    c.stride = 1;
+    DD_TRY(launch_scan16(D, fp16, c, st));
+    DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
+    unsigned ni = 0;
+    DD_HIP(hipMemcpyAsync(&ni, n_items, sizeof(ni), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    if (ni > c.item_cap) {
+      // too many items were logged under the running bound: mark again under
+      // the final bound, which logs only tiles holding certified candidates
+      DD_HIP(hipMemsetAsync(n_items, 0, sizeof(unsigned), st));
+      DD_TRY(launch_scan16(D, fp16, c, st));
+      DD_HIP(hipMemcpyAsync(&ni, n_items, sizeof(ni), hipMemcpyDeviceToHost, st));
+      DD_HIP(hipStreamSynchronize(st));
+      if (ni > c.item_cap) return set_error(DD_ERR_TOO_LARGE, "16-bit scan work list overflow");
+    }
+    n_items_host = ni;
+    c.phase = Scan16Call::kExtract;
+    c.item_cap = ni;
+    DD_TRY(launch_scan16(D, fp16, c, st));
     DD_TRY(timing.mark(2, st));
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
-    DD_TRY(launch_merge_rerank(D, Q, all, m, cb, true, out, fb, counters,
+    DD_TRY(launch_merge_rerank(D, Q, all, m, cb, Q.u32, out, fb, counters,
                                reinterpret_cast<unsigned long long*>(counters + 2), st));
     int h = 0;
     DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -190,6 +236,7 @@ extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, 
     opts->stats->visited = 0;
     opts->stats->scan_ms = scan_ms;
     opts->stats->total_ms = total_ms;
+    opts->stats->slow_tiles = n_items_host;
   }
   return DD_OK;
 }

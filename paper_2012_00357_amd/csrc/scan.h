@@ -41,22 +41,87 @@ dd_status prepare_queries(const Dataset& D, const double* states, int64_t m, con
 // FP64 MFMA scan (expanded form) over the list; fills cb (P = 4, d-space bounds).
 dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len,
                         const CandBuf& cb, hipStream_t st);
-// 16-bit MFMA scan over tile-centred data (P = 2, sqrt-space bounds).
-dd_status launch_scan16(const Dataset& D, bool fp16, const QueryPrep& Q, QueryList L,
-                        int64_t list_len, const CandBuf& cb, hipStream_t st);
+// 16-bit MFMA scan over tile-centred data (sqrt-space bounds), in phases:
+//   kBound    streaming pass: U_out[p][S] = split bounds (tiles visited with stride)
+//   kMark     the same, also logging work items (query group, tile) that may hold
+//             candidates under the running bound
+//   kExtract  recompute the logged items and append every point whose lower bound
+//             is <= the query's final bound Q->u32 to cb (slot p*2 + half, counts
+//             claimed atomically; cb.count must start at zero)
+struct WorkItem {
+  uint32_t group;   // list position of the group's first query / 32
+  uint32_t tile;
+};
+struct Scan16Call {
+  enum Phase { kBound = 0, kMark = 1, kExtract = 2 };
+  int phase = kBound;
+  const QueryPrep* Q = nullptr;
+  QueryList L;
+  int64_t list_len_max = 0;
+  int S = 1;
+  int stride = 1;
+  float* U_out = nullptr;
+  WorkItem* items = nullptr;
+  unsigned* n_items = nullptr;
+  unsigned item_cap = 0;
+  CandBuf cb;
+};
+dd_status launch_scan16(const Dataset& D, bool fp16, const Scan16Call& call, hipStream_t st);
 // Merge candidate lists, rerank in FP64 direct form, write outputs; queries that
-// overflowed (or found no candidate) are appended to fb_list / fb_count.
+// overflowed (or found no candidate) are appended to fb_list / fb_count.  The
+// bound is Uq[q] when given, else the minimum of cb.U over the splits.
 dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
-                              int64_t list_len, const CandBuf& cb, bool sqrt_space, Outputs out,
+                              int64_t list_len, const CandBuf& cb, const float* Uq, Outputs out,
                               int* fb_list, int* fb_count, unsigned long long* n_cand,
                               hipStream_t st);
 // Plain FP64 direct-form scan with lexicographic (dist, original index) minimum,
 // split over the data, followed by its merge.
 dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len, int S,
                      Outputs out, hipStream_t st);
-// Write idx -1 / dist NaN for invalid states.
-dd_status launch_mark_invalid(const QueryPrep& Q, int64_t m, Outputs out, hipStream_t st);
 
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
+
+// u32[q] = min(u32[q], min over the S split bounds U[p][S]).
+dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U, int S, float* u32,
+                               hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Device helpers shared by the scan translation units
+// ---------------------------------------------------------------------------
+constexpr float kRelUp = 1.0f + 9.5367431640625e-07f;   // 1 + 2^-20
+constexpr float kRelDn = 1.0f - 9.5367431640625e-07f;   // 1 - 2^-20
+
+// Candidate list append; a full list is compacted to the entries whose lower
+// bound is still <= U before it is declared overflowed.
+__device__ inline void cand_append(const CandBuf& cb, int64_t slot, int& cnt, bool& ovf, float lb,
+                                   uint32_t j, float U) {
+  if (ovf) return;
+  float* L = cb.lb + slot * cb.K;
+  uint32_t* J = cb.j + slot * cb.K;
+  if (cnt == cb.K) {
+    int k = 0;
+    for (int c = 0; c < cb.K; ++c) {
+      float v = L[c];
+      if (v <= U) {
+        uint32_t jj = J[c];
+        L[k] = v;
+        J[k] = jj;
+        ++k;
+      }
+    }
+    cnt = k;
+    if (cnt == cb.K) {
+      ovf = true;
+      return;
+    }
+  }
+  L[cnt] = lb;
+  J[cnt] = j;
+  ++cnt;
+}
+
+__device__ inline int64_t list_len(const QueryList& L) { return L.list ? (int64_t)*L.count : L.m; }
+__device__ inline int64_t list_query(const QueryList& L, int64_t p) { return L.list ? (int64_t)L.list[p] : p; }
+
 
 }  // namespace dd

@@ -22,9 +22,6 @@
 
 namespace dd {
 
-constexpr float kRelUp = 1.0f + 9.5367431640625e-07f;   // 1 + 2^-20
-constexpr float kRelDn = 1.0f - 9.5367431640625e-07f;   // 1 - 2^-20
-
 static unsigned grid1(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested) {
@@ -114,398 +111,26 @@ dd_status prepare_queries(const Dataset& D, const double* states, int64_t m, con
   return DD_OK;
 }
 
+
 // ---------------------------------------------------------------------------
-// Candidate list append with compaction
+// Bound-only pass reduction: u32[q] = min over splits of the split bounds.
 // ---------------------------------------------------------------------------
-__device__ inline void cand_append(const CandBuf& cb, int64_t slot, int& cnt, bool& ovf, float lb,
-                                   uint32_t j, float U) {
-  if (ovf) return;
-  float* L = cb.lb + slot * cb.K;
-  uint32_t* J = cb.j + slot * cb.K;
-  if (cnt == cb.K) {
-    int k = 0;
-    for (int c = 0; c < cb.K; ++c) {
-      float v = L[c];
-      if (v <= U) {
-        uint32_t jj = J[c];
-        L[k] = v;
-        J[k] = jj;
-        ++k;
-      }
-    }
-    cnt = k;
-    if (cnt == cb.K) {
-      ovf = true;
-      return;
-    }
-  }
-  L[cnt] = lb;
-  J[cnt] = j;
-  ++cnt;
+__global__ void reduce_bounds_kernel(QueryList L, const float* __restrict__ U, int S,
+                                     float* __restrict__ u32) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= list_len(L)) return;
+  float u = INFINITY;
+  for (int s = 0; s < S; ++s) u = fminf(u, U[p * S + s]);
+  const int64_t q = list_query(L, p);
+  u32[q] = fminf(u32[q], u);
 }
 
-__device__ inline int64_t list_len(const QueryList& L) { return L.list ? (int64_t)*L.count : L.m; }
-__device__ inline int64_t list_query(const QueryList& L, int64_t p) { return L.list ? (int64_t)L.list[p] : p; }
-
-// ---------------------------------------------------------------------------
-// FP64 MFMA scan.  v_mfma_f64_16x16x4: A (16 data rows x 4 k) one double per
-// lane (row = lane%16, k = lane/16), B (4 k x 16 queries) one double per lane
-// (query = lane%16, k = lane/16), D register i holds row lane/16 + 4 i of
-// query lane%16.
-// Score s_j = |x_j|^2 - 2 q.x_j over K = 12 (three MFMAs); d~ = s + |q|^2.
-// ---------------------------------------------------------------------------
-constexpr int kG64 = 4;                                  // 16-query groups per wave
-constexpr int kQ64 = 4 * kG64 * 16;                      // queries per workgroup
-
-__global__ __launch_bounds__(256) void scan64_kernel(
-    const double* __restrict__ w64, const double* __restrict__ n64, int64_t n_tiles, int64_t N,
-    const double* __restrict__ qw, const double* __restrict__ qn2, const double* __restrict__ u64,
-    const int* __restrict__ invalid, double xmax, QueryList L, CandBuf cb) {
-  __shared__ double xs[2][12][kTile64];
-  __shared__ double ns[2][kTile64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int col = lane & 15, kq = lane >> 4;
-  const int S = cb.S;
-  const int split = blockIdx.x % S;
-  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ64;
-  const int64_t len = list_len(L);
-  if (qbase >= len) return;
-  const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
-
-  double b[kG64][3], qn[kG64], U[kG64], alpha[kG64];
-  bool valid[kG64];
-  int64_t pos[kG64];
-  int cnt[kG64];
-  bool ovf[kG64];
-#pragma unroll
-  for (int g = 0; g < kG64; ++g) {
-    int64_t p = qbase + wave * 16 * kG64 + g * 16 + col;
-    bool v = p < len;
-    int64_t q = v ? list_query(L, p) : 0;
-    v = v && !invalid[q];
-    valid[g] = v;
-    pos[g] = p;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) b[g][s] = v ? -2.0 * qw[12 * q + 4 * s + kq] : 0.0;
-    qn[g] = v ? qn2[q] : 0.0;
-    U[g] = v ? u64[q] : INFINITY;
-    double qa = sqrt(qn[g]) + xmax;
-    // |d~ - d| <= 15 roundings of terms bounded by (|q| + max|x|)^2
-    alpha[g] = 0x1p-48 * qa * qa + 1e-300;
-    cnt[g] = 0;
-    ovf[g] = false;
-  }
-
-  if (t0 < t1) {
-    auto load = [&](int64_t t, double (&reg)[6], double& nreg) {
-      const double* src = w64 + t * kTile64 * 12;
-#pragma unroll
-      for (int r = 0; r < 6; ++r) reg[r] = src[tid + 256 * r];
-      nreg = (tid < kTile64) ? n64[t * kTile64 + tid] : 0.0;
-    };
-    auto store = [&](int buf, const double (&reg)[6], double nreg) {
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
-        int e = tid + 256 * r;
-        xs[buf][e % 12][e / 12] = reg[r];
-      }
-      if (tid < kTile64) ns[buf][tid] = nreg;
-    };
-    double reg[6], nreg;
-    load(t0, reg, nreg);
-    store(0, reg, nreg);
-    __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) {
-      const int cur = (int)((t - t0) & 1);
-      const bool more = t + 1 < t1;
-      if (more) load(t + 1, reg, nreg);
-      double tm[kG64];
-#pragma unroll
-      for (int g = 0; g < kG64; ++g) tm[g] = INFINITY;
-#pragma unroll 2
-      for (int rb = 0; rb < kTile64 / 16; ++rb) {
-        const int r0 = rb * 16 + col;
-        double a0 = xs[cur][kq][r0], a1 = xs[cur][4 + kq][r0], a2 = xs[cur][8 + kq][r0];
-        double nr[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) nr[i] = ns[cur][rb * 16 + kq + 4 * i];
-#pragma unroll
-        for (int g = 0; g < kG64; ++g) {
-          f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[g][0], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[g][1], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b[g][2], acc, 0, 0, 0);
-          double m01 = fmin(acc[0] + nr[0], acc[1] + nr[1]);
-          double m23 = fmin(acc[2] + nr[2], acc[3] + nr[3]);
-          tm[g] = fmin(tm[g], fmin(m01, m23));
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < kG64; ++g) {
-        double v = tm[g];
-        v = fmin(v, __shfl_xor(v, 16));
-        v = fmin(v, __shfl_xor(v, 32));
-        double dmin = v + qn[g];
-        double Un = fmin(U[g], dmin + alpha[g]);
-        bool need = valid[g] && (dmin - alpha[g] <= Un);
-        U[g] = Un;
-        if (__any(need)) {
-          const float Uf = __double2float_ru(U[g]);
-          const int64_t slot = (pos[g] * S + split) * 4 + kq;
-          for (int rb = 0; rb < kTile64 / 16; ++rb) {
-            const int r0 = rb * 16 + col;
-            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][kq][r0], b[g][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][4 + kq][r0], b[g][1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][8 + kq][r0], b[g][2], acc, 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int row = rb * 16 + kq + 4 * i;
-              const int64_t j = t * kTile64 + row;
-              double d = acc[i] + ns[cur][row] + qn[g];
-              double lb = d - alpha[g];
-              if (valid[g] && j < N && lb <= U[g])
-                cand_append(cb, slot, cnt[g], ovf[g], __double2float_rd(lb), (uint32_t)j, Uf);
-            }
-          }
-        }
-      }
-      if (more) store(cur ^ 1, reg, nreg);
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int g = 0; g < kG64; ++g) {
-    if (pos[g] < len) {
-      const int64_t slot = (pos[g] * S + split) * 4 + kq;
-      cb.count[slot] = cnt[g] | (ovf[g] ? kOverflowBit : 0);
-      if (kq == 0) cb.U[pos[g] * S + split] = __double2float_ru(U[g]);
-    }
-  }
-}
-
-dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len_max,
-                        const CandBuf& cb, hipStream_t st) {
+dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U, int S, float* u32,
+                               hipStream_t st) {
   if (list_len_max <= 0) return DD_OK;
-  int64_t qblocks = (list_len_max + kQ64 - 1) / kQ64;
-  int64_t n_tiles = D.n_pad64 / kTile64;
-  hipLaunchKernelGGL(scan64_kernel, dim3((unsigned)(qblocks * cb.S)), dim3(256), 0, st,
-                     D.w64.as<double>(), D.n64.as<double>(), n_tiles, D.N, Q.qw, Q.qn2, Q.u64,
-                     Q.invalid, D.xmax, L, cb);
+  hipLaunchKernelGGL(reduce_bounds_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, U, S, u32);
   DD_HIP(hipGetLastError());
   return DD_OK;
-}
-
-// ---------------------------------------------------------------------------
-// 16-bit MFMA scan over tile-centred data.  v_mfma_f32_32x32x16_{bf16,f16}:
-// A (32 data rows x 16 k): lane supplies row lane%32, k = 8*(lane/32)..+7;
-// B (16 k x 32 queries): lane supplies query lane%32, same k range;
-// D: lane holds rows 8*(i/4) + 4*(lane/32) + i%4 (i < 16) of query lane%32.
-// Data row (-2 x', n_hi, n_mid, n_lo, 0), query column (q', 1, 1, 1, 0) with
-// q' = round16(q - c_T): the MFMA yields |x'|^2 - 2 q'.x', and d~ = that + |q'|^2.
-// ---------------------------------------------------------------------------
-template <class T16> struct Vec16;
-template <> struct Vec16<Bf16> {
-  typedef bf16x8_t type;
-  __device__ static inline f32x16_t mfma(type a, type b, f32x16_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Vec16<Fp16> {
-  typedef f16x8_t type;
-  __device__ static inline f32x16_t mfma(type a, type b, f32x16_t c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-  }
-};
-
-__device__ inline float min16(const f32x16_t& a) {
-  float m0 = fminf(fminf(a[0], a[1]), a[2]);
-  float m1 = fminf(fminf(a[3], a[4]), a[5]);
-  float m2 = fminf(fminf(a[6], a[7]), a[8]);
-  float m3 = fminf(fminf(a[9], a[10]), a[11]);
-  float m4 = fminf(fminf(a[12], a[13]), a[14]);
-  float m5 = fminf(fminf(m0, m1), m2);
-  float m6 = fminf(fminf(m3, m4), a[15]);
-  return fminf(m5, m6);
-}
-
-constexpr int kG16 = 2;                                  // 32-query groups per wave
-constexpr int kQ16 = 4 * kG16 * 32;                      // queries per workgroup
-
-template <class T16, int TILE>
-__global__ __launch_bounds__(256) void scan16_kernel(
-    const uint4* __restrict__ wp, const float* __restrict__ centre, const float* __restrict__ radius,
-    int64_t n_tiles, int64_t N, const double* __restrict__ qw, const double* __restrict__ qn2,
-    const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L, CandBuf cb) {
-  typedef typename Vec16<T16>::type vec_t;
-  constexpr int V = TILE * 2 / 256;   // uint4 per thread per tile
-  static_assert(V >= 1 && TILE * 2 % 256 == 0, "tile");
-  __shared__ uint4 lds[2][TILE * 2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int h = lane >> 5, col = lane & 31;
-  const int S = cb.S;
-  const int split = blockIdx.x % S;
-  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ16;
-  const int64_t len = list_len(L);
-  if (qbase >= len) return;
-  const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
-
-  float qf[kG16][8], qabs[kG16], U[kG16];
-  bool valid[kG16];
-  int64_t pos[kG16];
-  int cnt[kG16];
-  bool ovf[kG16];
-#pragma unroll
-  for (int g = 0; g < kG16; ++g) {
-    int64_t p = qbase + wave * 32 * kG16 + g * 32 + col;
-    bool v = p < len;
-    int64_t q = v ? list_query(L, p) : 0;
-    v = v && !invalid[q];
-    valid[g] = v;
-    pos[g] = p;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      int k = 8 * h + i;
-      qf[g][i] = (k < 12) ? (v ? (float)qw[12 * q + k] : 0.0f) : (k < 15 ? 1.0f : 0.0f);
-    }
-    qabs[g] = v ? (float)sqrt(qn2[q]) : 0.0f;
-    U[g] = v ? u32[q] : INFINITY;
-    cnt[g] = 0;
-    ovf[g] = false;
-  }
-
-  if (t0 < t1) {
-    uint4 pre[V];
-    {
-      const uint4* src = wp + t0 * TILE * 2;
-#pragma unroll
-      for (int v = 0; v < V; ++v) lds[0][tid + 256 * v] = src[tid + 256 * v];
-    }
-    __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) {
-      const int cur = (int)((t - t0) & 1);
-      const bool more = t + 1 < t1;
-      if (more) {
-        const uint4* src = wp + (t + 1) * TILE * 2;
-#pragma unroll
-        for (int v = 0; v < V; ++v) pre[v] = src[tid + 256 * v];
-      }
-      // centred query operands of this tile
-      const float* cp = centre + 12 * t;
-      const float rad = radius[t];
-      float cs[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) cs[i] = h ? (i < 4 ? cp[8 + i] : 0.0f) : cp[i];
-      vec_t B[kG16];
-      float o[kG16], eta[kG16], alpha[kG16];
-#pragma unroll
-      for (int g = 0; g < kG16; ++g) {
-        uint16_t bits[8];
-        float rsq = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          bits[i] = T16::from_float(qf[g][i] - cs[i]);
-          float rv = T16::to_float(bits[i]);
-          if (i < 4 || h == 0) rsq = fmaf(rv, rv, rsq);
-        }
-        o[g] = rsq + __shfl_xor(rsq, 32);
-        uint4 pk;
-        pk.x = bits[0] | ((uint32_t)bits[1] << 16);
-        pk.y = bits[2] | ((uint32_t)bits[3] << 16);
-        pk.z = bits[4] | ((uint32_t)bits[5] << 16);
-        pk.w = bits[6] | ((uint32_t)bits[7] << 16);
-        B[g] = __builtin_bit_cast(vec_t, pk);
-        const float so = sqrtf(o[g]);
-        // |q^' - (q - c)| <= u (|q - c| + ...) with |q - c| <= so / (1 - u); |x^' - x'| <= u r
-        eta[g] = (T16::kUnit * (1.0043f * so + rad) + 1.8e-7f * (qabs[g] + so) + 8.0f * T16::kAbs) * kRelUp;
-        const float sr = so + rad;
-        alpha[g] = 3.814697265625e-06f * sr * sr + 16.0f * T16::kAbs;   // 2^-18 (|q'| + r)^2
-      }
-      float tm[kG16];
-#pragma unroll
-      for (int g = 0; g < kG16; ++g) tm[g] = INFINITY;
-      const f32x16_t zero = {};
-#pragma unroll 4
-      for (int rb = 0; rb < TILE / 32; ++rb) {
-        vec_t A = __builtin_bit_cast(vec_t, lds[cur][(rb * 32 + col) * 2 + h]);
-#pragma unroll
-        for (int g = 0; g < kG16; ++g) {
-          f32x16_t acc = Vec16<T16>::mfma(A, B[g], zero);
-          tm[g] = fminf(tm[g], min16(acc));
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < kG16; ++g) {
-        float v = fminf(tm[g], __shfl_xor(tm[g], 32));
-        float dmin = v + o[g];
-        float Uc = (sqrtf(dmin + alpha[g]) + eta[g]) * kRelUp;
-        float Un = fminf(U[g], Uc);
-        float lbmin = sqrtf(fmaxf(dmin - alpha[g], 0.0f)) * kRelDn - eta[g];
-        bool need = valid[g] && (lbmin <= Un);
-        U[g] = Un;
-        if (__any(need)) {
-          const int64_t slot = (pos[g] * S + split) * 2 + h;
-          for (int rb = 0; rb < TILE / 32; ++rb) {
-            vec_t A = __builtin_bit_cast(vec_t, lds[cur][(rb * 32 + col) * 2 + h]);
-            f32x16_t acc = Vec16<T16>::mfma(A, B[g], zero);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-              const int64_t j = t * TILE + row;
-              float d = acc[i] + o[g];
-              float lb = sqrtf(fmaxf(d - alpha[g], 0.0f)) * kRelDn - eta[g];
-              if (valid[g] && j < N && lb <= U[g])
-                cand_append(cb, slot, cnt[g], ovf[g], lb, (uint32_t)j, U[g]);
-            }
-          }
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) lds[cur ^ 1][tid + 256 * v] = pre[v];
-      }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int g = 0; g < kG16; ++g) {
-    if (pos[g] < len) {
-      const int64_t slot = (pos[g] * S + split) * 2 + h;
-      cb.count[slot] = cnt[g] | (ovf[g] ? kOverflowBit : 0);
-      if (h == 0) cb.U[pos[g] * S + split] = U[g];
-    }
-  }
-}
-
-template <class T16>
-static dd_status launch16(const Dataset& D, const uint16_t* pack, const QueryPrep& Q, QueryList L,
-                          int64_t list_len_max, const CandBuf& cb, hipStream_t st) {
-  int64_t qblocks = (list_len_max + kQ16 - 1) / kQ16;
-  dim3 grid((unsigned)(qblocks * cb.S));
-  const uint4* wp = reinterpret_cast<const uint4*>(pack);
-#define DD_SCAN16_CASE(TT)                                                                        \
-  case TT:                                                                                        \
-    hipLaunchKernelGGL((scan16_kernel<T16, TT>), grid, dim3(256), 0, st, wp, D.centre.as<float>(), \
-                       D.radius.as<float>(), D.n_tiles, D.N, Q.qw, Q.qn2, Q.u32, Q.invalid, L, cb); \
-    break;
-  switch (D.tile) {
-    DD_SCAN16_CASE(128)
-    DD_SCAN16_CASE(256)
-    DD_SCAN16_CASE(512)
-    DD_SCAN16_CASE(1024)
-    default:
-      return set_error(DD_ERR_UNSUPPORTED, "16-bit scan supports tiles of 128, 256, 512 or 1024");
-  }
-#undef DD_SCAN16_CASE
-  DD_HIP(hipGetLastError());
-  return DD_OK;
-}
-
-dd_status launch_scan16(const Dataset& D, bool fp16, const QueryPrep& Q, QueryList L,
-                        int64_t list_len_max, const CandBuf& cb, hipStream_t st) {
-  if (list_len_max <= 0) return DD_OK;
-  if (fp16) return launch16<Fp16>(D, D.wfp16.as<uint16_t>(), Q, L, list_len_max, cb, st);
-  return launch16<Bf16>(D, D.wbf16.as<uint16_t>(), Q, L, list_len_max, cb, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,7 +138,8 @@ dd_status launch_scan16(const Dataset& D, bool fp16, const QueryPrep& Q, QueryLi
 // (distance, original index) over every certified candidate.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void merge_rerank_kernel(
-    QueryList L, CandBuf cb, const double* __restrict__ qw, const int* __restrict__ invalid,
+    QueryList L, CandBuf cb, const float* __restrict__ Uq, const double* __restrict__ qw,
+    const int* __restrict__ invalid,
     const double* __restrict__ w64, const float* __restrict__ w32, const uint32_t* __restrict__ perm,
     Outputs out, int* __restrict__ fb_list, int* __restrict__ fb_count,
     unsigned long long* __restrict__ n_cand) {
@@ -527,7 +153,11 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(
   }
   const int S = cb.S, P = cb.P, K = cb.K;
   float Uf = INFINITY;
-  for (int s = 0; s < S; ++s) Uf = fminf(Uf, cb.U[p * S + s]);
+  if (Uq) {
+    Uf = Uq[q];
+  } else {
+    for (int s = 0; s < S; ++s) Uf = fminf(Uf, cb.U[p * S + s]);
+  }
   double qv[12];
   for (int k = 0; k < 12; ++k) qv[k] = qw[12 * q + k];
   double best = INFINITY;
@@ -538,8 +168,9 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(
     for (int part = 0; part < P; ++part) {
       const int64_t slot = (p * S + s) * P + part;
       const int c = cb.count[slot];
-      ovf = ovf || (c & kOverflowBit);
-      const int n = c & ~kOverflowBit;
+      const int raw = c & ~kOverflowBit;
+      ovf = ovf || (c & kOverflowBit) || raw > K;
+      const int n = raw < K ? raw : K;
       for (int e = 0; e < n; ++e) {
         if (cb.lb[slot * K + e] <= Uf) {
           const uint32_t j = cb.j[slot * K + e];
@@ -570,11 +201,11 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(
 }
 
 dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
-                              int64_t list_len_max, const CandBuf& cb, bool /*sqrt_space*/,
+                              int64_t list_len_max, const CandBuf& cb, const float* Uq,
                               Outputs out, int* fb_list, int* fb_count, unsigned long long* n_cand,
                               hipStream_t st) {
   if (list_len_max <= 0) return DD_OK;
-  hipLaunchKernelGGL(merge_rerank_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, cb, Q.qw,
+  hipLaunchKernelGGL(merge_rerank_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, cb, Uq, Q.qw,
                      Q.invalid, D.w64.as<double>(), D.w64.p ? nullptr : D.w32.as<float>(),
                      D.perm.as<uint32_t>(), out, fb_list, fb_count, n_cand);
   DD_HIP(hipGetLastError());

@@ -1,0 +1,508 @@
+// MFMA scans of the projection P_D (Section 2) in whitened coordinates
+// (Section 3.2).  See scan.hip for the certification scheme they share.
+//
+// This translation unit is compiled with IEEE mode off and without NaN
+// semantics (its inputs are finite: invalid queries are zeroed by the
+// preparation kernel), so that min reductions of matrix-core results need no
+// canonicalisation, and with matrix results kept in ordinary VGPRs.
+#include <cmath>
+
+#include "pack16.h"
+#include "scan.h"
+
+namespace dd {
+
+__device__ static inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }   // 1 ulp
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA scan.  v_mfma_f64_16x16x4: A (16 data rows x 4 k) one double per
+// lane (row = lane%16, k = lane/16), B (4 k x 16 queries) one double per lane
+// (query = lane%16, k = lane/16), D register i holds row lane/16 + 4 i of
+// query lane%16.  Score s_j = |x_j|^2 - 2 q.x_j over K = 12 (three MFMAs);
+// d~ = s + |q|^2.
+// ---------------------------------------------------------------------------
+constexpr int kG64 = 4;                                  // 16-query groups per wave
+constexpr int kQ64 = 4 * kG64 * 16;                      // queries per workgroup
+
+__global__ __launch_bounds__(256) void scan64_kernel(
+    const double* __restrict__ w64, const double* __restrict__ n64, int64_t n_tiles, int64_t N,
+    const double* __restrict__ qw, const double* __restrict__ qn2, const double* __restrict__ u64,
+    const int* __restrict__ invalid, double xmax, QueryList L, CandBuf cb) {
+  __shared__ double xs[2][12][kTile64];
+  __shared__ double ns[2][kTile64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int S = cb.S;
+  const int split = blockIdx.x % S;
+  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ64;
+  const int64_t len = list_len(L);
+  if (qbase >= len) return;
+  const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
+
+  double b[kG64][3], qn[kG64], U[kG64], alpha[kG64];
+  bool valid[kG64];
+  int64_t pos[kG64];
+  int cnt[kG64];
+  bool ovf[kG64];
+#pragma unroll
+  for (int g = 0; g < kG64; ++g) {
+    int64_t p = qbase + wave * 16 * kG64 + g * 16 + col;
+    bool v = p < len;
+    int64_t q = v ? list_query(L, p) : 0;
+    v = v && !invalid[q];
+    valid[g] = v;
+    pos[g] = p;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) b[g][s] = v ? -2.0 * qw[12 * q + 4 * s + kq] : 0.0;
+    qn[g] = v ? qn2[q] : 0.0;
+    U[g] = v ? u64[q] : INFINITY;
+    double qa = sqrt(qn[g]) + xmax;
+    // |d~ - d| <= 15 roundings of terms bounded by (|q| + max|x|)^2
+    alpha[g] = 0x1p-48 * qa * qa + 1e-300;
+    cnt[g] = 0;
+    ovf[g] = false;
+  }
+
+  if (t0 < t1) {
+    auto load = [&](int64_t t, double (&reg)[6], double& nreg) {
+      const double* src = w64 + t * kTile64 * 12;
+#pragma unroll
+      for (int r = 0; r < 6; ++r) reg[r] = src[tid + 256 * r];
+      nreg = (tid < kTile64) ? n64[t * kTile64 + tid] : 0.0;
+    };
+    auto store = [&](int buf, const double (&reg)[6], double nreg) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        int e = tid + 256 * r;
+        xs[buf][e % 12][e / 12] = reg[r];
+      }
+      if (tid < kTile64) ns[buf][tid] = nreg;
+    };
+    double reg[6], nreg;
+    load(t0, reg, nreg);
+    store(0, reg, nreg);
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+      const int cur = (int)((t - t0) & 1);
+      const bool more = t + 1 < t1;
+      if (more) load(t + 1, reg, nreg);
+      double tm[kG64];
+#pragma unroll
+      for (int g = 0; g < kG64; ++g) tm[g] = INFINITY;
+#pragma unroll
+      for (int rb = 0; rb < kTile64 / 16; ++rb) {
+        const int r0 = rb * 16 + col;
+        double a0 = xs[cur][kq][r0], a1 = xs[cur][4 + kq][r0], a2 = xs[cur][8 + kq][r0];
+        double nr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) nr[i] = ns[cur][rb * 16 + kq + 4 * i];
+#pragma unroll
+        for (int g = 0; g < kG64; ++g) {
+          f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[g][0], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[g][1], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b[g][2], acc, 0, 0, 0);
+          double m01 = fmin(acc[0] + nr[0], acc[1] + nr[1]);
+          double m23 = fmin(acc[2] + nr[2], acc[3] + nr[3]);
+          tm[g] = fmin(tm[g], fmin(m01, m23));
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kG64; ++g) {
+        double v = tm[g];
+        v = fmin(v, __shfl_xor(v, 16));
+        v = fmin(v, __shfl_xor(v, 32));
+        double dmin = v + qn[g];
+        double Un = fmin(U[g], dmin + alpha[g]);
+        bool need = valid[g] && (dmin - alpha[g] <= Un);
+        U[g] = Un;
+        if (__any(need)) {
+          const float Uf = __double2float_ru(U[g]);
+          const int64_t slot = (pos[g] * S + split) * 4 + kq;
+          for (int rb = 0; rb < kTile64 / 16; ++rb) {
+            const int r0 = rb * 16 + col;
+            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][kq][r0], b[g][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][4 + kq][r0], b[g][1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][8 + kq][r0], b[g][2], acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = rb * 16 + kq + 4 * i;
+              const int64_t j = t * kTile64 + row;
+              double d = acc[i] + ns[cur][row] + qn[g];
+              double lb = d - alpha[g];
+              if (valid[g] && j < N && lb <= U[g])
+                cand_append(cb, slot, cnt[g], ovf[g], __double2float_rd(lb), (uint32_t)j, Uf);
+            }
+          }
+        }
+      }
+      if (more) store(cur ^ 1, reg, nreg);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < kG64; ++g) {
+    if (pos[g] < len) {
+      const int64_t slot = (pos[g] * S + split) * 4 + kq;
+      cb.count[slot] = cnt[g] | (ovf[g] ? kOverflowBit : 0);
+      if (kq == 0) cb.U[pos[g] * S + split] = __double2float_ru(U[g]);
+    }
+  }
+}
+
+dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len_max,
+                        const CandBuf& cb, hipStream_t st) {
+  if (list_len_max <= 0) return DD_OK;
+  int64_t qblocks = (list_len_max + kQ64 - 1) / kQ64;
+  int64_t n_tiles = D.n_pad64 / kTile64;
+  hipLaunchKernelGGL(scan64_kernel, dim3((unsigned)(qblocks * cb.S)), dim3(256), 0, st,
+                     D.w64.as<double>(), D.n64.as<double>(), n_tiles, D.N, Q.qw, Q.qn2, Q.u64,
+                     Q.invalid, D.xmax, L, cb);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit MFMA scan over tile-centred data.  v_mfma_f32_32x32x16_{bf16,f16}:
+// A (32 data rows x 16 k): lane supplies row lane%32, k = 8*(lane/32)..+7;
+// B (16 k x 32 queries): lane supplies query lane%32, same k range;
+// D: lane holds rows 8*(i/4) + 4*(lane/32) + i%4 (i < 16) of query lane%32.
+// Data row (-2 x', n_hi, n_mid, n_lo, 0), query column (q', 1, 1, 1, 0) with
+// q' = round16(q - c_T): the MFMA yields |x'|^2 - 2 q'.x', and d~ = that + |q'|^2.
+//
+// Bounds per (query, tile), sqrt-space: |sqrt(d~) - sqrt(d)| <= eta + alpha terms
+//   eta   = u (|q'| + r_T) + FP32 rounding of q and q - c_T (+ subnormal floor)
+//   alpha = 2^-18 (|q'| + r_T)^2 >= the FP32 accumulation error of 16 terms
+// EXTRACT = false: bound-only pass (no candidate lists).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
+template <class T16> struct Vec16;
+template <> struct Vec16<Bf16> {
+  typedef bf16x8_t type;
+  __device__ static inline f32x16_t mfma(type a, type b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  // two FP32 values -> packed pair, round to nearest even (v_cvt_pk_bf16_f32)
+  __device__ static inline uint32_t pack2(float a, float b) {
+    bf16x2_t v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+  }
+  // FP32 dot of a packed pair with itself, accumulated (v_dot2c_f32_bf16)
+  __device__ static inline float dot2(uint32_t p, float c) {
+    bf16x2_t v = __builtin_bit_cast(bf16x2_t, p);
+    return __builtin_amdgcn_fdot2_f32_bf16(v, v, c, false);
+  }
+};
+template <> struct Vec16<Fp16> {
+  typedef f16x8_t type;
+  __device__ static inline f32x16_t mfma(type a, type b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline uint32_t pack2(float a, float b) {
+    f16x2_t v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+  }
+  __device__ static inline float dot2(uint32_t p, float c) {
+    f16x2_t v = __builtin_bit_cast(f16x2_t, p);
+    return __builtin_amdgcn_fdot2(v, v, c, false);
+  }
+};
+
+// Running minimum over 16 new values: 17 inputs, eight 3-input minima.
+__device__ inline float min16(float run, const f32x16_t& a) {
+  float m0 = fminf(fminf(a[0], a[1]), a[2]);
+  float m1 = fminf(fminf(a[3], a[4]), a[5]);
+  float m2 = fminf(fminf(a[6], a[7]), a[8]);
+  float m3 = fminf(fminf(a[9], a[10]), a[11]);
+  float m4 = fminf(fminf(a[12], a[13]), a[14]);
+  float m5 = fminf(fminf(m0, m1), m2);
+  float m6 = fminf(fminf(m3, m4), a[15]);
+  return fminf(fminf(run, m5), m6);
+}
+
+constexpr int kG16 = 2;                                  // 32-query groups per wave
+constexpr int kQ16 = 4 * kG16 * 32;                      // queries per workgroup
+static_assert(kG16 == 2, "the pipelined inner loop is written for two query groups");
+
+// Per-(query group, tile) operands of the 16-bit scans: centred query column
+// q' = round16(q - c_T) packed for the MFMA B operand, o = |q'|^2 and the
+// sqrt-space error terms eta, alpha of the bound described above.
+template <class T16>
+__device__ inline void tile_operands(const float (&qf)[8], float qabs, const float (&cs)[8],
+                                     float rad, int h, typename Vec16<T16>::type& B, float& o,
+                                     float& eta, float& alpha) {
+  typedef Vec16<T16> VT;
+  uint4 pk;
+  pk.x = VT::pack2(qf[0] - cs[0], qf[1] - cs[1]);
+  pk.y = VT::pack2(qf[2] - cs[2], qf[3] - cs[3]);
+  pk.z = VT::pack2(qf[4] - cs[4], qf[5] - cs[5]);
+  pk.w = VT::pack2(qf[6] - cs[6], qf[7] - cs[7]);
+  B = __builtin_bit_cast(typename VT::type, pk);
+  // lanes of the upper half hold coordinates 8..11 and the constant slots
+  float lo = VT::dot2(pk.y, VT::dot2(pk.x, 0.0f));
+  float hi = VT::dot2(pk.w, VT::dot2(pk.z, 0.0f));
+  float part = h ? lo : lo + hi;
+  o = part + __shfl_xor(part, 32);
+  const float so = fsqrt(o);
+  eta = (T16::kUnit * (1.0043f * so + rad) + 1.8e-7f * (qabs + so) + 8.0f * T16::kAbs) * kRelUp;
+  const float sr = so + rad;
+  alpha = 3.814697265625e-06f * sr * sr + 16.0f * T16::kAbs + 1e-30f;
+}
+
+// Lane's query coordinates for the B operand: lanes of half h hold k = 8h..8h+7
+// (coordinates 0..11, then the constant slots 1, 1, 1, 0).
+__device__ inline void load_query_column(const double* __restrict__ qw, int64_t q, bool v, int h,
+                                         float (&qf)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int k = 8 * h + i;
+    qf[i] = (k < 12) ? (v ? (float)qw[12 * q + k] : 0.0f) : (k < 15 ? 1.0f : 0.0f);
+  }
+}
+
+__device__ inline void centre_select(const float* __restrict__ cp, int h, float (&cs)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) cs[i] = h ? (i < 4 ? cp[8 + i] : 0.0f) : cp[i];
+}
+
+// Streaming pass of the 16-bit scan.  Every workgroup covers 256 queries (two
+// 32-query groups per wave) against the tiles of its split; the split's tiles
+// are visited with stride `stride` (1 = all; > 1 = a bound-seeding subsample).
+// Tracks the sqrt-space bound U of each query; with MARK, appends a work item
+// whenever some query of a group may have a candidate in the tile (its lower
+// bound <= its running U).  Tiles are staged through LDS half-major (each lane
+// reads 16 consecutive bytes of its row half: conflict-free 128-bit reads).
+template <class T16, int TILE, bool MARK>
+__global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
+    const uint4* __restrict__ wp, const float* __restrict__ centre, const float* __restrict__ radius,
+    int64_t n_tiles, int stride, const double* __restrict__ qw, const double* __restrict__ qn2,
+    const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L, int S,
+    float* __restrict__ U_out, WorkItem* __restrict__ items, unsigned* __restrict__ n_items,
+    unsigned item_cap) {
+  typedef Vec16<T16> VT;
+  typedef typename VT::type vec_t;
+  constexpr int V = TILE * 2 / 256;   // uint4 per thread per tile
+  constexpr int NB = TILE / 32;       // 32-row blocks per tile
+  static_assert(V >= 1 && TILE * 2 % 256 == 0, "tile");
+  __shared__ uint4 lds[2][2 * TILE];  // [buffer][half * TILE + row]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, col = lane & 31;
+  const int split = blockIdx.x % S;
+  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ16;
+  const int64_t len = list_len(L);
+  if (qbase >= len) return;
+  const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
+
+  float qf[kG16][8], qabs[kG16], U[kG16];
+  bool valid[kG16];
+  int64_t pos[kG16];
+#pragma unroll
+  for (int g = 0; g < kG16; ++g) {
+    int64_t p = qbase + wave * 32 * kG16 + g * 32 + col;
+    bool v = p < len;
+    int64_t q = v ? list_query(L, p) : 0;
+    v = v && !invalid[q];
+    valid[g] = v;
+    pos[g] = p;
+    load_query_column(qw, q, v, h, qf[g]);
+    qabs[g] = v ? (float)sqrt(qn2[q]) : 0.0f;
+    U[g] = v ? u32[q] : INFINITY;
+  }
+  // element e of a tile (uint4 e = 2 row + half) lives at lds[half * TILE + row]
+  auto lds_slot = [](int e) { return (e & 1) * TILE + (e >> 1); };
+
+  if (t0 < t1) {
+    {
+      const uint4* src = wp + t0 * TILE * 2;
+#pragma unroll
+      for (int v = 0; v < V; ++v) lds[0][lds_slot(tid + 256 * v)] = src[tid + 256 * v];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t t = t0; t < t1; t += stride) {
+      const int64_t tn = t + stride;
+      const bool more = tn < t1;
+      uint4 pre[V];
+      {
+        const uint4* src = wp + (more ? tn : t) * TILE * 2;
+#pragma unroll
+        for (int v = 0; v < V; ++v) pre[v] = src[tid + 256 * v];
+      }
+      float cs[8];
+      centre_select(centre + 12 * t, h, cs);
+      const float rad = radius[t];
+      vec_t B[kG16];
+      float o[kG16], eta[kG16], alpha[kG16];
+#pragma unroll
+      for (int g = 0; g < kG16; ++g) tile_operands<T16>(qf[g], qabs[g], cs, rad, h, B[g], o[g], eta[g], alpha[g]);
+      // tile minimum of the scores: MFMA k = (row block k/2, group k%2); each
+      // reduction lags two MFMAs behind its producer, so the wave never waits
+      // on a result while the matrix core is busy
+      float tm0 = INFINITY, tm1 = INFINITY;
+      {
+        const f32x16_t zero = {};
+        const uint4* base = &lds[cur][h * TILE + col];
+        f32x16_t acc[3];
+        vec_t A = __builtin_bit_cast(vec_t, base[0]);
+        vec_t An = A;
+#pragma unroll
+        for (int k = 0; k < 2 * NB + 2; ++k) {
+          if (k < 2 * NB) {
+            const int rb = k >> 1, g = k & 1;
+            if (g == 0 && rb + 1 < NB) An = __builtin_bit_cast(vec_t, base[(rb + 1) * 32]);
+            acc[k % 3] = VT::mfma(A, B[g], zero);
+            if (g == 1) A = An;
+          }
+          if (k >= 2) {
+            const int kk = k - 2;
+            if (kk & 1)
+              tm1 = min16(tm1, acc[kk % 3]);
+            else
+              tm0 = min16(tm0, acc[kk % 3]);
+          }
+        }
+      }
+      float tmg[kG16] = {tm0, tm1};
+      unsigned mark = 0;
+#pragma unroll
+      for (int g = 0; g < kG16; ++g) {
+        float v = fminf(tmg[g], __shfl_xor(tmg[g], 32));
+        float dmin = v + o[g];
+        U[g] = fminf(U[g], (fsqrt(dmin + alpha[g]) + eta[g]) * kRelUp);
+        if (MARK) {
+          float lbmin = fsqrt(fmaxf(dmin - alpha[g], 0.0f)) * kRelDn - eta[g];
+          bool need = valid[g] && (lbmin <= U[g]);
+          mark |= __any(need) ? (1u << g) : 0u;
+        }
+      }
+      if (MARK && mark) {
+        // rare: log the (group, tile) items; group ids are wave-uniform
+        const uint32_t g0 = (uint32_t)((qbase + wave * 32 * kG16) / 32);
+        if (lane == 0) {
+          unsigned k = atomicAdd(n_items, (unsigned)__popc(mark));
+          for (int g = 0; g < kG16; ++g)
+            if ((mark >> g) & 1u) {
+              if (k < item_cap) items[k] = WorkItem{g0 + (uint32_t)g, (uint32_t)t};
+              ++k;
+            }
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) lds[cur ^ 1][lds_slot(tid + 256 * v)] = pre[v];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < kG16; ++g)
+    if (pos[g] < len && h == 0) U_out[pos[g] * S + split] = U[g];
+}
+
+// Extraction: one wavefront per work item recomputes the item's 32 x TILE
+// scores and appends every point whose sqrt-space lower bound is <= the query's
+// final bound U to the query's candidate list (two lists per query, one per
+// half-wave row set; slots claimed atomically, so only the order of a list
+// varies between runs, never its content).
+template <class T16, int TILE>
+__global__ __launch_bounds__(256) void scan16_extract_kernel(
+    const uint4* __restrict__ wp, const float* __restrict__ centre, const float* __restrict__ radius,
+    int64_t N, const double* __restrict__ qw, const double* __restrict__ qn2,
+    const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L,
+    const WorkItem* __restrict__ items, const unsigned* __restrict__ n_items, unsigned item_cap,
+    CandBuf cb) {
+  typedef Vec16<T16> VT;
+  typedef typename VT::type vec_t;
+  const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+  const unsigned w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const unsigned total = min(*n_items, item_cap);
+  if (w >= total) return;
+  const WorkItem it = items[w];
+  const int64_t len = list_len(L);
+  const int64_t p = (int64_t)it.group * 32 + col;
+  bool v = p < len;
+  const int64_t q = v ? list_query(L, p) : 0;
+  v = v && !invalid[q];
+  float qf[8];
+  load_query_column(qw, q, v, h, qf);
+  const float qabs = v ? (float)sqrt(qn2[q]) : 0.0f;
+  const float Uq = v ? u32[q] : -INFINITY;
+  const int64_t t = it.tile;
+  float cs[8];
+  centre_select(centre + 12 * t, h, cs);
+  vec_t B;
+  float o, eta, alpha;
+  tile_operands<T16>(qf, qabs, cs, radius[t], h, B, o, eta, alpha);
+  const f32x16_t zero = {};
+  const uint4* src = wp + t * TILE * 2;
+  float* L0 = cb.lb + (p * 2 + h) * cb.K;
+  uint32_t* J0 = cb.j + (p * 2 + h) * cb.K;
+  for (int rb = 0; rb < TILE / 32; ++rb) {
+    vec_t A = __builtin_bit_cast(vec_t, src[(rb * 32 + col) * 2 + h]);
+    f32x16_t acc = VT::mfma(A, B, zero);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+      const int64_t j = t * TILE + row;
+      float lb = fsqrt(fmaxf(acc[i] + o - alpha, 0.0f)) * kRelDn - eta;
+      if (v && j < N && lb <= Uq) {
+        int k = atomicAdd(&cb.count[p * 2 + h], 1);
+        if (k < cb.K) {
+          L0[k] = lb;
+          J0[k] = (uint32_t)j;
+        }
+      }
+    }
+  }
+}
+
+template <class T16, int TILE>
+static dd_status launch16(const Dataset& D, const uint16_t* pack, const Scan16Call& c, hipStream_t st) {
+  const uint4* wp = reinterpret_cast<const uint4*>(pack);
+  const int64_t qblocks = (c.list_len_max + kQ16 - 1) / kQ16;
+  if (c.phase == Scan16Call::kExtract) {
+    const unsigned waves = c.item_cap;   // grid sized for the capacity; extra waves exit
+    const unsigned blocks = (unsigned)(((uint64_t)waves * 64 + 255) / 256);
+    if (blocks == 0) return DD_OK;
+    hipLaunchKernelGGL((scan16_extract_kernel<T16, TILE>), dim3(blocks), dim3(256), 0, st, wp,
+                       D.centre.as<float>(), D.radius.as<float>(), D.N, c.Q->qw, c.Q->qn2,
+                       c.Q->u32, c.Q->invalid, c.L, c.items, c.n_items, c.item_cap, c.cb);
+  } else if (c.phase == Scan16Call::kMark) {
+    hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, true>), dim3((unsigned)(qblocks * c.S)),
+                       dim3(256), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
+                       c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
+                       c.items, c.n_items, c.item_cap);
+  } else {
+    hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, false>), dim3((unsigned)(qblocks * c.S)),
+                       dim3(256), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
+                       c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
+                       c.items, c.n_items, c.item_cap);
+  }
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+template <class T16>
+static dd_status launch16_tile(const Dataset& D, const uint16_t* pack, const Scan16Call& c,
+                               hipStream_t st) {
+  switch (D.tile) {
+    case 128: return launch16<T16, 128>(D, pack, c, st);
+    case 256: return launch16<T16, 256>(D, pack, c, st);
+    case 512: return launch16<T16, 512>(D, pack, c, st);
+    case 1024: return launch16<T16, 1024>(D, pack, c, st);
+    default:
+      return set_error(DD_ERR_UNSUPPORTED, "16-bit scan supports tiles of 128, 256, 512 or 1024");
+  }
+}
+
+dd_status launch_scan16(const Dataset& D, bool fp16, const Scan16Call& c, hipStream_t st) {
+  if (c.list_len_max <= 0) return DD_OK;
+  if (fp16) return launch16_tile<Fp16>(D, D.wfp16.as<uint16_t>(), c, st);
+  return launch16_tile<Bf16>(D, D.wbf16.as<uint16_t>(), c, st);
+}
+
+}  // namespace dd

@@ -37,11 +37,44 @@ __global__ void mfma64_probe(const double* A, const double* B, double* D) {
   for (int i = 0; i < 4; ++i) D[((l / 16) + 4 * i) * 16 + (l % 16)] = acc[i];
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
+// Round 512 FP32 values with the packed conversions the scans use for their
+// query operands (v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32) and widen them back.
+__global__ void cvt_probe(const float* in, float* out, int use_f16) {
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+    float a = in[2 * i], b = in[2 * i + 1];
+    if (use_f16) {
+      f16x2_t v = {(_Float16)a, (_Float16)b};
+      out[2 * i] = (float)v[0];
+      out[2 * i + 1] = (float)v[1];
+    } else {
+      bf16x2_t v = {(__bf16)a, (__bf16)b};
+      out[2 * i] = (float)v[0];
+      out[2 * i + 1] = (float)v[1];
+    }
+  }
+}
+
 }  // namespace dd
 
 extern "C" dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D) {
   using namespace dd;
-  if (!A || !B || !D || kind < 0 || kind > 2) return set_error(DD_ERR_ARG, "selftest arguments");
+  if (!A || !D || kind < 0 || kind > 4 || (kind < 3 && !B))
+    return set_error(DD_ERR_ARG, "selftest arguments");
+  if (kind >= 3) {
+    float in[512], outv[512];
+    for (int i = 0; i < 512; ++i) in[i] = (float)A[i];
+    DevBuf a, d;
+    DD_TRY(a.alloc(sizeof(in))); DD_TRY(d.alloc(sizeof(outv)));
+    DD_HIP(hipMemcpy(a.p, in, sizeof(in), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(cvt_probe, dim3(1), dim3(256), 0, 0, a.as<float>(), d.as<float>(), kind == 4);
+    DD_HIP(hipGetLastError());
+    DD_HIP(hipMemcpy(outv, d.p, sizeof(outv), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 512; ++i) D[i] = outv[i];
+    return DD_OK;
+  }
   if (kind == 2) {
     DevBuf a, b, d;
     DD_TRY(a.alloc(64 * 8)); DD_TRY(b.alloc(64 * 8)); DD_TRY(d.alloc(256 * 8));
