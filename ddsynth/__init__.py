@@ -177,3 +177,25 @@ CONFIGS = {
     4: dict(name="serving N=2^26 hex 4^3/8^3/16^3/24^3", N=1 << 26, meshes=(4, 8, 16, 24),
             traction=(50.0, 200.0), data_seed=1004),
 }
+
+
+def box_bc(n: int, traction: float):
+    """Boundary-value problem of the measured DD solves on the unit cube with
+    n^3 hexahedra (node (i,j,k) id i + (n+1)(j + (n+1)k), DOF 3 id + c):
+    all DOFs of the nodes on x = 0 fixed; uniform normal traction `traction`
+    (+x) on x = 1 as nodal loads, each face quad passing t h^2 / 4 to its nodes.
+    Returns (mask uint8 [ndof], force float64 [ndof])."""
+    n1 = n + 1
+    ndof = 3 * n1 ** 3
+    mask = np.zeros(ndof, dtype=np.uint8)
+    force = np.zeros(ndof)
+    h = 1.0 / n
+    for k in range(n1):
+        for j in range(n1):
+            mask[3 * (0 + n1 * (j + n1 * k)) + np.arange(3)] = 1
+    for k in range(n):
+        for j in range(n):
+            for dj, dk in ((0, 0), (1, 0), (0, 1), (1, 1)):
+                nid = n + n1 * ((j + dj) + n1 * (k + dk))
+                force[3 * nid] += traction * h * h / 4.0
+    return mask, force

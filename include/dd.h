@@ -172,6 +172,66 @@ dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
  */
 dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D);
 
+/* Structured hexahedral mesh of the box [0,lx] x [0,ly] x [0,lz] with
+ * nx x ny x nz trilinear elements and 2x2x2 Gauss points.
+ *   node (i,j,k)      id i + (nx+1)(j + (ny+1)k), DOF = 3 id + component (x,y,z)
+ *   element (ex,ey,ez) id ex + nx(ey + ny ez)
+ *   material point    8 element + Gauss point a + 2(b + 2c), abscissae -+1/sqrt(3)
+ *   weight w_e        (lx/nx)(ly/ny)(lz/nz)/8, the integration-point volume
+ * (the "volumes associated with the integration points" of Section 2). */
+typedef struct dd_mesh {
+  int32_t nx, ny, nz;
+  double lx, ly, lz;
+} dd_mesh;
+
+typedef struct dd_solve_opts {
+  int32_t max_iter;      /* 0 = 500 */
+  int32_t mode;          /* projection mode (dd_mode), default DD_EXACT_FP64 */
+  int32_t cg_max_iter;   /* 0 = 20000 */
+  int32_t reserved;
+  double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
+} dd_solve_opts;
+
+/* Results of dd_solve; every array is HOST memory provided by the caller and
+ * may be NULL when not wanted. */
+typedef struct dd_solve_result {
+  double* u;                /* [ndof] displacement of the last P_C */
+  int64_t* idx;             /* [n_mp] final association (original data indices) */
+  double* eps;              /* [n_mp][6] strain of the last P_C (raw Voigt) */
+  double* sig;              /* [n_mp][6] stress of the last P_C */
+  double* d_half;           /* [history_capacity] sum_e w_e dist(y_i, z_i) */
+  double* d_full;           /* [history_capacity] sum_e w_e dist(y_i, z_{i+1}) */
+  int64_t* changed;         /* [history_capacity] #associations changed by P_D */
+  int64_t* history;         /* [history_capacity+1][n_mp] idx_0 (init), idx_1, ... */
+  int32_t history_capacity; /* entries available in the four arrays above */
+  int32_t iterations;       /* out: DD iterations performed */
+  int32_t converged;        /* out: 1 if the association stopped changing */
+  int32_t reserved;
+  int64_t cg_iterations;    /* out: total CG iterations (both systems) */
+  double cg_max_residual;   /* out: largest final relative CG residual */
+  double elapsed_ms;        /* out: host wall time of the loop */
+} dd_solve_result;
+
+/*
+ * DD fixed-point loop (Section 2): starting from the association init_idx,
+ * repeat  y_i = P_C(z_i)  (eqs. "KuE", "KeS": K u = E, K eta = S with
+ * K = A_e{w B^T C B} factorised/prepared once, E = A_e{w B^T C eps*},
+ * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
+ * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
+ * exact projections).
+ *   mesh            structured box mesh (see dd_mesh)
+ *   dirichlet_mask  host uint8 [ndof]: 1 = homogeneous Dirichlet DOF (u = eta = 0)
+ *   nodal_force     host float64 [ndof]: consistent nodal forces f
+ *   init_idx        host int64 [n_mp]: initial association (e.g. random)
+ *   opts            NULL for defaults; result NULL or host arrays to fill
+ * Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED (no FP64 pack), DD_ERR_TOO_LARGE,
+ * DD_ERR_OOM, DD_ERR_DEVICE; DD_ERR_NOT_CONVERGED after max_iter (results are
+ * still written).  Synchronises hip_stream.
+ */
+dd_status dd_solve(const dd_dataset* ds, const dd_mesh* mesh, const uint8_t* dirichlet_mask,
+                   const double* nodal_force, const int64_t* init_idx, const dd_solve_opts* opts,
+                   dd_solve_result* result, void* hip_stream);
+
 /* Thread-local message for the calling thread's last non-OK status. */
 const char* dd_last_error(void);
 

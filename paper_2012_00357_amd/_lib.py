@@ -195,3 +195,71 @@ def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
 def dd_dataset_info(ds: Dataset):
     """dd_dataset_info: (number of points, device bytes held)."""
     return ds.info()
+
+
+class dd_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class dd_solve_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("cg_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double)]
+
+
+class dd_solve_result(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+                ("sig", ctypes.c_void_p), ("d_half", ctypes.c_void_p), ("d_full", ctypes.c_void_p),
+                ("changed", ctypes.c_void_p), ("history", ctypes.c_void_p),
+                ("history_capacity", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cg_iterations", ctypes.c_int64), ("cg_max_residual", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double)]
+
+
+_lib.dd_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_mesh), ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.POINTER(dd_solve_opts),
+                          ctypes.POINTER(dd_solve_result), ctypes.c_void_p]
+_lib.dd_solve.restype = ctypes.c_int
+
+
+def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
+             max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
+             cg_max_iter: int = 0, stream=None):
+    """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
+
+    Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
+    (when requested), iterations, converged, cg_iterations, cg_max_residual,
+    elapsed_ms.  Not converging within max_iter is reported, not raised."""
+    nx, ny, nz = mesh[:3]
+    lx, ly, lz = (mesh[3:] if len(mesh) > 3 else (1.0, 1.0, 1.0))
+    m = dd_mesh(nx, ny, nz, lx, ly, lz)
+    n_dof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+    n_mp = 8 * nx * ny * nz
+    mask = np.ascontiguousarray(np.asarray(dirichlet_mask, dtype=np.uint8).reshape(n_dof))
+    force = np.ascontiguousarray(np.asarray(nodal_force, dtype=np.float64).reshape(n_dof))
+    init = np.ascontiguousarray(np.asarray(init_idx, dtype=np.int64).reshape(n_mp))
+    cap = max_iter
+    out = {"u": np.zeros(n_dof), "idx": np.zeros(n_mp, np.int64), "eps": np.zeros((n_mp, 6)),
+           "sig": np.zeros((n_mp, 6)), "d_half": np.zeros(cap), "d_full": np.zeros(cap),
+           "changed": np.zeros(cap, np.int64)}
+    hist = np.zeros((cap + 1, n_mp), np.int64) if history else None
+    res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
+                          out["sig"].ctypes.data, out["d_half"].ctypes.data,
+                          out["d_full"].ctypes.data, out["changed"].ctypes.data,
+                          hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0)
+    opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
+                         cg_max_iter, 0, cg_tol)
+    st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
+                       init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
+    if st not in (DD_OK, 5):
+        raise DDError(st, "dd_solve", dd_last_error())
+    it = res.iterations
+    for k in ("d_half", "d_full", "changed"):
+        out[k] = out[k][:it]
+    if history:
+        out["history"] = hist[:it + 1]
+    out.update(iterations=it, converged=bool(res.converged), cg_iterations=res.cg_iterations,
+               cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
+    return out

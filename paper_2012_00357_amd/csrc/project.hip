@@ -4,6 +4,7 @@
 
 #include "pack16.h"
 #include "scan.h"
+#include "solve.h"
 
 namespace dd {
 
@@ -99,16 +100,14 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
 
 }  // namespace dd
 
-extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
-                                const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
-                                int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream) {
-  using namespace dd;
-  if (!ds) return set_error(DD_ERR_ARG, "dataset is NULL");
+namespace dd {
+
+dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
+                       const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                       int64_t* idx_out_dev, double* dist_out_dev, hipStream_t st) {
   if (m < 0 || m > 0x7FFFFFFFll) return set_error(DD_ERR_ARG, "m must be in [0, 2^31-1]");
   if (m == 0) return DD_OK;
   if (!states_dev || !idx_out_dev) return set_error(DD_ERR_ARG, "NULL states or idx_out");
-  const Dataset& D = ds->d;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int mode = opts ? opts->mode : DD_EXACT_FP64;
   const int splits = opts ? opts->splits : 0;
   if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
@@ -144,7 +143,7 @@ extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, 
   int* counters = nullptr;   // [0] fb1, [1] fb2, [2..3] candidates (u64), [4..5] slow tiles (u64)
   DD_TRY(sc.get(counters, 6));
   DD_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int), st));
-  DD_TRY(prepare_queries(D, states_dev, m, warm_start_idx_dev, Q, st));
+  DD_TRY(prepare_queries(D, states_dev, whitened, m, warm_start_idx_dev, Q, st));
   Outputs out{idx_out_dev, dist_out_dev};
   QueryList all{nullptr, nullptr, m};
   int64_t n_fallback = 0;
@@ -239,4 +238,22 @@ extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, 
     opts->stats->slow_tiles = n_items_host;
   }
   return DD_OK;
+}
+
+dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
+                           const int64_t* warm_dev, int mode, int64_t* idx_out, double* dist_out,
+                           hipStream_t st) {
+  dd_project_opts o{};
+  o.mode = mode;
+  return project_impl(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, st);
+}
+
+}  // namespace dd
+
+extern "C" dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
+                                const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                                int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream) {
+  if (!ds) return dd::set_error(DD_ERR_ARG, "dataset is NULL");
+  return dd::project_impl(ds->d, states_dev, false, m, warm_start_idx_dev, opts, idx_out_dev,
+                          dist_out_dev, static_cast<hipStream_t>(hip_stream));
 }

@@ -35,8 +35,9 @@ struct Outputs {
   double* dist = nullptr;       // [m] 1/2 d^2 or nullptr
 };
 
-dd_status prepare_queries(const Dataset& D, const double* states, int64_t m, const int64_t* warm,
-                          QueryPrep& Q, hipStream_t st);
+// Whiten m states (or take them as already whitened), |q|^2, warm-start bounds.
+dd_status prepare_queries(const Dataset& D, const double* states, bool whitened, int64_t m,
+                          const int64_t* warm, QueryPrep& Q, hipStream_t st);
 
 // FP64 MFMA scan (expanded form) over the list; fills cb (P = 4, d-space bounds).
 dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len,

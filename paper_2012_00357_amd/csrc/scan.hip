@@ -97,12 +97,13 @@ __global__ void prep_kernel(const double* __restrict__ states, int64_t m, Mats M
   u32[i] = ub32;
 }
 
-dd_status prepare_queries(const Dataset& D, const double* states, int64_t m, const int64_t* warm,
-                          QueryPrep& Q, hipStream_t st) {
+dd_status prepare_queries(const Dataset& D, const double* states, bool whitened, int64_t m,
+                          const int64_t* warm, QueryPrep& Q, hipStream_t st) {
   Mats M;
   for (int i = 0; i < 36; ++i) {
-    M.F[i] = D.F[i];
-    M.G[i] = D.G[i];
+    const double id = (i % 7 == 0) ? 1.0 : 0.0;   // identity: states already whitened
+    M.F[i] = whitened ? id : D.F[i];
+    M.G[i] = whitened ? id : D.G[i];
   }
   hipLaunchKernelGGL(prep_kernel, dim3(grid1(m)), dim3(256), 0, st, states, m, M, warm, D.N,
                      D.iperm.as<uint32_t>(), D.w64.as<double>(), D.w32.as<float>(), Q.qw, Q.qn2,

@@ -1,0 +1,45 @@
+// DD fixed-point solver (host side) and the whitened-query projection it uses.
+#pragma once
+#include "dd_internal.h"
+
+namespace dd {
+
+// Structured hexahedral mesh of the box [0,lx] x [0,ly] x [0,lz]: node (i,j,k)
+// has id i + (nx+1)(j + (ny+1)k), DOF 3 node + component; element (ex,ey,ez)
+// has id ex + nx(ey + ny ez); material point 8 element + Gauss point, Gauss
+// point a + 2(b + 2c) at -+1/sqrt(3).
+struct FEMesh {
+  int nx = 0, ny = 0, nz = 0;
+  double hx = 0, hy = 0, hz = 0, w = 0;
+  int64_t n_nodes = 0, n_dof = 0, n_el = 0, n_mp = 0;
+  double B[8][6 * 24];   // strain-displacement operators (Voigt, engineering shear)
+  void init(const dd_mesh& m);
+  int64_t node(int i, int j, int k) const;
+};
+
+// P_D of whitened states (already in the dataset's coordinates).
+dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
+                           const int64_t* warm_dev, int mode, int64_t* idx_out, double* dist_out,
+                           hipStream_t st);
+
+class DDSolver {
+ public:
+  dd_status setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* mask, const double* force,
+                  const dd_solve_opts* opts, hipStream_t st);
+  dd_status set_assignment(const int64_t* idx_host);
+  dd_status constraint_projection();
+  dd_status run(int max_iter, dd_solve_result* res);
+
+  FEMesh M;
+  const Dataset* ds = nullptr;
+  hipStream_t st = nullptr;
+  int mode = DD_EXACT_FP64;
+  double cg_tol = 1e-13;
+  int cg_max_iter = 20000;
+  int64_t nnz = 0;
+  double L[36], Lt[36];
+  DevBuf d_rowptr, d_col, d_val, d_dinv, d_mask, d_f, d_b, d_x, d_work;
+  DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
+};
+
+}  // namespace dd

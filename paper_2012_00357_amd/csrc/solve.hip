@@ -1,0 +1,648 @@
+// dd_solve: the data-driven fixed-point loop z_{i+1} = P_D(P_C(z_i)) of
+// Section 2 on one GPU, for a structured hexahedral mesh of a box.
+//
+// States are kept in whitened coordinates w = (F eps, G sig) with F = L^T,
+// G = L^-1 (C = L L^T), the coordinates in which P_D is evaluated.  P_C
+// (eqs. "KuE", "KeS") needs C eps* = L w_eps* and sig* = L w_sig*, and returns
+// eps = B u, sig = sig* + C B eta, i.e. w_eps = L^T B u, w_sig = w_sig* + L^T B eta.
+//
+// K = A_e{ w B^T C B } is assembled once (host, CSR over all DOFs with identity
+// rows at Dirichlet DOFs) and both systems K u = E, K eta = S are solved
+// together by a Jacobi-preconditioned conjugate-gradient kernel running in one
+// workgroup, warm-started from the previous iterate.  All reductions run in a
+// fixed order, so a solve is bitwise reproducible.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pack16.h"
+#include "scan.h"
+#include "solve.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Host finite-element operators of the structured mesh
+// ---------------------------------------------------------------------------
+static const double kGauss = 0.57735026918962576451;   // 1/sqrt(3)
+
+void FEMesh::init(const dd_mesh& m) {
+  nx = m.nx;
+  ny = m.ny;
+  nz = m.nz;
+  hx = m.lx / nx;
+  hy = m.ly / ny;
+  hz = m.lz / nz;
+  n_nodes = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  n_dof = 3 * n_nodes;
+  n_el = (int64_t)nx * ny * nz;
+  n_mp = 8 * n_el;
+  w = (hx / 2) * (hy / 2) * (hz / 2);
+  // trilinear shape-function gradients at the 2x2x2 Gauss points
+  for (int g = 0; g < 8; ++g) {
+    double xi[3] = {((g & 1) ? 1 : -1) * kGauss, (((g >> 1) & 1) ? 1 : -1) * kGauss,
+                    (((g >> 2) & 1) ? 1 : -1) * kGauss};
+    for (int i = 0; i < 6 * 24; ++i) B[g][i] = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      double s[3] = {(a & 1) ? 1.0 : -1.0, ((a >> 1) & 1) ? 1.0 : -1.0, ((a >> 2) & 1) ? 1.0 : -1.0};
+      double f[3] = {1 + s[0] * xi[0], 1 + s[1] * xi[1], 1 + s[2] * xi[2]};
+      double dx = s[0] * f[1] * f[2] / 8.0 * (2.0 / hx);
+      double dy = f[0] * s[1] * f[2] / 8.0 * (2.0 / hy);
+      double dz = f[0] * f[1] * s[2] / 8.0 * (2.0 / hz);
+      int c = 3 * a;
+      B[g][0 * 24 + c + 0] = dx;
+      B[g][1 * 24 + c + 1] = dy;
+      B[g][2 * 24 + c + 2] = dz;
+      B[g][3 * 24 + c + 1] = dz;   // gamma_23
+      B[g][3 * 24 + c + 2] = dy;
+      B[g][4 * 24 + c + 0] = dz;   // gamma_13
+      B[g][4 * 24 + c + 2] = dx;
+      B[g][5 * 24 + c + 0] = dy;   // gamma_12
+      B[g][5 * 24 + c + 1] = dx;
+    }
+  }
+}
+
+int64_t FEMesh::node(int i, int j, int k) const {
+  return i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+}
+
+// Element stiffness Ke = w sum_g B_g^T C B_g (24 x 24).
+static void element_stiffness(const FEMesh& M, const double* C, double* Ke) {
+  std::fill(Ke, Ke + 24 * 24, 0.0);
+  for (int g = 0; g < 8; ++g) {
+    const double* B = M.B[g];
+    double CB[6 * 24];
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 24; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += C[6 * r + k] * B[24 * k + c];
+        CB[24 * r + c] = s;
+      }
+    for (int i = 0; i < 24; ++i)
+      for (int j = 0; j < 24; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += B[24 * k + i] * CB[24 * k + j];
+        Ke[24 * i + j] += M.w * s;
+      }
+  }
+}
+
+// CSR of K over all DOFs; rows and columns of Dirichlet DOFs are replaced by the
+// identity so that the systems can be solved on full vectors.
+static void assemble_csr(const FEMesh& M, const double* C, const uint8_t* mask,
+                         std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                         std::vector<double>& val, std::vector<double>& dinv) {
+  double Ke[24 * 24];
+  element_stiffness(M, C, Ke);
+  const int64_t nd = M.n_dof;
+  rowptr.assign(nd + 1, 0);
+  col.clear();
+  val.clear();
+  dinv.assign(nd, 0.0);
+  std::vector<double> rowv;
+  std::vector<int32_t> rowc;
+  for (int k = 0; k <= M.nz; ++k)
+    for (int j = 0; j <= M.ny; ++j)
+      for (int i = 0; i <= M.nx; ++i) {
+        const int64_t nd0 = M.node(i, j, k);
+        for (int comp = 0; comp < 3; ++comp) {
+          const int64_t row = 3 * nd0 + comp;
+          // neighbouring nodes in index order; values summed over the elements
+          // sharing both nodes, in element order
+          std::vector<std::pair<int64_t, double>> entries;
+          if (mask[row]) {
+            entries.push_back({row, 1.0});
+          } else {
+            for (int dk = -1; dk <= 1; ++dk)
+              for (int dj = -1; dj <= 1; ++dj)
+                for (int di = -1; di <= 1; ++di) {
+                  int ii = i + di, jj = j + dj, kk = k + dk;
+                  if (ii < 0 || jj < 0 || kk < 0 || ii > M.nx || jj > M.ny || kk > M.nz) continue;
+                  const int64_t nb = M.node(ii, jj, kk);
+                  for (int c2 = 0; c2 < 3; ++c2) {
+                    const int64_t cdof = 3 * nb + c2;
+                    if (mask[cdof]) continue;
+                    double s = 0.0;
+                    bool any = false;
+                    for (int ez = std::max(k, kk) - 1; ez <= std::min(k, kk); ++ez)
+                      for (int ey = std::max(j, jj) - 1; ey <= std::min(j, jj); ++ey)
+                        for (int ex = std::max(i, ii) - 1; ex <= std::min(i, ii); ++ex) {
+                          if (ex < 0 || ey < 0 || ez < 0 || ex >= M.nx || ey >= M.ny || ez >= M.nz)
+                            continue;
+                          int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
+                          int b = (ii - ex) + 2 * (jj - ey) + 4 * (kk - ez);
+                          s += Ke[24 * (3 * a + comp) + 3 * b + c2];
+                          any = true;
+                        }
+                    if (any) entries.push_back({cdof, s});
+                  }
+                }
+            std::sort(entries.begin(), entries.end(),
+                      [](const std::pair<int64_t, double>& x, const std::pair<int64_t, double>& y) {
+                        return x.first < y.first;
+                      });
+          }
+          for (auto& e : entries) {
+            col.push_back((int32_t)e.first);
+            val.push_back(e.second);
+            if (e.first == row) dinv[row] = 1.0 / e.second;
+          }
+          rowptr[row + 1] = (int32_t)col.size();
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Device kernels
+// ---------------------------------------------------------------------------
+struct Mat6 {
+  double a[36];
+};
+struct BOps {
+  double B[8][6 * 24];
+};
+
+__device__ inline int64_t dnode(int nx, int ny, int i, int j, int k) {
+  return i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k);
+}
+
+// Per material point: the assigned data point's whitened state z_w (from the
+// sorted FP64 pack), and (C eps*, sig*) = (L w_eps*, L w_sig*).
+__global__ void gather_z_kernel(const int64_t* __restrict__ idx, int64_t n_mp, int64_t N,
+                                const uint32_t* __restrict__ iperm, const double* __restrict__ w64,
+                                Mat6 L, double* __restrict__ zw, double* __restrict__ zc,
+                                int* __restrict__ bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_mp) return;
+  int64_t j = idx[e];
+  if (j < 0 || j >= N) {   // a non-finite admissible state upstream: report, stay in bounds
+    atomicOr(bad, 1);
+    j = 0;
+  }
+  const int64_t p = iperm[j];
+  double z[12];
+  for (int k = 0; k < 12; ++k) {
+    z[k] = w64[12 * p + k];
+    zw[12 * e + k] = z[k];
+  }
+  for (int r = 0; r < 6; ++r) {
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      a = fma(L.a[6 * r + c], z[c], a);
+      b = fma(L.a[6 * r + c], z[6 + c], b);
+    }
+    zc[12 * e + r] = a;       // C eps*
+    zc[12 * e + 6 + r] = b;   // sig*
+  }
+}
+
+// RHS by gathering, per DOF, the contributions of its (<= 8) elements and their
+// Gauss points in a fixed order:  E = A{ w B^T C eps* },  S = f - A{ w B^T sig* }.
+// Dirichlet DOFs get 0.
+__global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
+                                    const double* __restrict__ zc, const uint8_t* __restrict__ mask,
+                                    const double* __restrict__ f, double* __restrict__ E,
+                                    double* __restrict__ S) {
+  const int64_t dof = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_dof = 3 * (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  if (dof >= n_dof) return;
+  if (mask[dof]) {
+    E[dof] = 0.0;
+    S[dof] = 0.0;
+    return;
+  }
+  const int comp = (int)(dof % 3);
+  const int64_t nd = dof / 3;
+  const int i = (int)(nd % (nx + 1));
+  const int j = (int)((nd / (nx + 1)) % (ny + 1));
+  const int k = (int)(nd / ((int64_t)(nx + 1) * (ny + 1)));
+  double se = 0.0, ss = 0.0;
+  for (int ez = k - 1; ez <= k; ++ez)
+    for (int ey = j - 1; ey <= j; ++ey)
+      for (int ex = i - 1; ex <= i; ++ex) {
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= nx || ey >= ny || ez >= nz) continue;
+        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
+        const int64_t el = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+        for (int g = 0; g < 8; ++g) {
+          const double* z = zc + 12 * (8 * el + g);
+          for (int r = 0; r < 6; ++r) {
+            const double bv = Bo.B[g][24 * r + 3 * a + comp];
+            se = fma(bv, z[r], se);
+            ss = fma(bv, z[6 + r], ss);
+          }
+        }
+      }
+  E[dof] = w * se;
+  S[dof] = f[dof] - w * ss;
+}
+
+constexpr int kCgThreads = 1024;
+
+__device__ inline void block_sum2(double& a, double& b, double* red) {
+  const int t = threadIdx.x;
+  red[t] = a;
+  red[kCgThreads + t] = b;
+  __syncthreads();
+  for (int off = kCgThreads / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      red[t] += red[t + off];
+      red[kCgThreads + t] += red[kCgThreads + t + off];
+    }
+    __syncthreads();
+  }
+  a = red[0];
+  b = red[kCgThreads];
+  __syncthreads();
+}
+
+// Both systems K x0 = b0 (u) and K x1 = b1 (eta) by Jacobi-preconditioned CG in
+// one workgroup.  x holds the initial guesses on entry.  Vectors are [2][n].
+// out_iters[0..1] = iterations per system, out_res[0..1] = final relative residuals.
+__global__ __launch_bounds__(kCgThreads) void cg2_kernel(
+    int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ dinv, const double* __restrict__ b,
+    double* __restrict__ x, double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
+    double* __restrict__ q, double tol, int max_iter, int* __restrict__ out_iters,
+    double* __restrict__ out_res) {
+  __shared__ double red[2 * kCgThreads];
+  const int t = threadIdx.x;
+  // r = b - K x, z = D^-1 r, p = z
+  double bb0 = 0, bb1 = 0, rz0 = 0, rz1 = 0;
+  for (int64_t i = t; i < n; i += kCgThreads) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const double v = val[e];
+      s0 = fma(v, x[col[e]], s0);
+      s1 = fma(v, x[n + col[e]], s1);
+    }
+    const double r0 = b[i] - s0, r1 = b[n + i] - s1;
+    r[i] = r0;
+    r[n + i] = r1;
+    const double z0 = dinv[i] * r0, z1 = dinv[i] * r1;
+    z[i] = z0;
+    z[n + i] = z1;
+    p[i] = z0;
+    p[n + i] = z1;
+    bb0 = fma(b[i], b[i], bb0);
+    bb1 = fma(b[n + i], b[n + i], bb1);
+    rz0 = fma(r0, z0, rz0);
+    rz1 = fma(r1, z1, rz1);
+  }
+  block_sum2(bb0, bb1, red);
+  block_sum2(rz0, rz1, red);
+  double rr0 = 0, rr1 = 0;
+  for (int64_t i = t; i < n; i += kCgThreads) {
+    rr0 = fma(r[i], r[i], rr0);
+    rr1 = fma(r[n + i], r[n + i], rr1);
+  }
+  block_sum2(rr0, rr1, red);
+  const double lim0 = tol * tol * bb0, lim1 = tol * tol * bb1;
+  bool act0 = rr0 > lim0, act1 = rr1 > lim1;
+  int it0 = 0, it1 = 0;
+  for (int it = 0; it < max_iter && (act0 || act1); ++it) {
+    __syncthreads();
+    // q = K p, pq = p.q
+    double pq0 = 0.0, pq1 = 0.0;
+    for (int64_t i = t; i < n; i += kCgThreads) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const double v = val[e];
+        s0 = fma(v, p[col[e]], s0);
+        s1 = fma(v, p[n + col[e]], s1);
+      }
+      q[i] = s0;
+      q[n + i] = s1;
+      pq0 = fma(p[i], s0, pq0);
+      pq1 = fma(p[n + i], s1, pq1);
+    }
+    block_sum2(pq0, pq1, red);
+    const double a0 = act0 ? rz0 / pq0 : 0.0, a1 = act1 ? rz1 / pq1 : 0.0;
+    double nrz0 = 0.0, nrz1 = 0.0, nrr0 = 0.0, nrr1 = 0.0;
+    for (int64_t i = t; i < n; i += kCgThreads) {
+      x[i] = fma(a0, p[i], x[i]);
+      x[n + i] = fma(a1, p[n + i], x[n + i]);
+      const double r0 = fma(-a0, q[i], r[i]), r1 = fma(-a1, q[n + i], r[n + i]);
+      r[i] = r0;
+      r[n + i] = r1;
+      const double z0 = dinv[i] * r0, z1 = dinv[i] * r1;
+      z[i] = z0;
+      z[n + i] = z1;
+      nrz0 = fma(r0, z0, nrz0);
+      nrz1 = fma(r1, z1, nrz1);
+      nrr0 = fma(r0, r0, nrr0);
+      nrr1 = fma(r1, r1, nrr1);
+    }
+    block_sum2(nrz0, nrz1, red);
+    block_sum2(nrr0, nrr1, red);
+    const double be0 = act0 ? nrz0 / rz0 : 0.0, be1 = act1 ? nrz1 / rz1 : 0.0;
+    for (int64_t i = t; i < n; i += kCgThreads) {
+      if (act0) p[i] = fma(be0, p[i], z[i]);
+      if (act1) p[n + i] = fma(be1, p[n + i], z[n + i]);
+    }
+    if (act0) {
+      rz0 = nrz0;
+      rr0 = nrr0;
+      ++it0;
+      act0 = rr0 > lim0;
+    }
+    if (act1) {
+      rz1 = nrz1;
+      rr1 = nrr1;
+      ++it1;
+      act1 = rr1 > lim1;
+    }
+  }
+  if (t == 0) {
+    out_iters[0] = it0;
+    out_iters[1] = it1;
+    out_res[0] = bb0 > 0 ? sqrt(rr0 / bb0) : 0.0;
+    out_res[1] = bb1 > 0 ? sqrt(rr1 / bb1) : 0.0;
+  }
+}
+
+// Admissible state at every material point from u, eta (whitened):
+//   w_eps = L^T B u,  w_sig = w_sig* + L^T B eta;  optionally raw eps = B u,
+//   sig = sig* + C B eta with C B eta = L (L^T B eta).
+__global__ void recover_kernel(int nx, int ny, int nz, BOps Bo, Mat6 LT, Mat6 L,
+                               const double* __restrict__ x /*[2][n_dof]*/, int64_t n_dof,
+                               const double* __restrict__ zw, const double* __restrict__ zc,
+                               double* __restrict__ yw, double* __restrict__ eps_raw,
+                               double* __restrict__ sig_raw) {
+  const int64_t mp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_mp = 8 * (int64_t)nx * ny * nz;
+  if (mp >= n_mp) return;
+  const int g = (int)(mp % 8);
+  const int64_t el = mp / 8;
+  const int ex = (int)(el % nx), ey = (int)((el / nx) % ny), ez = (int)(el / ((int64_t)nx * ny));
+  double eu[6] = {0, 0, 0, 0, 0, 0}, ee[6] = {0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 8; ++a) {
+    const int64_t nd = dnode(nx, ny, ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
+    for (int c = 0; c < 3; ++c) {
+      const double uv = x[3 * nd + c], ev = x[n_dof + 3 * nd + c];
+      for (int r = 0; r < 6; ++r) {
+        const double bv = Bo.B[g][24 * r + 3 * a + c];
+        eu[r] = fma(bv, uv, eu[r]);
+        ee[r] = fma(bv, ev, ee[r]);
+      }
+    }
+  }
+  double we[6], ws[6];
+  for (int r = 0; r < 6; ++r) {
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      a = fma(LT.a[6 * r + c], eu[c], a);
+      b = fma(LT.a[6 * r + c], ee[c], b);
+    }
+    we[r] = a;
+    ws[r] = b;
+  }
+  for (int r = 0; r < 6; ++r) {
+    yw[12 * mp + r] = we[r];
+    yw[12 * mp + 6 + r] = zw[12 * mp + 6 + r] + ws[r];
+  }
+  if (eps_raw) {
+    for (int r = 0; r < 6; ++r) {
+      double cb = 0.0;
+      for (int c = 0; c < 6; ++c) cb = fma(L.a[6 * r + c], ws[c], cb);
+      eps_raw[6 * mp + r] = eu[r];
+      sig_raw[6 * mp + r] = zc[12 * mp + 6 + r] + cb;
+    }
+  }
+}
+
+// Deterministic per-iteration scalars over the material points (one block):
+//   out[0] = sum_e w 1/2 |y_e - z_e|^2 (D_half), out[1] = sum_e w dist_e (D_full),
+//   out[2] = #{idx_new != idx_old}.
+__global__ __launch_bounds__(1024) void iter_scalars_kernel(
+    int64_t n_mp, double w, const double* __restrict__ yw, const double* __restrict__ zw,
+    const double* __restrict__ dist, const int64_t* __restrict__ idx_new,
+    const int64_t* __restrict__ idx_old, double* __restrict__ out) {
+  __shared__ double red[3 * 1024];
+  const int t = threadIdx.x;
+  double dh = 0.0, df = 0.0, ch = 0.0;
+  for (int64_t e = t; e < n_mp; e += 1024) {
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      const double d = yw[12 * e + k] - zw[12 * e + k];
+      s = fma(d, d, s);
+    }
+    dh += 0.5 * s;
+    df += dist[e];
+    ch += (idx_new[e] != idx_old[e]) ? 1.0 : 0.0;
+  }
+  red[t] = dh;
+  red[1024 + t] = df;
+  red[2048 + t] = ch;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) {
+      red[t] += red[t + off];
+      red[1024 + t] += red[1024 + t + off];
+      red[2048 + t] += red[2048 + t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = w * red[0];
+    out[1] = w * red[1024];
+    out[2] = red[2048];
+  }
+}
+
+static unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ---------------------------------------------------------------------------
+// Solver object
+// ---------------------------------------------------------------------------
+dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* mask,
+                          const double* force, const dd_solve_opts* opts, hipStream_t st) {
+  if (!(D.packs & DD_PACK_FP64))
+    return set_error(DD_ERR_UNSUPPORTED, "dd_solve needs the dataset's FP64 pack");
+  if (mesh.nx < 1 || mesh.ny < 1 || mesh.nz < 1 || !(mesh.lx > 0) || !(mesh.ly > 0) ||
+      !(mesh.lz > 0))
+    return set_error(DD_ERR_ARG, "mesh needs nx, ny, nz >= 1 and positive edge lengths");
+  if ((int64_t)mesh.nx * mesh.ny * mesh.nz > (1 << 24))
+    return set_error(DD_ERR_TOO_LARGE, "mesh too large");
+  ds = &D;
+  M.init(mesh);
+  this->st = st;
+  mode = opts ? opts->mode : DD_EXACT_FP64;
+  cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
+  cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
+  // Cholesky factor of the metric for the whitened/raw conversions
+  double Lm[36], LT[36];
+  cholesky6(D.C, Lm);
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) LT[6 * r + c] = Lm[6 * c + r];
+  std::memcpy(L, Lm, sizeof(L));
+  std::memcpy(Lt, LT, sizeof(Lt));
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val, dinv;
+  assemble_csr(M, D.C, mask, rowptr, col, val, dinv);
+  nnz = (int64_t)col.size();
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  DD_TRY(d_rowptr.alloc(sizeof(int32_t) * (nd + 1)));
+  DD_TRY(d_col.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  DD_TRY(d_val.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)));
+  DD_TRY(d_dinv.alloc(sizeof(double) * nd));
+  DD_TRY(d_mask.alloc(nd));
+  DD_TRY(d_f.alloc(sizeof(double) * nd));
+  DD_TRY(d_b.alloc(sizeof(double) * 2 * nd));
+  DD_TRY(d_x.alloc(sizeof(double) * 2 * nd));
+  DD_TRY(d_work.alloc(sizeof(double) * 8 * nd));
+  DD_TRY(d_idx.alloc(sizeof(int64_t) * nm));
+  DD_TRY(d_idx_new.alloc(sizeof(int64_t) * nm));
+  DD_TRY(d_dist.alloc(sizeof(double) * nm));
+  DD_TRY(d_zw.alloc(sizeof(double) * 12 * nm));
+  DD_TRY(d_zc.alloc(sizeof(double) * 12 * nm));
+  DD_TRY(d_yw.alloc(sizeof(double) * 12 * nm));
+  DD_TRY(d_scal.alloc(sizeof(double) * 4));
+  DD_TRY(d_cgstat.alloc(64));
+  DD_HIP(hipMemcpyAsync(d_rowptr.p, rowptr.data(), sizeof(int32_t) * (nd + 1), hipMemcpyHostToDevice, st));
+  if (nnz) {
+    DD_HIP(hipMemcpyAsync(d_col.p, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+    DD_HIP(hipMemcpyAsync(d_val.p, val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  }
+  DD_HIP(hipMemcpyAsync(d_dinv.p, dinv.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  DD_HIP(hipMemcpyAsync(d_mask.p, mask, nd, hipMemcpyHostToDevice, st));
+  DD_HIP(hipMemcpyAsync(d_f.p, force, sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  DD_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double) * 2 * nd, st));
+  DD_HIP(hipMemsetAsync(d_cgstat.p, 0, 64, st));
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+dd_status DDSolver::set_assignment(const int64_t* idx_host) {
+  const int64_t nm = M.n_mp;
+  for (int64_t e = 0; e < nm; ++e)
+    if (idx_host[e] < 0 || idx_host[e] >= ds->N) return set_error(DD_ERR_ARG, "init_idx out of range");
+  DD_HIP(hipMemcpyAsync(d_idx.p, idx_host, sizeof(int64_t) * nm, hipMemcpyHostToDevice, st));
+  return DD_OK;
+}
+
+dd_status DDSolver::constraint_projection() {
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  Mat6 Lm, LTm;
+  std::memcpy(Lm.a, L, sizeof(L));
+  std::memcpy(LTm.a, Lt, sizeof(Lt));
+  BOps Bo;
+  std::memcpy(Bo.B, M.B, sizeof(Bo.B));
+  hipLaunchKernelGGL(gather_z_kernel, dim3(g256(nm)), dim3(256), 0, st, d_idx.as<int64_t>(), nm,
+                     ds->N, ds->iperm.as<uint32_t>(), ds->w64.as<double>(), Lm, d_zw.as<double>(),
+                     d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
+  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
+                     Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
+                     d_b.as<double>(), d_b.as<double>() + nd);
+  double* wk = d_work.as<double>();
+  hipLaunchKernelGGL(cg2_kernel, dim3(1), dim3(kCgThreads), 0, st, nd, d_rowptr.as<int32_t>(),
+                     d_col.as<int32_t>(), d_val.as<double>(), d_dinv.as<double>(), d_b.as<double>(),
+                     d_x.as<double>(), wk, wk + 2 * nd, wk + 4 * nd, wk + 6 * nd, cg_tol, cg_max_iter,
+                     d_cgstat.as<int>(), reinterpret_cast<double*>(d_cgstat.as<char>() + 16));
+  hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
+                     d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),
+                     (double*)nullptr, (double*)nullptr);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
+  const int64_t nm = M.n_mp, nd = M.n_dof;
+  auto t0 = std::chrono::steady_clock::now();
+  int it = 0;
+  bool converged = false;
+  int64_t cg_total = 0;
+  double cg_res_max = 0.0;
+  if (res && res->history) {
+    DD_HIP(hipMemcpyAsync(res->history, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
+  }
+  for (it = 1; it <= max_iter; ++it) {
+    DD_TRY(constraint_projection());
+    DD_TRY(project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode,
+                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st));
+    hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
+                       d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
+                       d_idx.as<int64_t>(), d_scal.as<double>());
+    DD_HIP(hipGetLastError());
+    double sc[3];
+    char cgs[64];
+    DD_HIP(hipMemcpyAsync(sc, d_scal.p, sizeof(sc), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(cgs, d_cgstat.p, 40, hipMemcpyDeviceToHost, st));
+    if (res && res->history && it <= res->history_capacity)
+      DD_HIP(hipMemcpyAsync(res->history + (int64_t)it * nm, d_idx_new.p, sizeof(int64_t) * nm,
+                            hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    int cg_it[2];
+    double cg_res[2];
+    int bad = 0;
+    std::memcpy(cg_it, cgs, sizeof(cg_it));
+    std::memcpy(cg_res, cgs + 16, sizeof(cg_res));
+    std::memcpy(&bad, cgs + 32, sizeof(bad));
+    if (bad) return set_error(DD_ERR_DEVICE, "dd_solve: the admissible state became non-finite");
+    cg_total += cg_it[0] + cg_it[1];
+    cg_res_max = std::max(cg_res_max, std::max(cg_res[0], cg_res[1]));
+    if (res) {
+      if (res->d_half && it <= res->history_capacity) res->d_half[it - 1] = sc[0];
+      if (res->d_full && it <= res->history_capacity) res->d_full[it - 1] = sc[1];
+      if (res->changed && it <= res->history_capacity) res->changed[it - 1] = (int64_t)sc[2];
+    }
+    // the new association becomes the current one
+    std::swap(d_idx.p, d_idx_new.p);
+    if (sc[2] == 0.0) {
+      converged = true;
+      break;
+    }
+  }
+  if (it > max_iter) it = max_iter;
+  if (res) {
+    res->iterations = it;
+    res->converged = converged ? 1 : 0;
+    res->cg_iterations = cg_total;
+    res->cg_max_residual = cg_res_max;
+    if (res->u) DD_HIP(hipMemcpyAsync(res->u, d_x.p, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
+    if (res->idx) DD_HIP(hipMemcpyAsync(res->idx, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
+    if (res->eps || res->sig) {
+      // raw admissible state of the last P_C (recomputed from u, eta and z*)
+      DevBuf er, sr;
+      DD_TRY(er.alloc(sizeof(double) * 6 * nm));
+      DD_TRY(sr.alloc(sizeof(double) * 6 * nm));
+      Mat6 Lm, LTm;
+      std::memcpy(Lm.a, L, sizeof(L));
+      std::memcpy(LTm.a, Lt, sizeof(Lt));
+      BOps Bo;
+      std::memcpy(Bo.B, M.B, sizeof(Bo.B));
+      // z of the last P_C is the association before the final swap when not
+      // converged; at convergence both coincide.  Recompute from the stored zc.
+      hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm,
+                         Lm, d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(),
+                         d_yw.as<double>(), er.as<double>(), sr.as<double>());
+      DD_HIP(hipGetLastError());
+      if (res->eps) DD_HIP(hipMemcpyAsync(res->eps, er.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
+      if (res->sig) DD_HIP(hipMemcpyAsync(res->sig, sr.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
+      DD_HIP(hipStreamSynchronize(st));
+    }
+    DD_HIP(hipStreamSynchronize(st));
+    res->elapsed_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return converged ? DD_OK : set_error(DD_ERR_NOT_CONVERGED, "dd_solve reached max_iter");
+}
+
+}  // namespace dd
+
+extern "C" dd_status dd_solve(const dd_dataset* ds, const dd_mesh* mesh,
+                              const uint8_t* dirichlet_mask, const double* nodal_force,
+                              const int64_t* init_idx, const dd_solve_opts* opts,
+                              dd_solve_result* result, void* hip_stream) {
+  using namespace dd;
+  if (!ds || !mesh || !dirichlet_mask || !nodal_force || !init_idx)
+    return set_error(DD_ERR_ARG, "dd_solve: NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  DDSolver S;
+  DD_TRY(S.setup(ds->d, *mesh, dirichlet_mask, nodal_force, opts, st));
+  DD_TRY(S.set_assignment(init_idx));
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 500;
+  return S.run(max_iter, result);
+}

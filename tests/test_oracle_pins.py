@@ -339,3 +339,13 @@ def test_dd_planted_fe_solution_clamped(C0):
     assert r.converged and r.iterations == 1
     np.testing.assert_allclose(r.u, u_fe, rtol=1e-10, atol=1e-16)
     assert r.d_full[0] <= 1e-20
+
+
+def test_input_bc_matches_oracle_mesh():
+    """The benchmark's boundary conditions describe the same problem as the
+    oracle's mesh helpers (clamped x = 0, traction on x = 1)."""
+    for n in (1, 3, 8):
+        mask, f = ddsynth.box_bc(n, 100.0)
+        m = fe.Mesh(n)
+        assert np.array_equal(mask.astype(bool), m.clamp_mask())
+        np.testing.assert_allclose(f, m.traction_x1(100.0), rtol=1e-15, atol=0)
