@@ -31,6 +31,43 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def dd_solve_latency(L, C, R):
+    """p50/p99 wall latency of complete DD solves: 8^3 hexahedra (4096 material
+    points), clamped at x = 0, 100 MPa traction on x = 1, N = 1e6 data points,
+    random initial associations with seeds 0..R-1, until the association stops
+    changing."""
+    import numpy as np
+    import torch
+
+    import ddsynth
+    N, n = 1_000_000, 8
+    e, s = ddsynth.data_points(N, 1001)
+    ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
+                             packs=0x1 | 0x4)
+    mask, force = ddsynth.box_bc(n, 100.0)
+    out = {"workload": "DD solve, 8^3 hex (4096 material points), N=1e6, clamp + 100 MPa",
+           "solves": R}
+    for mode in ("bf16", "fp64"):
+        L.dd_solve(ds, (n, n, n), mask, force, ddsynth.indices(8 * n ** 3, N, 999), mode=mode)
+        lat, iters, conv = [], [], 0
+        for seed in range(R):
+            init = ddsynth.indices(8 * n ** 3, N, seed)
+            torch.cuda.synchronize()
+            t = time.time()
+            r = L.dd_solve(ds, (n, n, n), mask, force, init, mode=mode)
+            lat.append((time.time() - t) * 1e3)
+            iters.append(r["iterations"])
+            conv += int(r["converged"])
+        lat = np.array(lat)
+        out[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 2),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                     "mean_iterations": round(float(np.mean(iters)), 2), "converged": conv}
+        log(f"dd_solve {mode}: p50 {out[mode]['p50_ms']} ms, p99 {out[mode]['p99_ms']} ms, "
+            f"iterations {np.mean(iters):.1f}, converged {conv}/{R}")
+    ds.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +82,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--tile", type=int, default=1024)
     ap.add_argument("--passes", type=int, default=0)
+    ap.add_argument("--dd-solves", type=int, default=20,
+                    help="DD solves (8^3 hex, N=1e6) timed for the p50/p99 latency leg; 0 = skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -141,6 +180,10 @@ def main():
                                                   / dist_mixed))}
         log(f"fp64: {wall * 1e3:.1f} ms/step, indices equal to {args.mode}: {same}")
 
+    dd = None
+    if args.dd_solves > 0:
+        dd = dd_solve_latency(L, C, args.dd_solves)
+
     cpu = None
     if not args.skip_cpu:
         import oracle
@@ -170,6 +213,7 @@ def main():
                    "slow_tiles_per_step": slow / args.steps, "tile": args.tile},
         "roofline": roofline,
         "fp64_scan": fp64,
+        "dd_solve": dd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

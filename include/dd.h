@@ -102,7 +102,8 @@ typedef struct dd_project_stats {
   int64_t candidates;       /* candidates reranked in FP64 (mixed modes) */
   int64_t overflowed;       /* queries rescanned by the FP64 fallback */
   int64_t visited;          /* data points visited (DD_ANN) */
-  double scan_ms;           /* device time of the main scan kernel (HIP events on the call's stream) */
+  double scan_ms;           /* device time of the main scan kernel, the one pass over every
+                               (query, data point) pair (HIP events on the call's stream) */
   double total_ms;          /* device time from the first to the last kernel of the call */
   int64_t slow_tiles;       /* 16-bit scans: (32-query group, tile) items recomputed for candidates */
 } dd_project_stats;
@@ -188,9 +189,10 @@ typedef struct dd_solve_opts {
   int32_t max_iter;      /* 0 = 500 */
   int32_t mode;          /* projection mode (dd_mode), default DD_EXACT_FP64 */
   int32_t cg_max_iter;   /* 0 = 20000 */
-  int32_t reserved;
+  int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
 } dd_solve_opts;
+#define DD_SOLVE_NO_GRAPH 0x1
 
 /* Results of dd_solve; every array is HOST memory provided by the caller and
  * may be NULL when not wanted. */
@@ -215,7 +217,7 @@ typedef struct dd_solve_result {
 /*
  * DD fixed-point loop (Section 2): starting from the association init_idx,
  * repeat  y_i = P_C(z_i)  (eqs. "KuE", "KeS": K u = E, K eta = S with
- * K = A_e{w B^T C B} factorised/prepared once, E = A_e{w B^T C eps*},
+ * K = A_e{w B^T C B} assembled once, E = A_e{w B^T C eps*},
  * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
  * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
  * exact projections).

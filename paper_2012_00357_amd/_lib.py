@@ -48,6 +48,11 @@ class dd_project_opts(ctypes.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime (same SONAME as ROCm's).  Loading torch
+    # first makes libdd bind to that runtime; the other order would put two HIP
+    # (and HSA) runtimes in the process, and torch's streams and allocations
+    # would belong to the other one.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2012_00357_amd.build` "
                           "(or __graft_entry__.build())")
@@ -204,7 +209,7 @@ class dd_mesh(ctypes.Structure):
 
 class dd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("cg_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("cg_max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double)]
 
 
@@ -226,7 +231,7 @@ _lib.dd_solve.restype = ctypes.c_int
 
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
-             cg_max_iter: int = 0, stream=None):
+             cg_max_iter: int = 0, graph: bool = True, stream=None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
@@ -250,7 +255,7 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
                           hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0)
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
-                         cg_max_iter, 0, cg_tol)
+                         cg_max_iter, 0 if graph else 1, cg_tol)
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):

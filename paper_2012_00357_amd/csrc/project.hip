@@ -181,7 +181,6 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     // Without a warm start the bound starts at +inf; a streaming pass over every
     // 16th tile seeds it, so the marking pass logs few stale work items.
     const int passes = (opts && opts->passes) ? opts->passes : (warm_start_idx_dev ? 1 : 2);
-    DD_TRY(timing.mark(1, st));
     if (passes >= 2) {
       c.phase = Scan16Call::kBound;
       c.stride = 16;
@@ -190,7 +189,9 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     }
     c.phase = Scan16Call::kMark;
     c.stride = 1;
+    DD_TRY(timing.mark(1, st));   // the main scan: every (query, data point) pair
     DD_TRY(launch_scan16(D, fp16, c, st));
+    DD_TRY(timing.mark(2, st));
     DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
     unsigned ni = 0;
     DD_HIP(hipMemcpyAsync(&ni, n_items, sizeof(ni), hipMemcpyDeviceToHost, st));
@@ -208,7 +209,6 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     c.phase = Scan16Call::kExtract;
     c.item_cap = ni;
     DD_TRY(launch_scan16(D, fp16, c, st));
-    DD_TRY(timing.mark(2, st));
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
     DD_TRY(launch_merge_rerank(D, Q, all, m, cb, Q.u32, out, fb, counters,

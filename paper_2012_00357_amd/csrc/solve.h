@@ -24,10 +24,15 @@ dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
 
 class DDSolver {
  public:
+  DDSolver() = default;
+  DDSolver(const DDSolver&) = delete;
+  DDSolver& operator=(const DDSolver&) = delete;
+  ~DDSolver();
   dd_status setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* mask, const double* force,
                   const dd_solve_opts* opts, hipStream_t st);
   dd_status set_assignment(const int64_t* idx_host);
   dd_status constraint_projection();
+  dd_status cg_solve();
   dd_status run(int max_iter, dd_solve_result* res);
 
   FEMesh M;
@@ -40,6 +45,11 @@ class DDSolver {
   double L[36], Lt[36];
   DevBuf d_rowptr, d_col, d_val, d_dinv, d_mask, d_f, d_b, d_x, d_work;
   DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
+  DevBuf d_part, d_cgstate;
+  bool use_graph = true;
+  hipGraphExec_t cg_graph = nullptr;
+  int cg_last_iters[2] = {0, 0};
+  double cg_last_res[2] = {0.0, 0.0};
 };
 
 }  // namespace dd

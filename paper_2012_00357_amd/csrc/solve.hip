@@ -239,127 +239,215 @@ __global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
   S[dof] = f[dof] - w * ss;
 }
 
-constexpr int kCgThreads = 1024;
+// ---------------------------------------------------------------------------
+// Conjugate gradients for the two systems K u = E, K eta = S (Jacobi
+// preconditioner), spread over many workgroups.  One iteration = three kernels:
+//   cg_spmv     q = K p and per-block partial sums of p.q
+//   cg_update   alpha = rz / p.q (every block sums the partials in the same
+//               order), x += alpha p, r -= alpha q, z = D^-1 r, partials of
+//               r.z and r.r
+//   cg_pupdate  beta = rz_new / rz, p = z + beta p; block 0 stores the scalars
+//               of the next iteration (double-buffered by iteration parity)
+// A system whose residual |r| <= tol |b| is frozen; the host polls the flags
+// every few iterations.  All sums run in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kCgBlock = 256;
+constexpr int kCgPoll = 16;   // CG iterations per convergence poll (even)
 
-__device__ inline void block_sum2(double& a, double& b, double* red) {
+struct CGState {
+  double rz[2][2];     // [parity][system]
+  int active[2][2];
+  double bb[2];
+  double rr[2];
+  int iters[2];
+};
+
+__device__ inline void block_reduce(double* v, int k, double* red) {
+  // sums v[0..k) over the block (k <= 6); result in v for every thread
   const int t = threadIdx.x;
-  red[t] = a;
-  red[kCgThreads + t] = b;
+  for (int j = 0; j < k; ++j) red[j * kCgBlock + t] = v[j];
   __syncthreads();
-  for (int off = kCgThreads / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      red[t] += red[t + off];
-      red[kCgThreads + t] += red[kCgThreads + t + off];
-    }
+  for (int off = kCgBlock / 2; off > 0; off >>= 1) {
+    if (t < off)
+      for (int j = 0; j < k; ++j) red[j * kCgBlock + t] += red[j * kCgBlock + t + off];
     __syncthreads();
   }
-  a = red[0];
-  b = red[kCgThreads];
+  for (int j = 0; j < k; ++j) v[j] = red[j * kCgBlock];
   __syncthreads();
 }
 
-// Both systems K x0 = b0 (u) and K x1 = b1 (eta) by Jacobi-preconditioned CG in
-// one workgroup.  x holds the initial guesses on entry.  Vectors are [2][n].
-// out_iters[0..1] = iterations per system, out_res[0..1] = final relative residuals.
-__global__ __launch_bounds__(kCgThreads) void cg2_kernel(
+// every block sums the per-block partials (k <= 6 values per block): thread t
+// adds partials t, t + 256, ..., then a fixed-order tree over the block, so all
+// blocks obtain bitwise the same sums
+__device__ inline void sum_partials(const double* __restrict__ part, int nb, int k, double* out,
+                                    double* red) {
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += kCgBlock)
+    for (int j = 0; j < k; ++j) v[j] += part[b * 8 + j];
+  block_reduce(v, k, red);
+  for (int j = 0; j < k; ++j) out[j] = v[j];
+}
+
+__device__ inline double spmv_row(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, const double* __restrict__ v,
+                                  int64_t i) {
+  double s = 0.0;
+  for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s = fma(val[e], v[col[e]], s);
+  return s;
+}
+
+__global__ __launch_bounds__(kCgBlock) void cg_init_kernel(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ dinv, const double* __restrict__ b,
-    double* __restrict__ x, double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
-    double* __restrict__ q, double tol, int max_iter, int* __restrict__ out_iters,
-    double* __restrict__ out_res) {
-  __shared__ double red[2 * kCgThreads];
-  const int t = threadIdx.x;
-  // r = b - K x, z = D^-1 r, p = z
-  double bb0 = 0, bb1 = 0, rz0 = 0, rz1 = 0;
-  for (int64_t i = t; i < n; i += kCgThreads) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+    double* __restrict__ p, double* __restrict__ part) {
+  __shared__ double red[6 * kCgBlock];
+  const int64_t i = (int64_t)blockIdx.x * kCgBlock + threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};   // bb0 bb1 rz0 rz1 rr0 rr1
+  if (i < n) {
+    for (int s = 0; s < 2; ++s) {
+      const double bi = b[s * n + i];
+      const double ri = bi - spmv_row(rowptr, col, val, x + s * n, i);
+      const double zi = dinv[i] * ri;
+      r[s * n + i] = ri;
+      z[s * n + i] = zi;
+      p[s * n + i] = zi;
+      v[s] = bi * bi;
+      v[2 + s] = ri * zi;
+      v[4 + s] = ri * ri;
+    }
+  }
+  block_reduce(v, 6, red);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 6; ++j) part[blockIdx.x * 8 + j] = v[j];
+}
+
+__global__ __launch_bounds__(kCgBlock) void cg_init_finish_kernel(const double* __restrict__ part,
+                                                                  int nb, double tol,
+                                                                  CGState* __restrict__ st) {
+  __shared__ double red[6 * kCgBlock];
+  double v[6];
+  sum_partials(part, nb, 6, v, red);
+  if (threadIdx.x != 0) return;
+  for (int s = 0; s < 2; ++s) {
+    st->bb[s] = v[s];
+    st->rz[0][s] = v[2 + s];
+    st->rr[s] = v[4 + s];
+    st->active[0][s] = v[4 + s] > tol * tol * v[s] ? 1 : 0;
+    st->iters[s] = 0;
+  }
+}
+
+// q = K p for both systems, 16 lanes per row (rows have up to 81 entries), and
+// per-block partial sums of p.q.  Partial-sum order is fixed, so the result is
+// deterministic.
+constexpr int kRowLanes = 16;
+constexpr int kRowsPerBlock = kCgBlock / kRowLanes;
+
+__global__ __launch_bounds__(kCgBlock) void cg_spmv_kernel(
+    int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ p, double* __restrict__ q,
+    double* __restrict__ part, const CGState* __restrict__ st, int parity) {
+  __shared__ double red[2 * kCgBlock];
+  if (!st->active[parity][0] && !st->active[parity][1]) return;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kRowLanes;
+  double s0 = 0.0, s1 = 0.0;
+  if (i < n) {
+    const int32_t e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int32_t e = e0 + sub; e < e1; e += kRowLanes) {
       const double v = val[e];
-      s0 = fma(v, x[col[e]], s0);
-      s1 = fma(v, x[n + col[e]], s1);
+      const int32_t c = col[e];
+      s0 = fma(v, p[c], s0);
+      s1 = fma(v, p[n + c], s1);
     }
-    const double r0 = b[i] - s0, r1 = b[n + i] - s1;
-    r[i] = r0;
-    r[n + i] = r1;
-    const double z0 = dinv[i] * r0, z1 = dinv[i] * r1;
-    z[i] = z0;
-    z[n + i] = z1;
-    p[i] = z0;
-    p[n + i] = z1;
-    bb0 = fma(b[i], b[i], bb0);
-    bb1 = fma(b[n + i], b[n + i], bb1);
-    rz0 = fma(r0, z0, rz0);
-    rz1 = fma(r1, z1, rz1);
   }
-  block_sum2(bb0, bb1, red);
-  block_sum2(rz0, rz1, red);
-  double rr0 = 0, rr1 = 0;
-  for (int64_t i = t; i < n; i += kCgThreads) {
-    rr0 = fma(r[i], r[i], rr0);
-    rr1 = fma(r[n + i], r[n + i], rr1);
+  // reduce over the 16 lanes of the row (fixed butterfly order)
+  for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, kRowLanes);
+    s1 += __shfl_xor(s1, off, kRowLanes);
   }
-  block_sum2(rr0, rr1, red);
-  const double lim0 = tol * tol * bb0, lim1 = tol * tol * bb1;
-  bool act0 = rr0 > lim0, act1 = rr1 > lim1;
-  int it0 = 0, it1 = 0;
-  for (int it = 0; it < max_iter && (act0 || act1); ++it) {
-    __syncthreads();
-    // q = K p, pq = p.q
-    double pq0 = 0.0, pq1 = 0.0;
-    for (int64_t i = t; i < n; i += kCgThreads) {
-      double s0 = 0.0, s1 = 0.0;
-      for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const double v = val[e];
-        s0 = fma(v, p[col[e]], s0);
-        s1 = fma(v, p[n + col[e]], s1);
+  double v[2] = {0.0, 0.0};
+  if (i < n && sub == 0) {
+    q[i] = s0;
+    q[n + i] = s1;
+    v[0] = p[i] * s0;
+    v[1] = p[n + i] * s1;
+  }
+  block_reduce(v, 2, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 8 + 0] = v[0];
+    part[blockIdx.x * 8 + 1] = v[1];
+  }
+}
+
+__global__ __launch_bounds__(kCgBlock) void cg_update_kernel(
+    int64_t n, int nb, const double* __restrict__ dinv, double* __restrict__ x,
+    double* __restrict__ r, double* __restrict__ z, const double* __restrict__ p,
+    const double* __restrict__ q, const double* __restrict__ part_pq, double* __restrict__ part,
+    const CGState* __restrict__ st, int parity) {
+  __shared__ double red[4 * kCgBlock];
+  const int a0 = st->active[parity][0], a1 = st->active[parity][1];
+  if (!a0 && !a1) return;
+  double pq[2];
+  sum_partials(part_pq, nb, 2, pq, red);
+  const double alpha[2] = {a0 ? st->rz[parity][0] / pq[0] : 0.0, a1 ? st->rz[parity][1] / pq[1] : 0.0};
+  const int64_t i = (int64_t)blockIdx.x * kCgBlock + threadIdx.x;
+  double v[4] = {0, 0, 0, 0};   // rz0 rz1 rr0 rr1
+  if (i < n) {
+    for (int s = 0; s < 2; ++s) {
+      if (!(s ? a1 : a0)) continue;
+      x[s * n + i] = fma(alpha[s], p[s * n + i], x[s * n + i]);
+      const double ri = fma(-alpha[s], q[s * n + i], r[s * n + i]);
+      const double zi = dinv[i] * ri;
+      r[s * n + i] = ri;
+      z[s * n + i] = zi;
+      v[s] = ri * zi;
+      v[2 + s] = ri * ri;
+    }
+  }
+  block_reduce(v, 4, red);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < 4; ++j) part[blockIdx.x * 8 + j] = v[j];
+}
+
+__global__ __launch_bounds__(kCgBlock) void cg_pupdate_kernel(
+    int64_t n, int nb, const double* __restrict__ z, double* __restrict__ p,
+    const double* __restrict__ part, CGState* __restrict__ st, int parity, double tol) {
+  const int a0 = st->active[parity][0], a1 = st->active[parity][1];
+  if (!a0 && !a1) {
+    // both frozen: carry the state into the other parity slot
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      for (int s = 0; s < 2; ++s) {
+        st->rz[parity ^ 1][s] = st->rz[parity][s];
+        st->active[parity ^ 1][s] = 0;
       }
-      q[i] = s0;
-      q[n + i] = s1;
-      pq0 = fma(p[i], s0, pq0);
-      pq1 = fma(p[n + i], s1, pq1);
     }
-    block_sum2(pq0, pq1, red);
-    const double a0 = act0 ? rz0 / pq0 : 0.0, a1 = act1 ? rz1 / pq1 : 0.0;
-    double nrz0 = 0.0, nrz1 = 0.0, nrr0 = 0.0, nrr1 = 0.0;
-    for (int64_t i = t; i < n; i += kCgThreads) {
-      x[i] = fma(a0, p[i], x[i]);
-      x[n + i] = fma(a1, p[n + i], x[n + i]);
-      const double r0 = fma(-a0, q[i], r[i]), r1 = fma(-a1, q[n + i], r[n + i]);
-      r[i] = r0;
-      r[n + i] = r1;
-      const double z0 = dinv[i] * r0, z1 = dinv[i] * r1;
-      z[i] = z0;
-      z[n + i] = z1;
-      nrz0 = fma(r0, z0, nrz0);
-      nrz1 = fma(r1, z1, nrz1);
-      nrr0 = fma(r0, r0, nrr0);
-      nrr1 = fma(r1, r1, nrr1);
-    }
-    block_sum2(nrz0, nrz1, red);
-    block_sum2(nrr0, nrr1, red);
-    const double be0 = act0 ? nrz0 / rz0 : 0.0, be1 = act1 ? nrz1 / rz1 : 0.0;
-    for (int64_t i = t; i < n; i += kCgThreads) {
-      if (act0) p[i] = fma(be0, p[i], z[i]);
-      if (act1) p[n + i] = fma(be1, p[n + i], z[n + i]);
-    }
-    if (act0) {
-      rz0 = nrz0;
-      rr0 = nrr0;
-      ++it0;
-      act0 = rr0 > lim0;
-    }
-    if (act1) {
-      rz1 = nrz1;
-      rr1 = nrr1;
-      ++it1;
-      act1 = rr1 > lim1;
-    }
+    return;
   }
-  if (t == 0) {
-    out_iters[0] = it0;
-    out_iters[1] = it1;
-    out_res[0] = bb0 > 0 ? sqrt(rr0 / bb0) : 0.0;
-    out_res[1] = bb1 > 0 ? sqrt(rr1 / bb1) : 0.0;
+  __shared__ double red[4 * kCgBlock];
+  double v[4];
+  sum_partials(part, nb, 4, v, red);
+  const int act[2] = {a0, a1};
+  double beta[2];
+  for (int s = 0; s < 2; ++s) beta[s] = act[s] ? v[s] / st->rz[parity][s] : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kCgBlock + threadIdx.x;
+  if (i < n) {
+    for (int s = 0; s < 2; ++s)
+      if (act[s]) p[s * n + i] = fma(beta[s], p[s * n + i], z[s * n + i]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int s = 0; s < 2; ++s) {
+      if (act[s]) {
+        st->rz[parity ^ 1][s] = v[s];
+        st->rr[s] = v[2 + s];
+        st->iters[s] += 1;
+        st->active[parity ^ 1][s] = v[2 + s] > tol * tol * st->bb[s] ? 1 : 0;
+      } else {
+        st->rz[parity ^ 1][s] = st->rz[parity][s];
+        st->active[parity ^ 1][s] = 0;
+      }
+    }
   }
 }
 
@@ -470,6 +558,7 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   M.init(mesh);
   this->st = st;
   mode = opts ? opts->mode : DD_EXACT_FP64;
+  use_graph = !(opts && (opts->flags & DD_SOLVE_NO_GRAPH));
   cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
   cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
   // Cholesky factor of the metric for the whitened/raw conversions
@@ -501,6 +590,12 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   DD_TRY(d_yw.alloc(sizeof(double) * 12 * nm));
   DD_TRY(d_scal.alloc(sizeof(double) * 4));
   DD_TRY(d_cgstat.alloc(64));
+  {
+    const int64_t nb = (M.n_dof + kCgBlock - 1) / kCgBlock;
+    const int64_t nbs = (M.n_dof + kRowsPerBlock - 1) / kRowsPerBlock;
+    DD_TRY(d_part.alloc(sizeof(double) * 8 * (nb + nbs)));
+    DD_TRY(d_cgstate.alloc(sizeof(CGState)));
+  }
   DD_HIP(hipMemcpyAsync(d_rowptr.p, rowptr.data(), sizeof(int32_t) * (nd + 1), hipMemcpyHostToDevice, st));
   if (nnz) {
     DD_HIP(hipMemcpyAsync(d_col.p, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
@@ -515,11 +610,85 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   return DD_OK;
 }
 
+DDSolver::~DDSolver() {
+  if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+}
+
 dd_status DDSolver::set_assignment(const int64_t* idx_host) {
   const int64_t nm = M.n_mp;
   for (int64_t e = 0; e < nm; ++e)
     if (idx_host[e] < 0 || idx_host[e] >= ds->N) return set_error(DD_ERR_ARG, "init_idx out of range");
   DD_HIP(hipMemcpyAsync(d_idx.p, idx_host, sizeof(int64_t) * nm, hipMemcpyHostToDevice, st));
+  return DD_OK;
+}
+
+dd_status DDSolver::cg_solve() {
+  const int64_t nd = M.n_dof;
+  const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
+  const int nbs = (int)((nd + kRowsPerBlock - 1) / kRowsPerBlock);   // SpMV blocks
+  double* wk = d_work.as<double>();
+  double *r = wk, *z = wk + 2 * nd, *p = wk + 4 * nd, *q = wk + 6 * nd;
+  double* part = d_part.as<double>();
+  double* part2 = part + 8 * (int64_t)nb;
+  CGState* cs = d_cgstate.as<CGState>();
+  const int32_t *rp = d_rowptr.as<int32_t>(), *cl = d_col.as<int32_t>();
+  const double* vl = d_val.as<double>();
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(kCgBlock), 0, st, nd, rp, cl, vl,
+                     d_dinv.as<double>(), d_b.as<double>(), d_x.as<double>(), r, z, p, part);
+  hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kCgBlock), 0, st, part, nb, cg_tol, cs);
+  DD_HIP(hipGetLastError());
+  CGState hs;
+  int it = 0;
+  const int poll = kCgPoll;
+  auto enqueue = [&](hipStream_t s, int it0, int count) {
+    for (int k = 0; k < count; ++k) {
+      const int par = (it0 + k) & 1;
+      hipLaunchKernelGGL(cg_spmv_kernel, dim3(nbs), dim3(kCgBlock), 0, s, nd, rp, cl, vl, p, q,
+                         part2, cs, par);
+      hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kCgBlock), 0, s, nd, nbs,
+                         d_dinv.as<double>(), d_x.as<double>(), r, z, p, q, part2, part, cs, par);
+      hipLaunchKernelGGL(cg_pupdate_kernel, dim3(nb), dim3(kCgBlock), 0, s, nd, nb, z, p, part, cs,
+                         par, cg_tol);
+    }
+  };
+  if (use_graph && !cg_graph) {
+    // one batch of kCgPoll iterations (even start, so the parity sequence is
+    // fixed) captured on a private stream, replayed on the solver's stream
+    hipStream_t cap;
+    DD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      enqueue(cap, 0, poll);
+      e = hipStreamEndCapture(cap, &g);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&cg_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      cg_graph = nullptr;
+      use_graph = false;   // fall back to eager launches
+      (void)hipGetLastError();
+    }
+  }
+  while (it < cg_max_iter) {
+    if (use_graph && cg_graph && it + poll <= cg_max_iter) {
+      DD_HIP(hipGraphLaunch(cg_graph, st));
+      it += poll;
+    } else {
+      const int count = std::min(poll, cg_max_iter - it);
+      enqueue(st, it, count);
+      it += count;
+    }
+    DD_HIP(hipGetLastError());
+    DD_HIP(hipMemcpyAsync(&hs, cs, sizeof(hs), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    if (!hs.active[it & 1][0] && !hs.active[it & 1][1]) break;
+  }
+  cg_last_iters[0] = hs.iters[0];
+  cg_last_iters[1] = hs.iters[1];
+  cg_last_res[0] = hs.bb[0] > 0 ? std::sqrt(hs.rr[0] / hs.bb[0]) : 0.0;
+  cg_last_res[1] = hs.bb[1] > 0 ? std::sqrt(hs.rr[1] / hs.bb[1]) : 0.0;
   return DD_OK;
 }
 
@@ -536,11 +705,7 @@ dd_status DDSolver::constraint_projection() {
   hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
                      d_b.as<double>(), d_b.as<double>() + nd);
-  double* wk = d_work.as<double>();
-  hipLaunchKernelGGL(cg2_kernel, dim3(1), dim3(kCgThreads), 0, st, nd, d_rowptr.as<int32_t>(),
-                     d_col.as<int32_t>(), d_val.as<double>(), d_dinv.as<double>(), d_b.as<double>(),
-                     d_x.as<double>(), wk, wk + 2 * nd, wk + 4 * nd, wk + 6 * nd, cg_tol, cg_max_iter,
-                     d_cgstat.as<int>(), reinterpret_cast<double*>(d_cgstat.as<char>() + 16));
+  DD_TRY(cg_solve());
   hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
                      d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),
                      (double*)nullptr, (double*)nullptr);
@@ -574,11 +739,9 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
       DD_HIP(hipMemcpyAsync(res->history + (int64_t)it * nm, d_idx_new.p, sizeof(int64_t) * nm,
                             hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
-    int cg_it[2];
-    double cg_res[2];
+    int cg_it[2] = {cg_last_iters[0], cg_last_iters[1]};
+    double cg_res[2] = {cg_last_res[0], cg_last_res[1]};
     int bad = 0;
-    std::memcpy(cg_it, cgs, sizeof(cg_it));
-    std::memcpy(cg_res, cgs + 16, sizeof(cg_res));
     std::memcpy(&bad, cgs + 32, sizeof(bad));
     if (bad) return set_error(DD_ERR_DEVICE, "dd_solve: the admissible state became non-finite");
     cg_total += cg_it[0] + cg_it[1];

@@ -102,3 +102,15 @@ def test_dd_solve_config1_stepwise(L, C0):
         clear = o2 > od * (1 + 1e-12)
         assert np.array_equal(hist[i + 1][sample][clear], oi[clear]), f"P_D differs at iteration {i}"
     np.testing.assert_allclose(got["u"], u, rtol=0, atol=1e-10 * np.abs(u).max())
+
+
+def test_dd_solve_graph_replays_equal_eager(L, C0):
+    """The captured CG batches (replayed many times per solve, with eager work
+    and synchronisations between replays) give bitwise the eager result."""
+    e, s, m, mask, f, init = _problem(4, 30000, 71)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
+    a = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=True)
+    b = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=False)
+    assert a["cg_iterations"] > 100
+    assert np.array_equal(a["history"], b["history"])
+    assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["d_half"], b["d_half"])
