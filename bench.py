@@ -31,6 +31,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(mode, tile, N, m):
+    """HBM bytes per launch of the main scan kernel from the committed rocprofv3
+    counter summary, or None when that summary is for another kernel, workload
+    or an older version of the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "scan16_pass_bf16_N2e27_m65536.md")
+    if mode != "bf16" or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        line = line.strip()
+        if ":" in line and line.split(":")[0] in ("kernel", "workload", "traffic_bytes_per_launch",
+                                                  "source", "source_sha256_16"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    try:
+        src = open(os.path.join(ROOT, fields["source"]), "rb").read()
+    except (KeyError, OSError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != fields.get("source_sha256_16"):
+        return None
+    if fields.get("workload") != f"N={N} m={m} tile={tile}":
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def dd_solve_latency(L, C, R):
     """p50/p99 wall latency of complete DD solves: 8^3 hexahedra (4096 material
     points), clamped at x = 0, 100 MPa traction on x = 1, N = 1e6 data points,
@@ -153,9 +179,10 @@ def main():
         f"slow tiles/step {slow / args.steps:.0f}")
 
     peak = FP64_PEAK_TFLOPS if args.mode == "fp64" else BF16_PEAK_TFLOPS
+    traffic = measured_traffic(args.mode, args.tile, N, m)
     achieved = FLOPS_PER_PAIR * N * m / (scan_avg / 1e3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": f"scan16_pass_kernel<{args.mode}, {args.tile}, mark>",
                 "flops_per_pair": FLOPS_PER_PAIR,
                 "issued_frac": round(achieved * 32.0 / FLOPS_PER_PAIR / peak, 4)}
