@@ -13,7 +13,9 @@ Workload recipe (every configuration):
   * queries: a uniformly drawn data point plus N(0, (5e-5)^2) on each strain
     component and N(0, 10^2) MPa on each stress component (5 % of the scales).
 
-The C core (gen.c) is compiled with gcc on first use; `build()` forces it.
+The C core (gen.c) is compiled with gcc on first use; `build()` forces it and
+also compiles the GPU twin of the data-point recipe (gen_dev.hip, hipcc for
+gfx950), which writes the same bits on the device (`DevicePoints`).
 """
 from __future__ import annotations
 
@@ -26,7 +28,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
 _LIB_PATH = os.path.join(_HERE, "libddsynth.so")
+_DEV_SRC = os.path.join(_HERE, "gen_dev.hip")
+_DEV_LIB_PATH = os.path.join(_HERE, "libddsynth_dev.so")
 _lib = None
+_dev_lib = None
 
 E_MODULUS = 200000.0
 POISSON = 0.3
@@ -37,15 +42,25 @@ QUERY_EPS_STD = 0.05 * EPS_AMP               # 5e-5
 QUERY_SIG_STD = 0.05 * STRESS_SCALE          # 10 MPa
 
 
-def build(force: bool = True) -> str:
-    """Compile gen.c into libddsynth.so next to it (gcc, OpenMP)."""
-    global _lib
+def build(force: bool = True, device: bool = True) -> str:
+    """Compile gen.c into libddsynth.so next to it (gcc, OpenMP) and, with
+    `device`, gen_dev.hip into libddsynth_dev.so (hipcc, gfx950)."""
+    global _lib, _dev_lib
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
                                "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
         _lib = None
+    if device and (force or not os.path.exists(_DEV_LIB_PATH)):
+        tmp = _DEV_LIB_PATH + ".tmp"
+        hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
+                               "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+                               "-o", tmp, _DEV_SRC])
+        os.replace(tmp, _DEV_LIB_PATH)
+        _dev_lib = None
     return _LIB_PATH
 
 
@@ -63,8 +78,11 @@ def _load():
         lib.ddsynth_queries.argtypes = [u64, i64, vp, vp, i64, dbl, dbl, vp, vp, vp]
         lib.ddsynth_indices.argtypes = [u64, i64, i64, vp]
         lib.ddsynth_uniform.argtypes = [u64, i64, dbl, dbl, vp]
+        lib.ddsynth_box_muller.argtypes = [vp, vp, i64, vp]
+        lib.ddsynth_elementary.argtypes = [vp, i64, vp]
         for f in ("ddsynth_philox", "ddsynth_philox_many", "ddsynth_points",
-                  "ddsynth_queries", "ddsynth_indices", "ddsynth_uniform"):
+                  "ddsynth_queries", "ddsynth_indices", "ddsynth_uniform",
+                  "ddsynth_box_muller", "ddsynth_elementary"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -158,6 +176,70 @@ def uniform(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
     out = np.empty(n, dtype=np.float64)
     _load().ddsynth_uniform(seed, n, lo, hi, _ptr(out))
     return out
+
+
+def box_muller(ua: np.ndarray, ub: np.ndarray) -> np.ndarray:
+    """Pairs of standard normals [n][2] from uniforms ua, ub (the shared transform)."""
+    ua = np.ascontiguousarray(ua, dtype=np.float64)
+    ub = np.ascontiguousarray(ub, dtype=np.float64)
+    z = np.empty((ua.size, 2))
+    _load().ddsynth_box_muller(_ptr(ua), _ptr(ub), ua.size, _ptr(z))
+    return z
+
+
+def elementary(x: np.ndarray) -> np.ndarray:
+    """[n][3] = (log x, cos 2 pi x, sin 2 pi x) from the shared generator core."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty((x.size, 3))
+    _load().ddsynth_elementary(_ptr(x), x.size, _ptr(out))
+    return out
+
+
+class _PointParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("eps_amp", ctypes.c_double),
+                ("S0", ctypes.c_double * 36), ("noise_std", ctypes.c_double)]
+
+
+class DevicePoints:
+    """The data-point recipe on the GPU (same bits as `data_points`).
+
+    `fill_fn` / `user` form a producer for dd_dataset_create_streamed:
+    fill(user, first, count, strain_dev, stress_dev, hip_stream) -> 0 on success.
+    `generate(first, n)` returns device tensors (strain, stress) [n][6].
+    """
+
+    def __init__(self, seed: int, S0: np.ndarray | None = None, eps_amp: float = EPS_AMP,
+                 noise_std: float = DATA_NOISE_STD):
+        global _dev_lib
+        if _dev_lib is None:
+            if not os.path.exists(_DEV_LIB_PATH):
+                raise RuntimeError("libddsynth_dev.so is not built (ddsynth.build())")
+            import torch  # noqa: F401  (one HIP runtime per process: torch's)
+            lib = ctypes.CDLL(_DEV_LIB_PATH)
+            lib.ddsynth_dev_fill.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+            lib.ddsynth_dev_fill.restype = ctypes.c_int
+            lib.ddsynth_dev_params_bytes.restype = ctypes.c_int
+            if lib.ddsynth_dev_params_bytes() != ctypes.sizeof(_PointParams):
+                raise RuntimeError("libddsynth_dev.so parameter layout mismatch")
+            _dev_lib = lib
+        S0 = isotropic_stiffness() if S0 is None else np.asarray(S0, dtype=np.float64)
+        self.params = _PointParams(seed, eps_amp, (ctypes.c_double * 36)(*S0.ravel().tolist()),
+                                   noise_std)
+        self.lib = _dev_lib
+        self.fill_fn = ctypes.cast(_dev_lib.ddsynth_dev_fill, ctypes.c_void_p).value
+        self.user = ctypes.addressof(self.params)
+
+    def generate(self, first: int, n: int, stream: int = 0):
+        import torch
+        e = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+        s = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+        if stream == 0:
+            stream = torch.cuda.current_stream().cuda_stream
+        rc = self.lib.ddsynth_dev_fill(self.user, first, n, e.data_ptr(), s.data_ptr(), stream)
+        if rc != 0:
+            raise RuntimeError(f"ddsynth_dev_fill failed ({rc})")
+        return e, s
 
 
 def states(strain: np.ndarray, stress: np.ndarray) -> np.ndarray:

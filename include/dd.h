@@ -73,7 +73,13 @@ typedef enum dd_mode {
    * candidate inside the proven BF16 error margin reranked in FP64; queries
    * whose candidate list overflows are rescanned in FP64.  Exact. */
   DD_MIXED_BF16 = 2,
-  /* Approximate search: warm-started walk over spatial cells (budgeted). */
+  /* Warm-started walk over a 64-ary tree of principal-axis boxes (dataset
+   * pack DD_PACK_ANN), visiting subtrees nearest-box-first and pruning every
+   * box whose distance bound exceeds the best certified distance so far; FP32
+   * distances with a proven error margin, FP64 rerank.  With ann_budget = 0 the
+   * walk ends only when every box is pruned, and the result is exact; with a
+   * budget it stops after that many leaves (64 points each) and is approximate
+   * (never worse than the warm-start point). */
   DD_ANN = 3,
   /* Plain FP64 direct-form scan (VALU), the simplest exact kernel. */
   DD_DIRECT_FP64 = 4,
@@ -86,7 +92,7 @@ typedef enum dd_mode {
 #define DD_PACK_FP32 0x2u   /* whitened FP32 [N][12] + norms: DD_MIXED_FP32 */
 #define DD_PACK_BF16 0x4u   /* tile-centred BF16 [N][16] + tile centres/radii: DD_MIXED_BF16 */
 #define DD_PACK_FP16 0x8u   /* tile-centred FP16 [N][16]: DD_MIXED_FP16 */
-#define DD_PACK_ANN 0x10u   /* cell index over the FP32 pack: DD_ANN */
+#define DD_PACK_ANN 0x10u   /* box tree over the sorted FP32 pack (implies FP32 and FP64): DD_ANN */
 #define DD_PACK_DEFAULT (DD_PACK_FP64 | DD_PACK_BF16)
 
 typedef struct dd_dataset dd_dataset;
@@ -94,7 +100,7 @@ typedef struct dd_dataset dd_dataset;
 typedef struct dd_dataset_opts {
   uint32_t packs;      /* DD_PACK_* mask; 0 = DD_PACK_DEFAULT */
   int32_t tile;        /* points per centring tile of the 16-bit packs: 128, 256, 512 or 1024; 0 = 1024 */
-  int32_t ann_bits;    /* cell grid bits per principal axis for DD_PACK_ANN; 0 = default */
+  int32_t reserved;    /* must be 0 */
 } dd_dataset_opts;
 
 /* Per-call statistics (optional output of dd_project). */
@@ -106,12 +112,15 @@ typedef struct dd_project_stats {
                                (query, data point) pair (HIP events on the call's stream) */
   double total_ms;          /* device time from the first to the last kernel of the call */
   int64_t slow_tiles;       /* 16-bit scans: (32-query group, tile) items recomputed for candidates */
+  int64_t boxes;            /* DD_ANN: tree boxes tested */
+  int64_t leaves;           /* DD_ANN: leaves (64-point blocks) visited */
 } dd_project_stats;
 
 typedef struct dd_project_opts {
   int32_t mode;             /* dd_mode; default DD_EXACT_FP64 */
   int32_t splits;           /* data splits per query block; 0 = automatic */
-  int32_t ann_budget;       /* DD_ANN: max cells visited per query (0 = unlimited, exact) */
+  int32_t ann_budget;       /* DD_ANN: max leaves (64-point blocks) visited per query;
+                               0 = unlimited (exact) */
   int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
                                every 16th tile first; 0 = automatic (2 without a warm start) */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
@@ -133,6 +142,29 @@ typedef struct dd_project_opts {
 dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev, int64_t N,
                             const double* C, const dd_dataset_opts* opts, void* hip_stream,
                             dd_dataset** out);
+
+/*
+ * Producer of data points for dd_dataset_create_streamed: write points
+ * first .. first+count-1 into the library's device arrays strain_dev[count][6]
+ * and stress_dev[count][6], stream-ordered on hip_stream (the library's
+ * stream; the producer must not synchronise other streams against it).  Must
+ * return 0 on success and write the same values every time it is asked for a
+ * point: creation reads the data set three times, in chunks of up to 2^24
+ * points.  A non-zero return aborts creation with DD_ERR_ARG.
+ */
+typedef int (*dd_fill_fn)(void* user, int64_t first, int64_t count, double* strain_dev,
+                          double* stress_dev, void* hip_stream);
+
+/*
+ * As dd_dataset_create for a data set too large to hold in raw form next to
+ * its packs (Section 3 scales N to 10^9): the points come from `fill` in
+ * chunks, so only the packs and a chunk of raw data are ever resident.  The
+ * resulting dataset is identical to dd_dataset_create's on the same points.
+ * Errors: as dd_dataset_create; DD_ERR_ARG if fill fails.
+ */
+dd_status dd_dataset_create_streamed(int64_t N, const double* C, dd_fill_fn fill, void* user,
+                                     const dd_dataset_opts* opts, void* hip_stream,
+                                     dd_dataset** out);
 
 /* Release a dataset's device memory (NULL is a no-op). */
 dd_status dd_dataset_destroy(dd_dataset* ds);
@@ -191,6 +223,8 @@ typedef struct dd_solve_opts {
   int32_t cg_max_iter;   /* 0 = 20000 */
   int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
+  int32_t ann_budget;    /* DD_ANN: leaves per projection (0 = exact walk) */
+  int32_t reserved;      /* must be 0 */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
 
@@ -208,7 +242,8 @@ typedef struct dd_solve_result {
   int32_t history_capacity; /* entries available in the four arrays above */
   int32_t iterations;       /* out: DD iterations performed */
   int32_t converged;        /* out: 1 if the association stopped changing */
-  int32_t reserved;
+  int32_t stop_reason;      /* out: 0 max_iter reached, 1 association unchanged, 2 distance
+                               no longer decreasing (approximate projection only) */
   int64_t cg_iterations;    /* out: total CG iterations (both systems) */
   double cg_max_residual;   /* out: largest final relative CG residual */
   double elapsed_ms;        /* out: host wall time of the loop */
@@ -220,7 +255,10 @@ typedef struct dd_solve_result {
  * K = A_e{w B^T C B} assembled once, E = A_e{w B^T C eps*},
  * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
  * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
- * exact projections).
+ * exact projections).  With an approximate projection (DD_ANN with a budget)
+ * the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer decreases,
+ * since the alternating-minimisation descent no longer holds (Section 4.1);
+ * each projection is warm-started from the current association.
  *   mesh            structured box mesh (see dd_mesh)
  *   dirichlet_mask  host uint8 [ndof]: 1 = homogeneous Dirichlet DOF (u = eta = 0)
  *   nodal_force     host float64 [ndof]: consistent nodal forces f

@@ -33,13 +33,14 @@ class DDError(RuntimeError):
 
 
 class dd_dataset_opts(ctypes.Structure):
-    _fields_ = [("packs", ctypes.c_uint32), ("tile", ctypes.c_int32), ("ann_bits", ctypes.c_int32)]
+    _fields_ = [("packs", ctypes.c_uint32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class dd_project_stats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("overflowed", ctypes.c_int64),
                 ("visited", ctypes.c_int64), ("scan_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("slow_tiles", ctypes.c_int64)]
+                ("total_ms", ctypes.c_double), ("slow_tiles", ctypes.c_int64),
+                ("boxes", ctypes.c_int64), ("leaves", ctypes.c_int64)]
 
 
 class dd_project_opts(ctypes.Structure):
@@ -60,12 +61,14 @@ def _load():
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.dd_dataset_create.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_dataset_opts), vp,
                                       ctypes.POINTER(vp)]
+    lib.dd_dataset_create_streamed.argtypes = [i64, vp, vp, vp, ctypes.POINTER(dd_dataset_opts),
+                                               vp, ctypes.POINTER(vp)]
     lib.dd_dataset_destroy.argtypes = [vp]
     lib.dd_dataset_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.dd_project.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_project_opts), vp, vp, vp]
     lib.dd_selftest_mfma.argtypes = [i32, vp, vp, vp]
-    for f in ("dd_dataset_create", "dd_dataset_destroy", "dd_dataset_info", "dd_project",
-              "dd_selftest_mfma"):
+    for f in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
+              "dd_dataset_info", "dd_project", "dd_selftest_mfma"):
         getattr(lib, f).restype = ctypes.c_int
     lib.dd_last_error.restype = ctypes.c_char_p
     lib.dd_version.restype = ctypes.c_char_p
@@ -140,7 +143,7 @@ class Dataset:
             pass
 
 
-def dd_dataset_create(strain, stress, C, packs: int = 0, tile: int = 0, ann_bits: int = 0,
+def dd_dataset_create(strain, stress, C, packs: int = 0, tile: int = 0,
                       stream=None) -> Dataset:
     """dd_dataset_create: strain/stress are device float64 [N][6] tensors, C a 6x6 host array."""
     import torch
@@ -148,11 +151,25 @@ def dd_dataset_create(strain, stress, C, packs: int = 0, tile: int = 0, ann_bits
     ps = _dev_ptr(strain, torch.float64, (6,), "strain")
     pt = _dev_ptr(stress, torch.float64, (6,), "stress")
     Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(36))
-    opts = dd_dataset_opts(packs, tile, ann_bits)
+    opts = dd_dataset_opts(packs, tile, 0)
     out = ctypes.c_void_p()
     _check(_lib.dd_dataset_create(ps, pt, n, Cm.ctypes.data, ctypes.byref(opts), _stream(stream),
                                   ctypes.byref(out)), "dd_dataset_create")
     return Dataset(out.value, n)
+
+
+def dd_dataset_create_streamed(n: int, C, fill_fn: int, user: int, packs: int = 0, tile: int = 0,
+                               stream=None) -> Dataset:
+    """dd_dataset_create_streamed: fill_fn is the address of a C producer with the
+    dd_fill_fn signature, user its opaque argument (e.g. ddsynth.DevicePoints)."""
+    Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(36))
+    opts = dd_dataset_opts(packs, tile, 0)
+    out = ctypes.c_void_p()
+    _check(_lib.dd_dataset_create_streamed(int(n), Cm.ctypes.data, ctypes.c_void_p(fill_fn),
+                                           ctypes.c_void_p(user), ctypes.byref(opts),
+                                           _stream(stream), ctypes.byref(out)),
+           "dd_dataset_create_streamed")
+    return Dataset(out.value, int(n))
 
 
 def dd_dataset_destroy(ds: Dataset):
@@ -183,7 +200,8 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
     if stats:
         return idx_out, dist_out, {"candidates": st.candidates, "overflowed": st.overflowed,
                                    "visited": st.visited, "scan_ms": st.scan_ms,
-                                   "total_ms": st.total_ms, "slow_tiles": st.slow_tiles}
+                                   "total_ms": st.total_ms, "slow_tiles": st.slow_tiles,
+                                   "boxes": st.boxes, "leaves": st.leaves}
     return idx_out, dist_out
 
 
@@ -210,7 +228,8 @@ class dd_mesh(ctypes.Structure):
 class dd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("cg_max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("cg_tol", ctypes.c_double)]
+                ("cg_tol", ctypes.c_double), ("ann_budget", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class dd_solve_result(ctypes.Structure):
@@ -218,7 +237,7 @@ class dd_solve_result(ctypes.Structure):
                 ("sig", ctypes.c_void_p), ("d_half", ctypes.c_void_p), ("d_full", ctypes.c_void_p),
                 ("changed", ctypes.c_void_p), ("history", ctypes.c_void_p),
                 ("history_capacity", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
                 ("cg_iterations", ctypes.c_int64), ("cg_max_residual", ctypes.c_double),
                 ("elapsed_ms", ctypes.c_double)]
 
@@ -231,7 +250,7 @@ _lib.dd_solve.restype = ctypes.c_int
 
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
-             cg_max_iter: int = 0, graph: bool = True, stream=None):
+             cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, stream=None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
@@ -255,7 +274,7 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
                           hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0)
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
-                         cg_max_iter, 0 if graph else 1, cg_tol)
+                         cg_max_iter, 0 if graph else 1, cg_tol, ann_budget, 0)
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):
@@ -265,6 +284,7 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
         out[k] = out[k][:it]
     if history:
         out["history"] = hist[:it + 1]
-    out.update(iterations=it, converged=bool(res.converged), cg_iterations=res.cg_iterations,
+    out.update(iterations=it, converged=bool(res.converged), stop_reason=res.stop_reason,
+               cg_iterations=res.cg_iterations,
                cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
     return out

@@ -1,0 +1,350 @@
+// DD_ANN: warm-started walk over the box tree of the dataset (P_D of Section 2
+// by a search that starts from the previous association, as the graph walks of
+// Section 4.3 do, and that may stop early under a budget, as the approximate
+// searches of Section 4 trade accuracy for time).
+//
+// One wavefront per query.  The tree's level-0 boxes bound leaves of 64
+// consecutive points of the spatially sorted data, each higher level bounds 64
+// boxes of the level below; boxes live in principal-axis coordinates y = V^T x
+// (a rotation of the whitened space, so box distances are lower bounds of
+// whitened distances).  The walk is depth-first with the children of a node
+// pushed farthest-first, so the nearest box is always expanded next; a box is
+// skipped when its lower bound exceeds the current bound U.
+//
+// Certification.  Leaf points are read from the FP32 pack; s~ = sqrt(sum (q_f -
+// x_f)^2) in FP32 differs from the exact whitened distance by at most
+// E = 2^-20 (s~ + |q| + max|x|) (rounding of the stored and query operands,
+// 12 fused multiply-adds and the square root, with a wide margin).  U is the
+// minimum of s~ + E over everything seen (and the exact warm-start distance);
+// a point is kept as a candidate while s~ - E <= U.  Every point of a skipped
+// box, and every dropped candidate, is strictly farther than U, which is at
+// least the true minimum, so the kept candidates always contain every exact
+// minimiser once the walk runs to completion (budget 0); they are reranked in
+// FP64 direct form with ties to the lowest original index.  A candidate list
+// that overflows sends the query to the FP64 scan.
+#include <cmath>
+
+#include "scan.h"
+
+namespace dd {
+
+namespace {
+
+constexpr int kWaves = 4;                          // queries (wavefronts) per block
+constexpr int kStack = kAnnFan * kAnnMaxLevels;    // depth-first stack entries per wave
+constexpr int kCand = 64;                          // candidate list entries per wave
+constexpr float kEps20 = 9.5367431640625e-07f;     // 2^-20
+constexpr float kEps22 = 2.384185791015625e-07f;   // 2^-22
+constexpr float kLbShrink = 1.0f - 1.9073486328125e-06f;   // 1 - 2^-19
+
+struct AnnArgs {
+  const float* box[kAnnMaxLevels];
+  int64_t n[kAnnMaxLevels];
+  int levels;
+  const float* w32;
+  const double* w64;
+  const uint32_t* perm;
+  const uint32_t* iperm;
+  int64_t N;
+  double V[144];
+  float xmax;
+  int budget;
+  QueryList L;
+  const double* qw;
+  const double* qn2;
+  const float* u32;
+  const int* invalid;
+  const int64_t* warm;
+  Outputs out;
+  int* fb_list;
+  int* fb_count;
+  unsigned long long* counters;   // [0] points visited, [1] boxes tested, [2] leaves, [3] candidates
+};
+
+__device__ inline float wave_min_f(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+
+__device__ inline int lanes_below(uint64_t mask, int lane) {
+  return __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+}
+
+// FP32 distance of the query to stored row pos (direct form, fixed order).
+__device__ inline float leaf_dist(const float* __restrict__ w32, int64_t pos, const float qf[12]) {
+  const float4* r = reinterpret_cast<const float4*>(w32 + 12 * pos);
+  const float4 a = r[0], b = r[1], c = r[2];
+  const float x[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  float d = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const float t = qf[k] - x[k];
+    d = fmaf(t, t, d);
+  }
+  return d;
+}
+
+// Lower bound of the whitened distance from the query to box b, minus the slack
+// that covers the rounding of the query's rotated coordinates and of this sum.
+__device__ inline float box_lb(const float* __restrict__ b, const float yq[12], float slack) {
+  const float4* r = reinterpret_cast<const float4*>(b);
+  const float4 l0 = r[0], l1 = r[1], l2 = r[2], h0 = r[3], h1 = r[4], h2 = r[5];
+  const float lo[12] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x, l2.y, l2.z, l2.w};
+  const float hi[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const float g = fmaxf(fmaxf(lo[a] - yq[a], yq[a] - hi[a]), 0.0f);
+    s = fmaf(g, g, s);
+  }
+  return __builtin_sqrtf(s) * kLbShrink - slack;
+}
+
+// Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront.
+__device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const float ok = __shfl_xor(key, j);
+      const uint32_t ov = __shfl_xor(val, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const bool take = (lower == up) ? (ok < key) : (ok > key);
+      if (take) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
+  __shared__ uint32_t s_code[kWaves][kStack];
+  __shared__ float s_lb[kWaves][kStack];
+  __shared__ uint32_t s_cpos[kWaves][kCand];
+  __shared__ float s_clb[kWaves][kCand];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * kWaves + wv;
+  if (p >= list_len(A.L)) return;
+  const int64_t q = list_query(A.L, p);
+  if (A.invalid[q]) {
+    if (lane == 0) {
+      A.out.idx[q] = -1;
+      if (A.out.dist) A.out.dist[q] = NAN;
+    }
+    return;
+  }
+  float qf[12], yq[12];
+  {
+    double qd[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      qd[k] = A.qw[12 * q + k];
+      qf[k] = (float)qd[k];
+    }
+#pragma unroll
+    for (int a = 0; a < 12; ++a) {
+      double y = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
+      yq[a] = (float)y;
+    }
+  }
+  const float qnorm = (float)sqrt(A.qn2[q]);
+  const float ebase = kEps20 * (qnorm + A.xmax);
+  const float slack = kEps22 * (qnorm + A.xmax) + 1e-30f;
+  float U = A.u32[q];
+  int nc = 0;
+  bool ovf = false;
+
+  // the warm-start point is the first candidate
+  if (A.warm) {
+    const int64_t wi = A.warm[q];
+    if (wi >= 0 && wi < A.N) {
+      const int64_t pos = A.iperm[wi];
+      const float s = __builtin_sqrtf(leaf_dist(A.w32, pos, qf));
+      const float E = ebase + kEps20 * s;
+      U = fminf(U, s + E);
+      if (lane == 0) {
+        s_cpos[wv][0] = (uint32_t)pos;
+        s_clb[wv][0] = s - E;
+      }
+      nc = 1;
+    }
+  }
+
+  // push the children [c0, c0 + cnt) of level lv that may hold candidates,
+  // farthest first (so the nearest is on top of the stack)
+  int sp = 0;
+  unsigned long long boxes = 0, leaves = 0, visited = 0;
+  auto expand = [&](int lv, int64_t c0, int cnt) {
+    float key = INFINITY;
+    uint32_t val = 0;
+    if (lane < cnt) {
+      const float lb = box_lb(A.box[lv] + 24 * (c0 + lane), yq, slack);
+      if (lb <= U) key = fmaxf(lb, 0.0f);
+      val = (uint32_t)(c0 + lane);
+    }
+    const uint64_t pass = __ballot(key != INFINITY);
+    int k = __popcll(pass);
+    // depth-first order keeps at most kAnnFan entries per level on the stack;
+    // the guard only protects the shared array
+    if (sp + k > kStack) {
+      ovf = true;
+      k = 0;
+    }
+    wave_sort64(key, val, lane);
+    if (lane < k) {
+      s_code[wv][sp + k - 1 - lane] = ((uint32_t)lv << 28) | val;
+      s_lb[wv][sp + k - 1 - lane] = key;
+    }
+    __builtin_amdgcn_wave_barrier();
+    sp += k;
+    boxes += (unsigned long long)cnt;
+  };
+
+  expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
+  while (sp > 0 && !ovf) {
+    --sp;
+    const uint32_t code = s_code[wv][sp];
+    const float lb = s_lb[wv][sp];
+    if (lb > U) continue;
+    const int lv = (int)(code >> 28);
+    const int64_t idx = (int64_t)(code & 0x0FFFFFFFu);
+    if (lv > 0) {
+      const int64_t c0 = idx * kAnnFan;
+      const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
+      expand(lv - 1, c0, cnt);
+      if (ovf) break;
+      continue;
+    }
+    // leaf: 64 consecutive sorted points, one per lane
+    const int64_t pos = idx * kAnnLeaf + lane;
+    const bool v = pos < A.N;
+    float s = INFINITY, E = 0.0f;
+    if (v) {
+      s = __builtin_sqrtf(leaf_dist(A.w32, pos, qf));
+      E = ebase + kEps20 * s;
+    }
+    U = fminf(U, wave_min_f(v ? s + E : INFINITY));
+    const bool keep = v && (s - E <= U);
+    const uint64_t km = __ballot(keep);
+    const int cnt = __popcll(km);
+    visited += (unsigned long long)__popcll(__ballot(v));
+    ++leaves;
+    if (nc + cnt > kCand) {
+      // drop the candidates the bound has excluded since they were kept
+      uint32_t cp = 0;
+      float cl = INFINITY;
+      if (lane < nc) {
+        cp = s_cpos[wv][lane];
+        cl = s_clb[wv][lane];
+      }
+      const bool still = lane < nc && cl <= U;
+      const uint64_t sm = __ballot(still);
+      __builtin_amdgcn_wave_barrier();
+      if (still) {
+        const int at = lanes_below(sm, lane);
+        s_cpos[wv][at] = cp;
+        s_clb[wv][at] = cl;
+      }
+      __builtin_amdgcn_wave_barrier();
+      nc = __popcll(sm);
+      if (nc + cnt > kCand) {
+        ovf = true;
+        break;
+      }
+    }
+    if (keep) {
+      const int at = nc + lanes_below(km, lane);
+      s_cpos[wv][at] = (uint32_t)pos;
+      s_clb[wv][at] = s - E;
+    }
+    __builtin_amdgcn_wave_barrier();
+    nc += cnt;
+    if (A.budget > 0 && leaves >= (unsigned long long)A.budget) break;
+  }
+
+  if (lane == 0) {
+    atomicAdd(A.counters + 0, visited);
+    atomicAdd(A.counters + 1, boxes);
+    atomicAdd(A.counters + 2, leaves);
+  }
+  if (ovf) {
+    if (lane == 0) {
+      const int k = atomicAdd(A.fb_count, 1);
+      A.fb_list[k] = (int)q;
+    }
+    return;
+  }
+  // FP64 rerank of the surviving candidates (direct form, as every scan's merge)
+  double d = INFINITY;
+  uint32_t o = 0xFFFFFFFFu;
+  const bool mine = lane < nc && s_clb[wv][lane] <= U;
+  if (mine) {
+    const int64_t j = s_cpos[wv][lane];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double t = A.qw[12 * q + k] - A.w64[12 * j + k];
+      acc = fma(t, t, acc);
+    }
+    d = acc;
+    o = A.perm[j];
+  }
+  if (lane == 0) atomicAdd(A.counters + 3, (unsigned long long)__popcll(__ballot(mine)));
+  for (int off = 32; off > 0; off >>= 1) {
+    const double od = __shfl_xor(d, off);
+    const uint32_t oo = __shfl_xor(o, off);
+    if (od < d || (od == d && oo < o)) {
+      d = od;
+      o = oo;
+    }
+  }
+  if (lane == 0) {
+    A.out.idx[q] = (int64_t)o;
+    if (A.out.dist) A.out.dist[q] = 0.5 * d;
+  }
+}
+
+}  // namespace
+
+dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
+                          const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
+                          unsigned long long* counters, hipStream_t st) {
+  if (len_max <= 0) return DD_OK;
+  if (D.ann_levels < 1 || D.ann_levels > kAnnMaxLevels || D.ann_n[D.ann_levels - 1] > kAnnFan)
+    return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
+  AnnArgs A{};
+  for (int l = 0; l < D.ann_levels; ++l) {
+    A.box[l] = D.ann_box[l].as<float>();
+    A.n[l] = D.ann_n[l];
+  }
+  A.levels = D.ann_levels;
+  A.w32 = D.w32.as<float>();
+  A.w64 = D.w64.as<double>();
+  A.perm = D.perm.as<uint32_t>();
+  A.iperm = D.iperm.as<uint32_t>();
+  A.N = D.N;
+  for (int i = 0; i < 144; ++i) A.V[i] = D.V[i];
+  A.xmax = __builtin_nextafterf((float)D.xmax, INFINITY);
+  A.budget = budget;
+  A.L = L;
+  A.qw = Q.qw;
+  A.qn2 = Q.qn2;
+  A.u32 = Q.u32;
+  A.invalid = Q.invalid;
+  A.warm = warm;
+  A.out = out;
+  A.fb_list = fb_list;
+  A.fb_count = fb_count;
+  A.counters = counters;
+  const unsigned blocks = (unsigned)((len_max + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(ann_walk_kernel, dim3(blocks), dim3(kWaves * 64), 0, st, A);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+}  // namespace dd

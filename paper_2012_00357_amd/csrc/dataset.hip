@@ -1,8 +1,9 @@
 // Dataset creation: whitening (Section 3.2), spatial order, FP64 / FP32 /
-// tile-centred 16-bit packs.
+// tile-centred 16-bit packs and the ANN box tree.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "dd_internal.h"
@@ -16,12 +17,10 @@ struct Mat6x2 {
   double G[36];
 };
 
-// w = (F eps, G sig) for every point; flags non-finite input.
-__global__ void whiten_kernel(const double* __restrict__ strain, const double* __restrict__ stress,
-                              int64_t n, Mat6x2 M, double* __restrict__ w,
-                              int* __restrict__ bad) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Whitened row w = (F eps, G sig) of point i of a chunk; false if non-finite.
+__device__ inline bool whiten_row(const double* __restrict__ strain,
+                                  const double* __restrict__ stress, int64_t i, const Mat6x2& M,
+                                  double w[12]) {
   double e[6], s[6];
   bool ok = true;
   for (int k = 0; k < 6; ++k) {
@@ -29,25 +28,47 @@ __global__ void whiten_kernel(const double* __restrict__ strain, const double* _
     s[k] = stress[6 * i + k];
     ok = ok && isfinite(e[k]) && isfinite(s[k]);
   }
-  if (!ok) atomicOr(bad, 1);
   for (int r = 0; r < 6; ++r) {
     double a = 0.0, b = 0.0;
     for (int c = 0; c < 6; ++c) {
       a = fma(M.F[6 * r + c], e[c], a);
       b = fma(M.G[6 * r + c], s[c], b);
     }
-    w[12 * i + r] = a;
-    w[12 * i + 6 + r] = b;
+    w[r] = a;
+    w[6 + r] = b;
   }
+  return ok;
 }
 
-__global__ void sample_kernel(const double* __restrict__ w, int64_t n, int64_t stride, int64_t ns,
-                              double* __restrict__ out) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
-  int64_t i = s * stride;
-  if (i >= n) i = n - 1;
-  for (int k = 0; k < 12; ++k) out[12 * s + k] = w[12 * i + k];
+// Pass 1 over a chunk of rows first .. first+n-1: non-finite flag, max |w|
+// (non-negative doubles order like their bit patterns) and the strided sample
+// rows {s * stride : s < ns} used for the principal axes.
+__global__ __launch_bounds__(256) void stats_kernel(const double* __restrict__ strain,
+                                                    const double* __restrict__ stress, int64_t n,
+                                                    int64_t first, Mat6x2 M, int64_t stride,
+                                                    int64_t ns, double* __restrict__ samp,
+                                                    int* __restrict__ bad,
+                                                    unsigned long long* __restrict__ maxn) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double w[12];
+    if (!whiten_row(strain, stress, i, M, w)) atomicOr(bad, 1);
+    double s = 0.0;
+    for (int k = 0; k < 12; ++k) s = fma(w[k], w[k], s);
+    v = isfinite(s) ? sqrt(s) : 0.0;
+    const int64_t g = first + i;
+    if (g % stride == 0 && g / stride < ns)
+      for (int k = 0; k < 12; ++k) samp[12 * (g / stride) + k] = w[k];
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(maxn, (unsigned long long)__double_as_longlong(red[0]));
 }
 
 struct KeyParams {
@@ -58,13 +79,15 @@ struct KeyParams {
   int bits;
 };
 
-// Morton key of the point's cell in the principal-axis grid.
-__global__ void key_kernel(const double* __restrict__ w, int64_t n, KeyParams P,
+// Pass 2: Morton key of the point's cell in the principal-axis grid.
+__global__ void key_kernel(const double* __restrict__ strain, const double* __restrict__ stress,
+                           int64_t n, int64_t first, Mat6x2 M, KeyParams P,
                            uint32_t* __restrict__ keys) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double x[kDim];
-  for (int k = 0; k < kDim; ++k) x[k] = w[12 * i + k] - P.mean[k];
+  whiten_row(strain, stress, i, M, x);
+  for (int k = 0; k < kDim; ++k) x[k] -= P.mean[k];
   const int maxc = (1 << P.bits) - 1;
   uint32_t key = 0;
   int q[kKeyAxes];
@@ -76,7 +99,7 @@ __global__ void key_kernel(const double* __restrict__ w, int64_t n, KeyParams P,
   }
   for (int b = 0; b < P.bits; ++b)
     for (int a = 0; a < kKeyAxes; ++a) key |= (uint32_t)((q[a] >> b) & 1) << (b * kKeyAxes + a);
-  keys[i] = key;
+  keys[first + i] = key;
 }
 
 __global__ void invert_perm_kernel(const uint32_t* __restrict__ perm, int64_t n,
@@ -85,75 +108,52 @@ __global__ void invert_perm_kernel(const uint32_t* __restrict__ perm, int64_t n,
   if (i < n) iperm[perm[i]] = (uint32_t)i;
 }
 
-// Sorted FP64 pack and squared norms; padding rows are zero with norm +inf.
-__global__ void gather64_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
-                                int64_t n, int64_t n_pad, double* __restrict__ w64,
-                                double* __restrict__ n64) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
-  if (i < n) {
-    const double* src = w + 12 * (int64_t)perm[i];
+// Pass 3: each point's whitened row goes to its sorted position: the FP64 pack
+// with |x|^2, and the FP32 pack (round to nearest) with the FP32-rounded
+// squared norm of the stored values.
+__global__ void scatter_kernel(const double* __restrict__ strain, const double* __restrict__ stress,
+                               int64_t n, int64_t first, Mat6x2 M,
+                               const uint32_t* __restrict__ iperm, double* __restrict__ w64,
+                               double* __restrict__ n64, float* __restrict__ w32,
+                               float* __restrict__ n32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double w[12];
+  whiten_row(strain, stress, i, M, w);
+  const int64_t p = iperm[first + i];
+  if (w64) {
     double s = 0.0;
     for (int k = 0; k < 12; ++k) {
-      double v = src[k];
-      w64[12 * i + k] = v;
-      s = fma(v, v, s);
+      w64[12 * p + k] = w[k];
+      s = fma(w[k], w[k], s);
     }
-    n64[i] = s;
-  } else {
-    for (int k = 0; k < 12; ++k) w64[12 * i + k] = 0.0;
-    n64[i] = INFINITY;
+    n64[p] = s;
   }
-}
-
-// Sorted FP32 pack (round to nearest) and the exact-in-FP64 squared norm of the
-// stored values rounded to FP32; padding rows are zero with norm +inf.
-__global__ void gather32_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
-                                int64_t n, int64_t n_pad, float* __restrict__ w32,
-                                float* __restrict__ n32) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
-  if (i < n) {
-    const double* src = w + 12 * (int64_t)perm[i];
+  if (w32) {
     double s = 0.0;
     for (int k = 0; k < 12; ++k) {
-      float v = (float)src[k];
-      w32[12 * i + k] = v;
+      const float v = (float)w[k];
+      w32[12 * p + k] = v;
       s = fma((double)v, (double)v, s);
     }
-    n32[i] = (float)s;
-  } else {
-    for (int k = 0; k < 12; ++k) w32[12 * i + k] = 0.0f;
-    n32[i] = INFINITY;
+    n32[p] = (float)s;
   }
 }
 
-// max_i |x_i| over the rows (non-negative doubles order like their bit patterns).
-__global__ void max_norm_kernel(const double* __restrict__ w, int64_t n,
-                                unsigned long long* __restrict__ out) {
-  __shared__ double red[256];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v = 0.0;
-  if (i < n) {
-    double s = 0.0;
-    for (int k = 0; k < 12; ++k) s = fma(w[12 * i + k], w[12 * i + k], s);
-    v = sqrt(s);
-  }
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+// Padding rows [N, n_pad): zero with norm +inf (never a candidate).
+template <class T>
+__global__ void pad_kernel(int64_t N, int64_t n_pad, T* __restrict__ w, T* __restrict__ nrm) {
+  const int64_t i = N + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  for (int k = 0; k < 12; ++k) w[12 * i + k] = T(0);
+  nrm[i] = T(INFINITY);
 }
 
-// Per tile: centre = mean of its points (rounded to FP32), radius = max distance
-// of its points to that FP32 centre, rounded up.  One block of 256 per tile.
-__global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restrict__ w,
-                                                         const uint32_t* __restrict__ perm,
-                                                         int64_t n, int tile,
-                                                         float* __restrict__ centre,
+// Per tile of the sorted FP64 pack: centre = mean of its points (rounded to
+// FP32), radius = max distance of its points to that FP32 centre, rounded up.
+// One block of 256 per tile.
+__global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restrict__ w, int64_t n,
+                                                         int tile, float* __restrict__ centre,
                                                          float* __restrict__ radius) {
   __shared__ double red[256];
   __shared__ float cen[12];
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restric
   int cnt = (int)(last - first);
   for (int k = 0; k < 12; ++k) {
     double s = 0.0;
-    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) s += w[12 * (int64_t)perm[i] + k];
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) s += w[12 * i + k];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restric
   }
   double r = 0.0;
   for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
-    const double* x = w + 12 * (int64_t)perm[i];
+    const double* x = w + 12 * i;
     double s = 0.0;
     for (int k = 0; k < 12; ++k) {
       double d = x[k] - (double)cen[k];
@@ -201,14 +201,13 @@ __global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restric
 //   n = |x'|^2 (exact in FP64) split into three 16-bit terms.
 // Padding rows: zeros with n_hi = kPadNorm (never a candidate).
 template <class T16>
-__global__ void pack16_kernel(const double* __restrict__ w, const uint32_t* __restrict__ perm,
-                              int64_t n, int64_t n_rows, int tile,
+__global__ void pack16_kernel(const double* __restrict__ w, int64_t n, int64_t n_rows, int tile,
                               const float* __restrict__ centre, uint16_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
   uint16_t row[16];
   if (i < n) {
-    const double* x = w + 12 * (int64_t)perm[i];
+    const double* x = w + 12 * i;
     const float* c = centre + 12 * (i / tile);
     double nn = 0.0;
     for (int k = 0; k < 12; ++k) {
@@ -245,18 +244,131 @@ __global__ void pack16_kernel(const double* __restrict__ w, const uint32_t* __re
   o[1] = b;
 }
 
+// ---------------------------------------------------------------------------
+// ANN box tree.  A box bounds its points in principal-axis coordinates y = V^T x
+// (a rotation, so box distances are lower bounds of whitened distances); the
+// FP64 coordinates are rounded outward to FP32.
+// ---------------------------------------------------------------------------
+struct Rot12 {
+  double V[144];
+};
+
+__device__ inline double wave_min_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline double wave_max_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// One wavefront per leaf of kAnnLeaf consecutive sorted points.
+__global__ __launch_bounds__(256) void ann_leaf_box_kernel(const double* __restrict__ w64, int64_t N,
+                                                           Rot12 R, int64_t n_leaf,
+                                                           float* __restrict__ box) {
+  const int lane = threadIdx.x & 63;
+  const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (leaf >= n_leaf) return;
+  const int64_t i = leaf * kAnnLeaf + lane;
+  const bool v = i < N;
+  double x[12];
+  for (int k = 0; k < 12; ++k) x[k] = v ? w64[12 * i + k] : 0.0;
+  float* b = box + 24 * leaf;
+  for (int a = 0; a < 12; ++a) {
+    double y = 0.0;
+    for (int k = 0; k < 12; ++k) y = fma(R.V[12 * k + a], x[k], y);
+    const double lo = wave_min_d(v ? y : INFINITY);
+    const double hi = wave_max_d(v ? y : -INFINITY);
+    if (lane == 0) {
+      b[a] = __double2float_rd(lo);
+      b[12 + a] = __double2float_ru(hi);
+    }
+  }
+}
+
+// One wavefront per node: the box of its (up to) kAnnFan child boxes.
+__global__ __launch_bounds__(256) void ann_node_box_kernel(const float* __restrict__ child,
+                                                           int64_t n_child, int64_t n_node,
+                                                           float* __restrict__ box) {
+  const int lane = threadIdx.x & 63;
+  const int64_t node = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (node >= n_node) return;
+  const int64_t c = node * kAnnFan + lane;
+  const bool v = c < n_child;
+  for (int a = 0; a < 12; ++a) {
+    double lo = v ? (double)child[24 * c + a] : INFINITY;
+    double hi = v ? (double)child[24 * c + 12 + a] : -INFINITY;
+    lo = wave_min_d(lo);
+    hi = wave_max_d(hi);
+    if (lane == 0) {
+      box[24 * node + a] = (float)lo;
+      box[24 * node + 12 + a] = (float)hi;
+    }
+  }
+}
+
 static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
-static dd_status create_impl(const double* strain, const double* stress, int64_t N, const double* C,
-                             const dd_dataset_opts* opts, hipStream_t st, Dataset& D) {
+// Chunked access to the caller's raw (strain, stress) rows.  Creation reads
+// every row three times (statistics, keys, packs), a chunk at a time.
+struct Source {
+  int64_t chunk = 0;
+  virtual ~Source() = default;
+  // device pointers to rows first .. first+n-1 (n <= chunk), valid on st until
+  // the next call
+  virtual dd_status rows(int64_t first, int64_t n, const double** e, const double** s,
+                         hipStream_t st) = 0;
+};
+
+struct MemSource : Source {
+  const double* e;
+  const double* s;
+  MemSource(const double* e_, const double* s_, int64_t N) : e(e_), s(s_) { chunk = N; }
+  dd_status rows(int64_t first, int64_t, const double** eo, const double** so, hipStream_t) override {
+    *eo = e + 6 * first;
+    *so = s + 6 * first;
+    return DD_OK;
+  }
+};
+
+struct FillSource : Source {
+  dd_fill_fn fn;
+  void* user;
+  DevBuf be, bs;
+  FillSource(dd_fill_fn f, void* u, int64_t N) : fn(f), user(u) {
+    chunk = std::min<int64_t>(N, (int64_t)1 << 24);
+  }
+  dd_status init() {
+    DD_TRY(be.alloc(sizeof(double) * 6 * (size_t)chunk));
+    DD_TRY(bs.alloc(sizeof(double) * 6 * (size_t)chunk));
+    return DD_OK;
+  }
+  dd_status rows(int64_t first, int64_t n, const double** eo, const double** so,
+                 hipStream_t st) override {
+    const int rc = fn(user, first, n, be.as<double>(), bs.as<double>(), st);
+    if (rc != 0)
+      return set_error(DD_ERR_ARG, "data producer returned " + std::to_string(rc) + " for rows " +
+                                       std::to_string(first) + ".." + std::to_string(first + n - 1));
+    DD_HIP(hipGetLastError());
+    *eo = be.as<double>();
+    *so = bs.as<double>();
+    return DD_OK;
+  }
+};
+
+static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_dataset_opts* opts,
+                             hipStream_t st, Dataset& D) {
   uint32_t packs = (opts && opts->packs) ? opts->packs : DD_PACK_DEFAULT;
   int tile = (opts && opts->tile) ? opts->tile : 1024;
   if (tile != 128 && tile != 256 && tile != 512 && tile != 1024)
     return set_error(DD_ERR_ARG, "tile must be 128, 256, 512 or 1024");
+  if (opts && opts->reserved != 0) return set_error(DD_ERR_ARG, "dd_dataset_opts.reserved must be 0");
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN))
     return set_error(DD_ERR_ARG, "unknown pack bits");
-  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP32;
-  // the FP64 rerank reads the FP64 pack, or the FP32 pack promoted exactly
+  // the ANN walk reads the FP32 pack, its boxes and rerank the FP64 pack; the
+  // 16-bit packs are built from the sorted FP64 pack and reranked against it
+  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP32 | DD_PACK_FP64;
+  if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) packs |= DD_PACK_FP64;
   if (!(packs & (DD_PACK_FP64 | DD_PACK_FP32))) packs |= DD_PACK_FP64;
   D.N = N;
   D.packs = packs;
@@ -284,30 +396,36 @@ static dd_status create_impl(const double* strain, const double* stress, int64_t
     }
   std::memcpy(D.F, M.F, sizeof(D.F));
   std::memcpy(D.G, M.G, sizeof(D.G));
+  const int64_t CH = src.chunk;
 
-  // 1. whiten (original order)
-  DevBuf wraw, flag;
-  DD_TRY(wraw.alloc(sizeof(double) * 12 * (size_t)N));
-  DD_TRY(flag.alloc(sizeof(int)));
-  DD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-  hipLaunchKernelGGL(whiten_kernel, dim3(grid_for(N)), dim3(256), 0, st, strain, stress, N, M,
-                     wraw.as<double>(), flag.as<int>());
-  DD_HIP(hipGetLastError());
-  int bad = 0;
-  DD_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-  DD_HIP(hipStreamSynchronize(st));
-  if (bad) return set_error(DD_ERR_ARG, "data set contains non-finite strain or stress values");
-
-  // 2. principal axes of a strided sample (host, 12x12 eigenproblem)
-  int64_t ns = std::min<int64_t>(N, 65536);
-  int64_t stride = std::max<int64_t>(1, N / ns);
-  DevBuf dsamp;
+  // 1. statistics pass: finiteness, max |x|, strided sample of whitened rows
+  const int64_t ns = std::min<int64_t>(N, 65536);
+  const int64_t stride = std::max<int64_t>(1, N / ns);
+  DevBuf dsamp, flag, mx;
   DD_TRY(dsamp.alloc(sizeof(double) * 12 * (size_t)ns));
-  hipLaunchKernelGGL(sample_kernel, dim3(grid_for(ns)), dim3(256), 0, st, wraw.as<double>(), N,
-                     stride, ns, dsamp.as<double>());
+  DD_TRY(flag.alloc(sizeof(int)));
+  DD_TRY(mx.alloc(sizeof(unsigned long long)));
+  DD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  DD_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), st));
+  for (int64_t f = 0; f < N; f += CH) {
+    const int64_t n = std::min(CH, N - f);
+    const double *e, *s;
+    DD_TRY(src.rows(f, n, &e, &s, st));
+    hipLaunchKernelGGL(stats_kernel, dim3(grid_for(n)), dim3(256), 0, st, e, s, n, f, M, stride, ns,
+                       dsamp.as<double>(), flag.as<int>(), mx.as<unsigned long long>());
+    DD_HIP(hipGetLastError());
+  }
+  int bad = 0;
+  unsigned long long bitsx = 0;
+  DD_HIP(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipMemcpyAsync(&bitsx, mx.p, sizeof(bitsx), hipMemcpyDeviceToHost, st));
   std::vector<double> samp(12 * (size_t)ns);
   DD_HIP(hipMemcpyAsync(samp.data(), dsamp.p, sizeof(double) * samp.size(), hipMemcpyDeviceToHost, st));
   DD_HIP(hipStreamSynchronize(st));
+  if (bad) return set_error(DD_ERR_ARG, "data set contains non-finite strain or stress values");
+  std::memcpy(&D.xmax, &bitsx, sizeof(D.xmax));
+
+  // 2. principal axes of the sample (host, 12x12 eigenproblem)
   KeyParams P;
   {
     double mean[12] = {0};
@@ -319,10 +437,10 @@ static dd_status create_impl(const double* strain, const double* stress, int64_t
       for (int a = 0; a < 12; ++a)
         for (int b = 0; b < 12; ++b)
           cov[12 * a + b] += (samp[12 * s + a] - mean[a]) * (samp[12 * s + b] - mean[b]);
-    double ev[12], V[144];
-    sym_eigen(12, cov, ev, V);
+    double ev[12];
+    sym_eigen(12, cov, ev, D.V);
     for (int a = 0; a < kKeyAxes; ++a)
-      for (int k = 0; k < 12; ++k) P.axes[kDim * a + k] = V[12 * k + a];
+      for (int k = 0; k < 12; ++k) P.axes[kDim * a + k] = D.V[12 * k + a];
     for (int k = 0; k < 12; ++k) P.mean[k] = mean[k];
     for (int a = 0; a < kKeyAxes; ++a) {
       double lo = INFINITY, hi = -INFINITY;
@@ -340,91 +458,134 @@ static dd_status create_impl(const double* strain, const double* stress, int64_t
       D.lo[a] = lo;
       D.hi[a] = hi;
     }
-    std::memcpy(D.axes, P.axes, sizeof(D.axes));
     std::memcpy(D.mean, P.mean, sizeof(D.mean));
   }
-  // cell resolution: about 2^bits cells per axis, 6 axes -> 6*bits key bits
-  int bits = 5;
+  // cell resolution: 2^bits cells per axis, 6 axes -> 6*bits key bits
+  const int bits = 5;
   P.bits = bits;
   for (int a = 0; a < kKeyAxes; ++a) P.scale[a] *= (double)(1 << bits);
+  dsamp.release();
 
-  // 3. keys, stable sort -> permutation
-  DevBuf keys;
-  DD_TRY(keys.alloc(sizeof(uint32_t) * (size_t)N));
-  DD_TRY(D.perm.alloc(sizeof(uint32_t) * (size_t)N));
-  hipLaunchKernelGGL(key_kernel, dim3(grid_for(N)), dim3(256), 0, st, wraw.as<double>(), N, P,
-                     keys.as<uint32_t>());
-  DD_HIP(hipGetLastError());
-  DD_TRY(iota_u32(D.perm.as<uint32_t>(), N, st));
-  DD_TRY(radix_sort_pairs(keys.as<uint32_t>(), D.perm.as<uint32_t>(), N, kKeyAxes * bits, st));
-  keys.release();
+  // 3. keys pass, stable sort -> permutation and its inverse
+  {
+    DevBuf keys;
+    DD_TRY(keys.alloc(sizeof(uint32_t) * (size_t)N));
+    DD_TRY(D.perm.alloc(sizeof(uint32_t) * (size_t)N));
+    for (int64_t f = 0; f < N; f += CH) {
+      const int64_t n = std::min(CH, N - f);
+      const double *e, *s;
+      DD_TRY(src.rows(f, n, &e, &s, st));
+      hipLaunchKernelGGL(key_kernel, dim3(grid_for(n)), dim3(256), 0, st, e, s, n, f, M, P,
+                         keys.as<uint32_t>());
+      DD_HIP(hipGetLastError());
+    }
+    DD_TRY(iota_u32(D.perm.as<uint32_t>(), N, st));
+    DD_TRY(radix_sort_pairs(keys.as<uint32_t>(), D.perm.as<uint32_t>(), N, kKeyAxes * bits, st));
+  }
   DD_TRY(D.iperm.alloc(sizeof(uint32_t) * (size_t)N));
   hipLaunchKernelGGL(invert_perm_kernel, dim3(grid_for(N)), dim3(256), 0, st,
                      D.perm.as<uint32_t>(), N, D.iperm.as<uint32_t>());
   DD_HIP(hipGetLastError());
 
-  // 4. packs
-  {
-    DevBuf mx;
-    DD_TRY(mx.alloc(sizeof(unsigned long long)));
-    DD_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(max_norm_kernel, dim3(grid_for(N)), dim3(256), 0, st, wraw.as<double>(), N,
-                       mx.as<unsigned long long>());
-    unsigned long long bitsx = 0;
-    DD_HIP(hipMemcpyAsync(&bitsx, mx.p, sizeof(bitsx), hipMemcpyDeviceToHost, st));
-    DD_HIP(hipStreamSynchronize(st));
-    double xm;
-    std::memcpy(&xm, &bitsx, sizeof(xm));
-    D.xmax = xm;
-  }
+  // 4. packs pass: rows scattered to their sorted positions
   if (packs & DD_PACK_FP64) {
     D.n_pad64 = (N + kTile64 - 1) / kTile64 * kTile64;
     DD_TRY(D.w64.alloc(sizeof(double) * 12 * (size_t)D.n_pad64));
     DD_TRY(D.n64.alloc(sizeof(double) * (size_t)D.n_pad64));
-    hipLaunchKernelGGL(gather64_kernel, dim3(grid_for(D.n_pad64)), dim3(256), 0, st,
-                       wraw.as<double>(), D.perm.as<uint32_t>(), N, D.n_pad64, D.w64.as<double>(),
-                       D.n64.as<double>());
-    DD_HIP(hipGetLastError());
   }
   if (packs & DD_PACK_FP32) {
     D.n_pad32 = (N + kTile32 - 1) / kTile32 * kTile32;
     DD_TRY(D.w32.alloc(sizeof(float) * 12 * (size_t)D.n_pad32));
     DD_TRY(D.n32.alloc(sizeof(float) * (size_t)D.n_pad32));
-    hipLaunchKernelGGL(gather32_kernel, dim3(grid_for(D.n_pad32)), dim3(256), 0, st,
-                       wraw.as<double>(), D.perm.as<uint32_t>(), N, D.n_pad32, D.w32.as<float>(),
-                       D.n32.as<float>());
-    DD_HIP(hipGetLastError());
     D.xmax32 = D.xmax * (1.0 + 1e-6);
   }
+  for (int64_t f = 0; f < N; f += CH) {
+    const int64_t n = std::min(CH, N - f);
+    const double *e, *s;
+    DD_TRY(src.rows(f, n, &e, &s, st));
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(n)), dim3(256), 0, st, e, s, n, f, M,
+                       D.iperm.as<uint32_t>(), D.w64.as<double>(), D.n64.as<double>(),
+                       D.w32.as<float>(), D.n32.as<float>());
+    DD_HIP(hipGetLastError());
+  }
+  if (D.n_pad64 > N) {
+    hipLaunchKernelGGL(pad_kernel<double>, dim3(grid_for(D.n_pad64 - N)), dim3(256), 0, st, N,
+                       D.n_pad64, D.w64.as<double>(), D.n64.as<double>());
+    DD_HIP(hipGetLastError());
+  }
+  if (D.n_pad32 > N) {
+    hipLaunchKernelGGL(pad_kernel<float>, dim3(grid_for(D.n_pad32 - N)), dim3(256), 0, st, N,
+                       D.n_pad32, D.w32.as<float>(), D.n32.as<float>());
+    DD_HIP(hipGetLastError());
+  }
+
+  // 5. tile-centred 16-bit packs, from the sorted FP64 pack
   if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) {
     D.n_tiles = (N + tile - 1) / tile;
     int64_t rows = D.n_tiles * tile;
     DD_TRY(D.centre.alloc(sizeof(float) * 12 * (size_t)D.n_tiles));
     DD_TRY(D.radius.alloc(sizeof(float) * (size_t)D.n_tiles));
     hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)D.n_tiles), dim3(256), 0, st,
-                       wraw.as<double>(), D.perm.as<uint32_t>(), N, tile, D.centre.as<float>(),
-                       D.radius.as<float>());
+                       D.w64.as<double>(), N, tile, D.centre.as<float>(), D.radius.as<float>());
     DD_HIP(hipGetLastError());
     if (packs & DD_PACK_BF16) {
       DD_TRY(D.wbf16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
       hipLaunchKernelGGL(pack16_kernel<Bf16>, dim3(grid_for(rows)), dim3(256), 0, st,
-                         wraw.as<double>(), D.perm.as<uint32_t>(), N, rows, tile,
-                         D.centre.as<float>(), D.wbf16.as<uint16_t>());
+                         D.w64.as<double>(), N, rows, tile, D.centre.as<float>(),
+                         D.wbf16.as<uint16_t>());
       DD_HIP(hipGetLastError());
     }
     if (packs & DD_PACK_FP16) {
       DD_TRY(D.wfp16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
       hipLaunchKernelGGL(pack16_kernel<Fp16>, dim3(grid_for(rows)), dim3(256), 0, st,
-                         wraw.as<double>(), D.perm.as<uint32_t>(), N, rows, tile,
-                         D.centre.as<float>(), D.wfp16.as<uint16_t>());
+                         D.w64.as<double>(), N, rows, tile, D.centre.as<float>(),
+                         D.wfp16.as<uint16_t>());
       DD_HIP(hipGetLastError());
     }
+  }
+
+  // 6. ANN box tree over the sorted order
+  if (packs & DD_PACK_ANN) {
+    Rot12 R;
+    std::memcpy(R.V, D.V, sizeof(R.V));
+    int64_t n = (N + kAnnLeaf - 1) / kAnnLeaf;
+    int l = 0;
+    DD_TRY(D.ann_box[0].alloc(sizeof(float) * 24 * (size_t)n));
+    D.ann_n[0] = n;
+    hipLaunchKernelGGL(ann_leaf_box_kernel, dim3(grid_for(n, 4)), dim3(256), 0, st,
+                       D.w64.as<double>(), N, R, n, D.ann_box[0].as<float>());
+    DD_HIP(hipGetLastError());
+    while (n > kAnnFan) {
+      const int64_t m = (n + kAnnFan - 1) / kAnnFan;
+      if (l + 1 >= kAnnMaxLevels) return set_error(DD_ERR_TOO_LARGE, "ANN tree too deep");
+      DD_TRY(D.ann_box[l + 1].alloc(sizeof(float) * 24 * (size_t)m));
+      hipLaunchKernelGGL(ann_node_box_kernel, dim3(grid_for(m, 4)), dim3(256), 0, st,
+                         D.ann_box[l].as<float>(), n, m, D.ann_box[l + 1].as<float>());
+      DD_HIP(hipGetLastError());
+      ++l;
+      D.ann_n[l] = m;
+      n = m;
+    }
+    D.ann_levels = l + 1;
   }
   DD_HIP(hipStreamSynchronize(st));
   return DD_OK;
 }
 
 }  // namespace dd
+
+static dd_status finish_create(dd::Source& src, int64_t N, const double* C,
+                               const dd_dataset_opts* opts, void* hip_stream, dd_dataset** out) {
+  dd_dataset* ds = new (std::nothrow) dd_dataset();
+  if (!ds) return dd::set_error(DD_ERR_OOM, "host allocation failed");
+  dd_status st = dd::create_impl(src, N, C, opts, static_cast<hipStream_t>(hip_stream), ds->d);
+  if (st != DD_OK) {
+    delete ds;
+    return st;
+  }
+  *out = ds;
+  return DD_OK;
+}
 
 extern "C" dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev,
                                        int64_t N, const double* C, const dd_dataset_opts* opts,
@@ -433,16 +594,21 @@ extern "C" dd_status dd_dataset_create(const double* strain_dev, const double* s
   *out = nullptr;
   if (!strain_dev || !stress_dev || !C) return dd::set_error(DD_ERR_ARG, "NULL input pointer");
   if (N < 1 || N > 0x7FFFFFFFll) return dd::set_error(DD_ERR_ARG, "N must be in [1, 2^31-1]");
-  dd_dataset* ds = new (std::nothrow) dd_dataset();
-  if (!ds) return dd::set_error(DD_ERR_OOM, "host allocation failed");
-  dd_status st = dd::create_impl(strain_dev, stress_dev, N, C, opts,
-                                 static_cast<hipStream_t>(hip_stream), ds->d);
-  if (st != DD_OK) {
-    delete ds;
-    return st;
-  }
-  *out = ds;
-  return DD_OK;
+  dd::MemSource src(strain_dev, stress_dev, N);
+  return finish_create(src, N, C, opts, hip_stream, out);
+}
+
+extern "C" dd_status dd_dataset_create_streamed(int64_t N, const double* C, dd_fill_fn fill,
+                                                void* user, const dd_dataset_opts* opts,
+                                                void* hip_stream, dd_dataset** out) {
+  if (!out) return dd::set_error(DD_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!fill || !C) return dd::set_error(DD_ERR_ARG, "NULL producer or metric");
+  if (N < 1 || N > 0x7FFFFFFFll) return dd::set_error(DD_ERR_ARG, "N must be in [1, 2^31-1]");
+  dd::FillSource src(fill, user, N);
+  dd_status s = src.init();
+  if (s != DD_OK) return s;
+  return finish_create(src, N, C, opts, hip_stream, out);
 }
 
 extern "C" dd_status dd_dataset_destroy(dd_dataset* ds) {

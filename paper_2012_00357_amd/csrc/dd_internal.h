@@ -58,6 +58,9 @@ void sym_eigen(int n, const double* A, double* evals, double* V);
 // ---------------------------------------------------------------------------
 constexpr int kDim = 12;           // phase-space dimension 2M (M = 6 Voigt components)
 constexpr int kKeyAxes = 6;        // principal axes used for the spatial order
+constexpr int kAnnLeaf = 64;       // points per ANN leaf (one wavefront)
+constexpr int kAnnFan = 64;        // children per ANN tree node (one wavefront)
+constexpr int kAnnMaxLevels = 6;   // 64^6 leaves exceed any N <= 2^31 - 1
 
 struct Dataset {
   int device = 0;
@@ -86,12 +89,18 @@ struct Dataset {
   DevBuf radius;   // float [n_tiles]  upper bound of |x_j - c_T| over the tile
   DevBuf wbf16;    // uint16 [n_tiles*tile][16]
   DevBuf wfp16;    // uint16 [n_tiles*tile][16]
-  // ANN cell index (over the FP32 pack)
-  DevBuf cell_start;     // uint32 [n_cells+1]
-  int ann_bits = 0;
-  double axes[kKeyAxes * kDim];  // principal axes (rows)
+  // principal axes of the whitened data (sample estimate): V[12*k + a] is
+  // component k of axis a, axes by decreasing variance
+  double V[kDim * kDim];
   double mean[kDim];
   double lo[kKeyAxes], hi[kKeyAxes];
+  // ANN box tree over the sorted order: level 0 boxes bound leaves of kAnnLeaf
+  // consecutive points, level k+1 boxes bound kAnnFan boxes of level k; boxes
+  // are float lo[12], hi[12] in principal-axis coordinates y = V^T x, rounded
+  // outward.  The top stored level has at most kAnnFan boxes.
+  DevBuf ann_box[kAnnMaxLevels];
+  int64_t ann_n[kAnnMaxLevels] = {0};
+  int ann_levels = 0;
 
   int64_t device_bytes() const;
 };

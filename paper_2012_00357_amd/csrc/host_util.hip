@@ -118,8 +118,10 @@ void sym_eigen(int n, const double* A_in, double* evals, double* V) {
 }
 
 int64_t Dataset::device_bytes() const {
-  return (int64_t)(perm.bytes + iperm.bytes + w64.bytes + n64.bytes + w32.bytes + n32.bytes + centre.bytes +
-                   radius.bytes + wbf16.bytes + wfp16.bytes + cell_start.bytes);
+  int64_t b = (int64_t)(perm.bytes + iperm.bytes + w64.bytes + n64.bytes + w32.bytes + n32.bytes +
+                        centre.bytes + radius.bytes + wbf16.bytes + wfp16.bytes);
+  for (int l = 0; l < kAnnMaxLevels; ++l) b += (int64_t)ann_box[l].bytes;
+  return b;
 }
 
 }  // namespace dd

@@ -111,6 +111,8 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
   const int mode = opts ? opts->mode : DD_EXACT_FP64;
   const int splits = opts ? opts->splits : 0;
   if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
+  const int budget = opts ? opts->ann_budget : 0;
+  if (budget < 0) return set_error(DD_ERR_ARG, "ann_budget must be >= 0");
   switch (mode) {
     case DD_EXACT_FP64:
     case DD_DIRECT_FP64:
@@ -123,6 +125,9 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     case DD_MIXED_FP16:
       if (!(D.packs & DD_PACK_FP16) || !(D.packs & DD_PACK_FP64))
         return set_error(DD_ERR_UNSUPPORTED, "FP16 mode needs the FP16 and FP64 packs");
+      break;
+    case DD_ANN:
+      if (!(D.packs & DD_PACK_ANN)) return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
       break;
     default:
       return set_error(DD_ERR_UNSUPPORTED, "projection mode not available");
@@ -140,14 +145,17 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
   DD_TRY(sc.get(Q.u64, (size_t)m));
   DD_TRY(sc.get(Q.u32, (size_t)m));
   DD_TRY(sc.get(Q.invalid, (size_t)m));
-  int* counters = nullptr;   // [0] fb1, [1] fb2, [2..3] candidates (u64), [4..5] slow tiles (u64)
-  DD_TRY(sc.get(counters, 6));
-  DD_HIP(hipMemsetAsync(counters, 0, 6 * sizeof(int), st));
+  // [0] fb1, [1] fb2, [2..3] candidates (u64), [4..5] slow tiles (u64),
+  // [6..13] ANN: points visited, boxes tested, leaves visited, candidates (u64 each)
+  int* counters = nullptr;
+  DD_TRY(sc.get(counters, 14));
+  DD_HIP(hipMemsetAsync(counters, 0, 14 * sizeof(int), st));
   DD_TRY(prepare_queries(D, states_dev, whitened, m, warm_start_idx_dev, Q, st));
   Outputs out{idx_out_dev, dist_out_dev};
   QueryList all{nullptr, nullptr, m};
   int64_t n_fallback = 0;
   int64_t n_items_host = 0;
+  unsigned long long* ann = nullptr;
 
   if (mode == DD_DIRECT_FP64) {
     DD_TRY(timing.mark(1, st));
@@ -155,6 +163,21 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     DD_TRY(timing.mark(2, st));
   } else if (mode == DD_EXACT_FP64) {
     DD_TRY(exact64(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));
+  } else if (mode == DD_ANN) {
+    int* fb = nullptr;
+    DD_TRY(sc.get(fb, (size_t)m));
+    ann = reinterpret_cast<unsigned long long*>(counters + 6);
+    DD_TRY(timing.mark(1, st));
+    DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann, st));
+    DD_TRY(timing.mark(2, st));
+    int h = 0;
+    DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    n_fallback += h;
+    if (h > 0) {
+      QueryList L1{fb, counters, h};
+      DD_TRY(exact64(D, Q, L1, h, 0, out, sc, counters, st, nullptr, nullptr));
+    }
   } else {
     const bool fp16 = (mode == DD_MIXED_FP16);
     int64_t qblocks = (m + 255) / 256;
@@ -224,15 +247,20 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
   }
   if (opts && opts->stats) {
     unsigned long long nc = 0;
+    unsigned long long a[4] = {0, 0, 0, 0};
     DD_HIP(hipMemcpyAsync(&nc, counters + 2, sizeof(nc), hipMemcpyDeviceToHost, st));
+    if (ann) DD_HIP(hipMemcpyAsync(a, ann, sizeof(a), hipMemcpyDeviceToHost, st));
     DD_TRY(timing.mark(3, st));
     DD_HIP(hipStreamSynchronize(st));
+    nc += a[3];
     float scan_ms = 0.0f, total_ms = 0.0f;
     DD_HIP(hipEventElapsedTime(&scan_ms, timing.ev[1], timing.ev[2]));
     DD_HIP(hipEventElapsedTime(&total_ms, timing.ev[0], timing.ev[3]));
     opts->stats->candidates = (int64_t)nc;
     opts->stats->overflowed = n_fallback;
-    opts->stats->visited = 0;
+    opts->stats->visited = (int64_t)a[0];
+    opts->stats->boxes = (int64_t)a[1];
+    opts->stats->leaves = (int64_t)a[2];
     opts->stats->scan_ms = scan_ms;
     opts->stats->total_ms = total_ms;
     opts->stats->slow_tiles = n_items_host;
@@ -241,10 +269,11 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
 }
 
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
-                           const int64_t* warm_dev, int mode, int64_t* idx_out, double* dist_out,
-                           hipStream_t st) {
+                           const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
+                           double* dist_out, hipStream_t st) {
   dd_project_opts o{};
   o.mode = mode;
+  o.ann_budget = ann_budget;
   return project_impl(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, st);
 }
 

@@ -82,6 +82,14 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
 
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
 
+// DD_ANN walk over the dataset's box tree for the queries of L (one wavefront
+// each): writes outputs, appends overflowed queries to fb_list / fb_count, adds
+// (points visited, boxes tested, leaves visited, candidates reranked) to
+// counters[0..3].  budget = max leaves per query, 0 = exact.
+dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
+                          const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
+                          unsigned long long* counters, hipStream_t st);
+
 // u32[q] = min(u32[q], min over the S split bounds U[p][S]).
 dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U, int S, float* u32,
                                hipStream_t st);

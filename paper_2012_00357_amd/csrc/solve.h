@@ -19,8 +19,8 @@ struct FEMesh {
 
 // P_D of whitened states (already in the dataset's coordinates).
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
-                           const int64_t* warm_dev, int mode, int64_t* idx_out, double* dist_out,
-                           hipStream_t st);
+                           const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
+                           double* dist_out, hipStream_t st);
 
 class DDSolver {
  public:
@@ -39,6 +39,7 @@ class DDSolver {
   const Dataset* ds = nullptr;
   hipStream_t st = nullptr;
   int mode = DD_EXACT_FP64;
+  int ann_budget = 0;
   double cg_tol = 1e-13;
   int cg_max_iter = 20000;
   int64_t nnz = 0;

@@ -558,6 +558,9 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   M.init(mesh);
   this->st = st;
   mode = opts ? opts->mode : DD_EXACT_FP64;
+  ann_budget = opts ? opts->ann_budget : 0;
+  if (ann_budget < 0 || (opts && opts->reserved != 0))
+    return set_error(DD_ERR_ARG, "dd_solve_opts: ann_budget must be >= 0 and reserved 0");
   use_graph = !(opts && (opts->flags & DD_SOLVE_NO_GRAPH));
   cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
   cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
@@ -718,6 +721,9 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   auto t0 = std::chrono::steady_clock::now();
   int it = 0;
   bool converged = false;
+  int stop_reason = 0;
+  double prev_full = INFINITY;
+  const bool approximate = (mode == DD_ANN && ann_budget > 0);
   int64_t cg_total = 0;
   double cg_res_max = 0.0;
   if (res && res->history) {
@@ -725,7 +731,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   }
   for (it = 1; it <= max_iter; ++it) {
     DD_TRY(constraint_projection());
-    DD_TRY(project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode,
+    DD_TRY(project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, ann_budget,
                             d_idx_new.as<int64_t>(), d_dist.as<double>(), st));
     hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
                        d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
@@ -755,13 +761,22 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     std::swap(d_idx.p, d_idx_new.p);
     if (sc[2] == 0.0) {
       converged = true;
+      stop_reason = 1;
       break;
     }
+    // an approximate projection gives no descent guarantee: stop once the
+    // distance to the data stops decreasing
+    if (approximate && it > 1 && !(sc[1] < prev_full)) {
+      stop_reason = 2;
+      break;
+    }
+    prev_full = sc[1];
   }
   if (it > max_iter) it = max_iter;
   if (res) {
     res->iterations = it;
     res->converged = converged ? 1 : 0;
+    res->stop_reason = stop_reason;
     res->cg_iterations = cg_total;
     res->cg_max_residual = cg_res_max;
     if (res->u) DD_HIP(hipMemcpyAsync(res->u, d_x.p, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
@@ -790,7 +805,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     res->elapsed_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
-  return converged ? DD_OK : set_error(DD_ERR_NOT_CONVERGED, "dd_solve reached max_iter");
+  return stop_reason != 0 ? DD_OK : set_error(DD_ERR_NOT_CONVERGED, "dd_solve reached max_iter");
 }
 
 }  // namespace dd

@@ -1,0 +1,122 @@
+"""GPU tests of the ANN path (box-tree walk) and of the streamed dataset
+creation it relies on at large N, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import ddsynth
+import oracle
+from gpu_util import compare_to_oracle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32, BF16, ANN = 0x1, 0x2, 0x4, 0x10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2012_00357_amd import _lib
+    return _lib
+
+
+def test_device_generator_matches_host_bits():
+    """The GPU twin of the data-point recipe writes the host generator's bits."""
+    import torch
+    gen = ddsynth.DevicePoints(1003)
+    for first, n in ((0, 1000), (123456789, 777), (999_999_000, 1000)):
+        _say("generator bits", first, n)
+        e_d, s_d = gen.generate(first, n)
+        torch.cuda.synchronize()
+        e_h, s_h = ddsynth.data_points(n, 1003, first=first)
+        assert np.array_equal(e_d.cpu().numpy().view(np.uint64), e_h.view(np.uint64))
+        assert np.array_equal(s_d.cpu().numpy().view(np.uint64), s_h.view(np.uint64))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 70001])
+def test_streamed_create_equals_in_memory(L, C0, n):
+    """dd_dataset_create_streamed (device producer, chunked reads) builds the same
+    dataset as dd_dataset_create on the same points: equal results in every mode."""
+    import torch
+    _say("streamed vs in-memory", n)
+    gen = ddsynth.DevicePoints(77)
+    e, s = gen.generate(0, n)
+    packs = FP64 | BF16 | ANN
+    ds_mem = L.dd_dataset_create(e, s, C0, packs=packs)
+    ds_str = L.dd_dataset_create_streamed(n, C0, gen.fill_fn, gen.user, packs=packs)
+    assert ds_mem.info() == ds_str.info()
+    he, hs = ddsynth.data_points(n, 77)
+    qe, qs, _ = ddsynth.queries(he, hs, 300, 78)
+    states = to_dev(ddsynth.states(qe, qs))
+    for mode in ("fp64", "bf16", "ann"):
+        i1, d1 = L.dd_project(ds_mem, states, mode=mode)
+        i2, d2 = L.dd_project(ds_str, states, mode=mode)
+        assert torch.equal(i1, i2) and torch.equal(d1, d2), mode
+    oi, od, o2 = oracle.pd_raw(he, hs, C0, qe, qs)
+    compare_to_oracle(i2.cpu().numpy(), d2.cpu().numpy(), oi, od, o2)
+
+
+@pytest.fixture(scope="module")
+def config0(L, C0):
+    e, s = ddsynth.data_points(65536, 1000)
+    qe, qs, base = ddsynth.queries(e, s, 4096, 2000)
+    oi, od, o2 = oracle.pd_raw(e, s, C0, qe, qs)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN)
+    return dict(e=e, s=s, oi=oi, od=od, o2=o2, base=base, ds=ds,
+                states=to_dev(ddsynth.states(qe, qs)))
+
+
+def test_ann_exact_without_budget(L, config0):
+    """Budget 0: the walk is exact, with or without a warm start."""
+    import torch
+    ds, states = config0["ds"], config0["states"]
+    idx, dist, st = L.dd_project(ds, states, mode="ann", stats=True)
+    _say("ann exact stats", st)
+    compare_to_oracle(idx.cpu().numpy(), dist.cpu().numpy(), config0["oi"], config0["od"],
+                      config0["o2"])
+    assert st["visited"] > 0 and st["leaves"] > 0 and st["boxes"] > 0
+    for warm in (to_dev(config0["base"]), to_dev(np.zeros(4096, np.int64)), idx.clone()):
+        i2, d2 = L.dd_project(ds, states, warm_start_idx=warm, mode="ann")
+        assert torch.equal(i2, idx) and torch.equal(d2, dist)
+
+
+def test_ann_warm_start_reduces_work(L, config0):
+    ds, states = config0["ds"], config0["states"]
+    idx, _, cold = L.dd_project(ds, states, mode="ann", stats=True)
+    _, _, warm = L.dd_project(ds, states, warm_start_idx=idx.clone(), mode="ann", stats=True)
+    _say("cold", cold, "warm", warm)
+    assert warm["visited"] <= cold["visited"]
+
+
+def test_ann_budget_is_never_worse_than_warm_start(L, config0, C0):
+    """A budgeted walk is approximate but never returns a point farther than the
+    warm-start point nor nearer than the exact one (to FP64 rounding); recall
+    grows with the budget and is reported."""
+    ds, states = config0["ds"], config0["states"]
+    st_np = states.cpu().numpy()
+    rng = np.random.default_rng(5)
+    warm = rng.integers(0, 65536, 4096).astype(np.int64)
+    wd = oracle.pair_dist_raw(st_np[:, :6], st_np[:, 6:], config0["e"][warm], config0["s"][warm], C0)
+    recalls = []
+    for budget in (1, 2, 4, 16, 64):
+        idx, dist, st = L.dd_project(ds, states, warm_start_idx=to_dev(warm), mode="ann",
+                                     ann_budget=budget, stats=True)
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        got = oracle.pair_dist_raw(st_np[:, :6], st_np[:, 6:], config0["e"][idx],
+                                   config0["s"][idx], C0)
+        recall = float(np.mean(idx == config0["oi"]))
+        recalls.append(recall)
+        _say(f"budget {budget}: recall {recall:.4f}, leaves/query {st['leaves'] / 4096:.2f}, "
+             f"visited/query {st['visited'] / 4096:.1f}, overflowed {st['overflowed']}")
+        assert st["leaves"] <= budget * 4096
+        np.testing.assert_allclose(dist, got, rtol=1e-12)         # reported distance is exact
+        assert np.all(got <= wd * (1 + 1e-12))                    # never worse than warm
+        assert np.all(got >= config0["od"] * (1 - 1e-12))         # never better than exact
+    assert recalls[-1] >= recalls[0] and recalls[-1] > 0.9

@@ -10,8 +10,8 @@ from gpu_util import compare_to_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["direct", "fp64", "bf16", "fp16"]
-ALL_PACKS = 0x1 | 0x4 | 0x8
+MODES = ["direct", "fp64", "bf16", "fp16", "ann"]
+ALL_PACKS = 0x1 | 0x4 | 0x8 | 0x10
 
 
 @pytest.fixture(scope="module")
@@ -114,7 +114,8 @@ def test_ragged_sizes(L, C0, n, m, tile, mode):
 @pytest.mark.parametrize("mode", MODES)
 def test_queries_on_data_points_and_duplicates(L, C0, mode):
     """A query equal to a data point is at distance 0; among duplicates (more of
-    them than any candidate list holds) the lowest index wins."""
+    them than any candidate list holds, so the overflow fallback runs) the
+    lowest index wins."""
     _say("duplicates", mode)
     n = 6000
     e, s = ddsynth.data_points(n, 77)
@@ -165,6 +166,12 @@ def test_error_paths(L, C0):
         L.dd_dataset_create(to_dev(e2), to_dev(s), C0)
     assert ex.value.status == 1
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1)
+    for mode in ("bf16", "fp16", "ann"):
+        with pytest.raises(L.DDError) as ex:
+            L.dd_project(ds, torch.zeros((3, 12), dtype=torch.float64, device="cuda"), mode=mode)
+        assert ex.value.status == 8
+    ds2 = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x10)
     with pytest.raises(L.DDError) as ex:
-        L.dd_project(ds, torch.zeros((3, 12), dtype=torch.float64, device="cuda"), mode="bf16")
-    assert ex.value.status == 8
+        L.dd_project(ds2, torch.zeros((3, 12), dtype=torch.float64, device="cuda"), mode="ann",
+                     ann_budget=-1)
+    assert ex.value.status == 1

@@ -26,12 +26,13 @@ def _problem(n, N, seed, traction=100.0):
     return e, s, m, mask, f, init
 
 
-@pytest.mark.parametrize("mode", ["fp64", "bf16"])
+@pytest.mark.parametrize("mode", ["fp64", "bf16", "ann"])
 def test_dd_solve_matches_oracle_trajectory(L, C0, mode):
-    """Same association at every iteration, same iteration count, same u."""
+    """Same association at every iteration, same iteration count, same u (the
+    ANN walk without a budget is exact)."""
     e, s, m, mask, f, init = _problem(3, 20000, 51)
     ref = fe.dd_solve(e, s, C0, m, mask, f, init, record_history=True)
-    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4 | 0x10)
     got = L.dd_solve(ds, (3, 3, 3), mask, f, init, mode=mode, history=True)
     print(f"iters oracle {ref.iterations} gpu {got['iterations']}, cg {got['cg_iterations']}, "
           f"res {got['cg_max_residual']:.2e}, {got['elapsed_ms']:.1f} ms", flush=True)

@@ -34,6 +34,24 @@ def test_philox_known_answers():
                                                            123456789012 >> 32], np.uint32)))
 
 
+def test_generator_elementary_functions():
+    """The generator's own log and cos/sin(2 pi u) (shared by its host and GPU
+    builds) agree with the C library to a few units in the last place."""
+    rng = np.random.default_rng(0)
+    u = np.concatenate([rng.random(200000), [2.0 ** -53, 0.25, 0.5, 0.75, 1.0 - 2.0 ** -53],
+                        np.arange(1, 64) / 64.0])
+    el = ddsynth.elementary(u)
+    ref_log = np.log(u)
+    assert np.all(np.abs(el[:, 0] - ref_log) <= 4 * np.spacing(np.abs(ref_log)) + 1e-300)
+    # 2 pi u is itself rounded in the library reference: compare absolutely
+    assert np.abs(el[:, 1] - np.cos(2 * np.pi * u)).max() < 2e-15
+    assert np.abs(el[:, 2] - np.sin(2 * np.pi * u)).max() < 2e-15
+    assert el[u == 0.25, 1][0] == 0.0 and el[u == 0.5, 2][0] == 0.0
+    z = ddsynth.box_muller(rng.random(400000), rng.random(400000)).ravel()
+    assert abs(z.mean()) < 5e-3 and abs(z.std() - 1.0) < 5e-3
+    assert abs(np.mean(z ** 4) - 3.0) < 0.05
+
+
 def test_generator_moments(C0):
     e, s = ddsynth.data_points(200000, 1000)
     assert e.min() >= -1e-3 and e.max() < 1e-3
