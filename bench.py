@@ -2,6 +2,7 @@
 """Benchmark of the DD projection hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-fp64]
+                    [--skip-ann | --ann-only]
 
 Workload (one step = one projection P_D of the whole query batch through the
 C ABI): N = 2^27 synthetic material data points, m = 65536 query states, BF16
@@ -9,7 +10,8 @@ MFMA scan on tile-centred data with certified candidates reranked in FP64
 (indices equal to the FP64 nearest neighbour).  The plain FP64 MFMA scan of the
 same batch is timed beside it.  Inputs are resident in HBM before timing; the
 dataset (whitening, spatial order, packs) is built once, outside the timed
-region.  Prints one JSON line.
+region.  Beside the headline: DD solve latency (8^3 hex, N = 1e6) and the ANN
+walk at N = 10^9 (exact and budgeted, 16^3 DD solve).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -35,9 +37,17 @@ def measured_traffic(mode, tile, N, m):
     """HBM bytes per launch of the main scan kernel from the committed rocprofv3
     counter summary, or None when that summary is for another kernel, workload
     or an older version of the kernel source."""
+    if mode != "bf16":
+        return None
+    return profile_traffic("scan16_pass_bf16_N2e27_m65536.md", f"N={N} m={m} tile={tile}")
+
+
+def profile_traffic(name, workload):
+    """traffic_bytes_per_launch of a committed profile summary when its workload
+    matches and the profiled kernel source is unchanged, else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "scan16_pass_bf16_N2e27_m65536.md")
-    if mode != "bf16" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
@@ -52,7 +62,7 @@ def measured_traffic(mode, tile, N, m):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != fields.get("source_sha256_16"):
         return None
-    if fields.get("workload") != f"N={N} m={m} tile={tile}":
+    if fields.get("workload") != workload:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -94,6 +104,89 @@ def dd_solve_latency(L, C, R):
     return out
 
 
+ANN_BYTES_PER_POINT = 48.0    # FP32 whitened row read per visited point
+ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per tested box
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
+
+
+def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
+    """ANN at scale: N = 10^9 points generated on the device (streamed into the
+    dataset), m = 32768 queries around generated points; exact walks cold and
+    warm-started from the exact answer (the steady state of the DD loop), a few
+    budgets with the generating point as warm start, and the 16^3 DD solve."""
+    import numpy as np
+    import torch
+
+    import ddsynth
+    N, m = 1_000_000_000, 32768
+    gen = ddsynth.DevicePoints(1003)
+    torch.cuda.synchronize()
+    t = time.time()
+    ds = L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user, packs=0x1 | 0x10)
+    torch.cuda.synchronize()
+    create_s = time.time() - t
+    qe, qs, base = ddsynth.queries_generated(N, 1003, m, 2003)
+    states = torch.from_numpy(ddsynth.states(qe, qs)).cuda()
+    out = {"workload": "ANN walk, N=1e9 (generated on device, streamed), m=32768 queries",
+           "N": N, "m": m, "dataset_create_s": round(create_s, 3),
+           "dataset_gb": round(ds.info()[1] / 1e9, 2)}
+
+    def run(warm, budget):
+        walk, tot, vis, box = [], [], 0, 0
+        L.dd_project(ds, states, warm_start_idx=warm, mode="ann", ann_budget=budget)
+        for _ in range(steps):
+            i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode="ann",
+                                    ann_budget=budget, stats=True)
+            walk.append(st["scan_ms"])
+            tot.append(st["total_ms"])
+            vis += st["visited"]
+            box += st["boxes"]
+        w, tt = sum(walk) / steps, sum(tot) / steps
+        byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_BOX * box) / steps
+        return i, d, {"walk_ms": round(w, 3), "total_ms": round(tt, 3),
+                      "proj_per_s": round(m / (tt / 1e3), 1),
+                      "points_per_query": round(vis / steps / m, 1),
+                      "boxes_per_query": round(box / steps / m, 1),
+                      "algorithmic_bytes_per_launch": round(byts), "achieved_gbs": round(byts / w / 1e6, 1)}
+
+    ie, de, cold = run(None, 0)
+    _, _, warm = run(ie.clone(), 0)
+    out["exact_cold"], out["exact_warm"] = cold, warm
+    out["roofline"] = {"bound": "hbm", "achieved": warm["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(warm["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                       "traffic": profile_traffic("ann_walk_N1e9_m32768.md",
+                                                  f"N={N} m={m} exact warm"),
+                       "kernel": "ann_walk_kernel (exact, warm-started)",
+                       "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_box": ANN_BYTES_PER_BOX}
+    log(f"ann 1e9: create {create_s:.2f}s, exact cold {cold['walk_ms']} ms, warm {warm['walk_ms']} ms "
+        f"({warm['achieved_gbs']} GB/s)")
+    wb = torch.from_numpy(base).cuda()
+    out["budgeted"] = {}
+    for b in budgets:
+        ib, db, r = run(wb, b)
+        r["recall"] = round(float((ib == ie).double().mean()), 4)
+        r["mean_rel_dist_excess"] = float(((db - de) / de).mean())
+        out["budgeted"][str(b)] = r
+        log(f"ann 1e9 budget {b}: recall {r['recall']}, walk {r['walk_ms']} ms")
+    if not solve:
+        ds.close()
+        return out
+    n = 16
+    mask, force = ddsynth.box_bc(n, 100.0)
+    init = ddsynth.indices(8 * n ** 3, N, 7)
+    L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann")
+    t = time.time()
+    r = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann")
+    solve_ms = (time.time() - t) * 1e3
+    out["dd_solve_16cube"] = {"workload": "16^3 hex (32768 material points), clamp + 100 MPa, "
+                                          "exact ANN projections",
+                              "ms": round(solve_ms, 1), "iterations": r["iterations"],
+                              "converged": bool(r["converged"])}
+    log(f"ann 1e9 dd_solve 16^3: {solve_ms:.0f} ms, {r['iterations']} iterations")
+    ds.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +203,11 @@ def main():
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--dd-solves", type=int, default=20,
                     help="DD solves (8^3 hex, N=1e6) timed for the p50/p99 latency leg; 0 = skip")
+    ap.add_argument("--skip-ann", action="store_true", help="skip the N=1e9 ANN leg")
+    ap.add_argument("--ann-only", action="store_true",
+                    help="run only the N=1e9 ANN leg and print its JSON object")
+    ap.add_argument("--ann-no-solve", action="store_true",
+                    help="with --ann-only: leave out the 16^3 DD solve (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -127,6 +225,10 @@ def main():
     torch.cuda.set_device(0)
     N, m = 1 << args.log2n, args.m
     C = ddsynth.isotropic_stiffness()
+    if args.ann_only:
+        print(json.dumps({"ann": ann_leg(L, C, args.steps, solve=not args.ann_no_solve)}),
+              flush=True)
+        return
     t = time.time()
     e, s = ddsynth.data_points(N, 1002)
     qe, qs, _ = ddsynth.queries(e, s, m, 2002)
@@ -211,6 +313,12 @@ def main():
     if args.dd_solves > 0:
         dd = dd_solve_latency(L, C, args.dd_solves)
 
+    ann = None
+    if not args.skip_ann:
+        ds.close()
+        torch.cuda.empty_cache()
+        ann = ann_leg(L, C, args.steps)
+
     cpu = None
     if not args.skip_cpu:
         import oracle
@@ -241,6 +349,7 @@ def main():
         "roofline": roofline,
         "fp64_scan": fp64,
         "dd_solve": dd,
+        "ann": ann,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

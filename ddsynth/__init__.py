@@ -79,10 +79,11 @@ def _load():
         lib.ddsynth_indices.argtypes = [u64, i64, i64, vp]
         lib.ddsynth_uniform.argtypes = [u64, i64, dbl, dbl, vp]
         lib.ddsynth_box_muller.argtypes = [vp, vp, i64, vp]
+        lib.ddsynth_queries_gen.argtypes = [u64, i64, u64, i64, dbl, vp, dbl, dbl, dbl, vp, vp, vp]
         lib.ddsynth_elementary.argtypes = [vp, i64, vp]
         for f in ("ddsynth_philox", "ddsynth_philox_many", "ddsynth_points",
                   "ddsynth_queries", "ddsynth_indices", "ddsynth_uniform",
-                  "ddsynth_box_muller", "ddsynth_elementary"):
+                  "ddsynth_box_muller", "ddsynth_elementary", "ddsynth_queries_gen"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -162,6 +163,22 @@ def queries(strain: np.ndarray, stress: np.ndarray, m: int, seed: int,
     base = np.empty(m, dtype=np.int64)
     _load().ddsynth_queries(seed, m, _ptr(strain), _ptr(stress), strain.shape[0], eps_std,
                             sig_std, _ptr(qe), _ptr(qs), _ptr(base))
+    return qe, qs, base
+
+
+def queries_generated(n_data: int, data_seed: int, m: int, seed: int,
+                      S0: np.ndarray | None = None, eps_amp: float = EPS_AMP,
+                      noise_std: float = DATA_NOISE_STD, eps_std: float = QUERY_EPS_STD,
+                      sig_std: float = QUERY_SIG_STD):
+    """As `queries` for the data set data_points(n_data, data_seed) without
+    holding it: each base point is regenerated from its index.  The result
+    equals queries(*data_points(n_data, data_seed), m, seed)."""
+    S0 = isotropic_stiffness() if S0 is None else np.ascontiguousarray(S0, dtype=np.float64)
+    qe = np.empty((m, 6), dtype=np.float64)
+    qs = np.empty((m, 6), dtype=np.float64)
+    base = np.empty(m, dtype=np.int64)
+    _load().ddsynth_queries_gen(seed, m, data_seed, n_data, eps_amp, _ptr(S0), noise_std, eps_std,
+                                sig_std, _ptr(qe), _ptr(qs), _ptr(base))
     return qe, qs, base
 
 

@@ -85,6 +85,42 @@ void ddsynth_queries(uint64_t seed, int64_t m, const double* strain, const doubl
   }
 }
 
+/*
+ * Query states around generated data points, for data sets too large to hold
+ * on the host: the base point j (stream 16) is regenerated from the data-point
+ * recipe (data_seed, item j), then perturbed as in ddsynth_queries.
+ */
+void ddsynth_queries_gen(uint64_t seed, int64_t m, uint64_t data_seed, int64_t n_data,
+                         double eps_amp, const double* S0, double noise_std, double eps_std,
+                         double sig_std, double* q_strain, double* q_stress, int64_t* base) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    uint32_t a[4];
+    dds_block(seed, (uint64_t)i, 16u, a);
+    double u = dds_u53(a[0], a[1]);
+    int64_t j = (int64_t)(u * (double)n_data);
+    if (j >= n_data) j = n_data - 1;
+    base[i] = j;
+    double e[6], s[6];
+    dds_point(data_seed, (uint64_t)j, eps_amp, S0, noise_std, e, s);
+    double ua[4], ub[4], uc[4];
+    dds_uniforms4(seed, (uint64_t)i, 18u, ua);
+    dds_uniforms4(seed, (uint64_t)i, 20u, ub);
+    dds_uniforms4(seed, (uint64_t)i, 22u, uc);
+    double z[12];
+    dds_box_muller(ua[0], ua[1], &z[0], &z[1]);
+    dds_box_muller(ua[2], ua[3], &z[2], &z[3]);
+    dds_box_muller(ub[0], ub[1], &z[4], &z[5]);
+    dds_box_muller(ub[2], ub[3], &z[6], &z[7]);
+    dds_box_muller(uc[0], uc[1], &z[8], &z[9]);
+    dds_box_muller(uc[2], uc[3], &z[10], &z[11]);
+    for (int k = 0; k < 6; ++k) {
+      q_strain[6 * i + k] = e[k] + eps_std * z[k];
+      q_stress[6 * i + k] = s[k] + sig_std * z[6 + k];
+    }
+  }
+}
+
 /* Uniform indices over [0, n_data) for items 0..n-1 (stream 32). */
 void ddsynth_indices(uint64_t seed, int64_t n, int64_t n_data, int64_t* out) {
 #pragma omp parallel for schedule(static)

@@ -52,6 +52,14 @@ def test_generator_elementary_functions():
     assert abs(np.mean(z ** 4) - 3.0) < 0.05
 
 
+def test_generated_queries_match_stored_queries():
+    e, s = ddsynth.data_points(5000, 91)
+    a = ddsynth.queries(e, s, 700, 92)
+    b = ddsynth.queries_generated(5000, 91, 700, 92)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
 def test_generator_moments(C0):
     e, s = ddsynth.data_points(200000, 1000)
     assert e.min() >= -1e-3 and e.max() < 1e-3
