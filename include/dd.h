@@ -272,6 +272,83 @@ dd_status dd_solve(const dd_dataset* ds, const dd_mesh* mesh, const uint8_t* dir
                    const double* nodal_force, const int64_t* init_idx, const dd_solve_opts* opts,
                    dd_solve_result* result, void* hip_stream);
 
+/*
+ * Serving: DD solves of different meshes against one resident dataset, their
+ * projections batched across solves (continuous batching).  A server runs two
+ * host threads: a scheduler that admits queued solves in arrival order while
+ * their device footprint fits the budget and advances every admitted solve on
+ * its own HIP stream, and a projection thread that runs one P_D batch at a
+ * time over the admissible states of every solve that is ready (a large mesh
+ * may span several batches).  Each solve computes exactly what dd_solve
+ * computes, so its result is the same alone and in any mix.
+ */
+typedef struct dd_server dd_server;
+
+typedef struct dd_server_opts {
+  int32_t mode;          /* dd_mode of every projection (the dataset must hold its pack) */
+  int32_t max_active;    /* solves admitted at once; 0 = 64 */
+  int32_t max_batch;     /* queries per projection batch; 0 = 65536 */
+  int32_t max_queue;     /* submitted, not yet admitted solves; 0 = 4096 */
+  int32_t ann_budget;    /* DD_ANN budget (0 = exact walk) */
+  int32_t reserved;      /* must be 0 */
+} dd_server_opts;
+
+typedef struct dd_solve_request {
+  dd_mesh mesh;                   /* as for dd_solve */
+  const uint8_t* dirichlet_mask;  /* host [ndof]; copied by dd_server_submit */
+  const double* nodal_force;      /* host [ndof]; copied */
+  const int64_t* init_idx;        /* host [n_mp]; copied */
+  int32_t max_iter;               /* 0 = 500 */
+  int32_t reserved;               /* must be 0 */
+  double deadline_s;              /* > 0: cancelled when still running this long after submit */
+} dd_solve_request;
+
+typedef struct dd_server_stats {
+  int64_t submitted, completed, failed, rejected, cancelled;
+  int64_t active, queued;           /* admitted solves now; submitted, not yet admitted */
+  int64_t batches, queries;         /* projection batches run; material points projected */
+  int64_t peak_active, peak_bytes;  /* most solves admitted at once; most footprint bytes in use */
+  int64_t budget_bytes;             /* the admission budget */
+  double proj_p50_ms, proj_p99_ms;  /* per projection: a solve's state ready -> association back */
+  double solve_p50_ms, solve_p99_ms;  /* per solve: submit -> result ready */
+  double queue_p50_ms, queue_p99_ms;  /* per solve: submit -> admission */
+  double queries_per_s;             /* queries / elapsed_s */
+  double elapsed_s;                 /* since the first submit */
+} dd_server_stats;
+
+/*
+ * Create a server over ds (which must outlive it).  hbm_budget_bytes bounds the
+ * summed device footprint of admitted solves (their P_C buffers, states and
+ * projection scratch); 0 = half of the free device memory.  opts NULL = BF16
+ * projections, defaults above.  Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED (mode
+ * without its pack), DD_ERR_OOM, DD_ERR_DEVICE.
+ */
+dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_bytes,
+                           const dd_server_opts* opts, dd_server** out);
+
+/* Queue a solve (non-blocking; inputs are copied).  *ticket identifies it.
+ * Errors: DD_ERR_ARG (invalid request, as dd_solve), DD_ERR_TOO_LARGE (its
+ * footprint exceeds the whole budget, or the queue is full: rejected). */
+dd_status dd_server_submit(dd_server* srv, const dd_solve_request* req, uint64_t* ticket);
+
+/* Wait for a solve: timeout_s < 0 waits without limit, 0 polls.  On completion
+ * fills result (host arrays as for dd_solve; history is not recorded) and
+ * releases the ticket; returns the solve's status (DD_OK, DD_ERR_NOT_CONVERGED,
+ * DD_ERR_CANCELLED, or the error that stopped it; other solves are not
+ * affected).  DD_ERR_TIMEOUT leaves the ticket valid; DD_ERR_ARG for an
+ * unknown ticket. */
+dd_status dd_server_wait(dd_server* srv, uint64_t ticket, dd_solve_result* result, double timeout_s);
+
+/* Ask a queued or running solve to stop; its wait returns DD_ERR_CANCELLED. */
+dd_status dd_server_cancel(dd_server* srv, uint64_t ticket);
+
+/* Counters and latency percentiles since creation. */
+dd_status dd_server_get_stats(dd_server* srv, dd_server_stats* stats);
+
+/* Stop the threads; unfinished solves end as DD_ERR_CANCELLED (their tickets
+ * become invalid). */
+dd_status dd_server_destroy(dd_server* srv);
+
 /* Thread-local message for the calling thread's last non-OK status. */
 const char* dd_last_error(void);
 

@@ -288,3 +288,142 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
                cg_iterations=res.cg_iterations,
                cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+class dd_server_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("ann_budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class dd_solve_request(ctypes.Structure):
+    _fields_ = [("mesh", dd_mesh), ("dirichlet_mask", ctypes.c_void_p),
+                ("nodal_force", ctypes.c_void_p), ("init_idx", ctypes.c_void_p),
+                ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("deadline_s", ctypes.c_double)]
+
+
+class dd_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("submitted", "completed", "failed", "rejected", "cancelled", "active", "queued",
+                 "batches", "queries", "peak_active", "peak_bytes", "budget_bytes")] + \
+               [(k, ctypes.c_double) for k in
+                ("proj_p50_ms", "proj_p99_ms", "solve_p50_ms", "solve_p99_ms", "queue_p50_ms",
+                 "queue_p99_ms", "queries_per_s", "elapsed_s")]
+
+
+_lib.dd_server_create.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(dd_server_opts),
+                                  ctypes.POINTER(ctypes.c_void_p)]
+_lib.dd_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_solve_request),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+_lib.dd_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(dd_solve_result),
+                                ctypes.c_double]
+_lib.dd_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+_lib.dd_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_server_stats)]
+_lib.dd_server_destroy.argtypes = [ctypes.c_void_p]
+for _f in ("dd_server_create", "dd_server_submit", "dd_server_wait", "dd_server_cancel",
+           "dd_server_get_stats", "dd_server_destroy"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class DDServer:
+    """Owning handle of a dd_server: submit(...) -> ticket, wait(ticket) -> result dict."""
+
+    def __init__(self, ds: Dataset, hbm_budget_bytes: int = 0, mode="bf16", max_active: int = 0,
+                 max_batch: int = 0, max_queue: int = 0, ann_budget: int = 0):
+        self.ds = ds   # keeps the dataset alive for the server's lifetime
+        opts = dd_server_opts(MODES[mode] if isinstance(mode, str) else int(mode), max_active,
+                              max_batch, max_queue, ann_budget, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.dd_server_create(ds.handle, hbm_budget_bytes, ctypes.byref(opts),
+                                     ctypes.byref(h)), "dd_server_create")
+        self._h = h
+        self._pending = {}
+
+    def submit(self, mesh, dirichlet_mask, nodal_force, init_idx, max_iter: int = 0,
+               deadline_s: float = 0.0) -> int:
+        nx, ny, nz = mesh[:3]
+        lx, ly, lz = (mesh[3:] if len(mesh) > 3 else (1.0, 1.0, 1.0))
+        n_dof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+        n_mp = 8 * nx * ny * nz
+        mask = np.ascontiguousarray(np.asarray(dirichlet_mask, dtype=np.uint8).reshape(n_dof))
+        force = np.ascontiguousarray(np.asarray(nodal_force, dtype=np.float64).reshape(n_dof))
+        init = np.ascontiguousarray(np.asarray(init_idx, dtype=np.int64).reshape(n_mp))
+        req = dd_solve_request(dd_mesh(nx, ny, nz, lx, ly, lz), mask.ctypes.data,
+                               force.ctypes.data, init.ctypes.data, max_iter, 0, deadline_s)
+        t = ctypes.c_uint64()
+        _check(_lib.dd_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)),
+               "dd_server_submit")
+        self._pending[t.value] = (n_dof, n_mp, max_iter if max_iter > 0 else 500)
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0, raise_on_error: bool = True):
+        if ticket not in self._pending:
+            _check(_lib.dd_server_wait(self._h, ticket, None, 0.0), "dd_server_wait")
+        n_dof, n_mp, cap = self._pending[ticket]
+        out = {"u": np.zeros(n_dof), "idx": np.zeros(n_mp, np.int64), "eps": np.zeros((n_mp, 6)),
+               "sig": np.zeros((n_mp, 6)), "d_half": np.zeros(cap), "d_full": np.zeros(cap),
+               "changed": np.zeros(cap, np.int64)}
+        res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
+                              out["sig"].ctypes.data, out["d_half"].ctypes.data,
+                              out["d_full"].ctypes.data, out["changed"].ctypes.data, None, cap,
+                              0, 0, 0, 0, 0.0, 0.0)
+        st = _lib.dd_server_wait(self._h, ticket, ctypes.byref(res), float(timeout_s))
+        if st == 9:   # DD_ERR_TIMEOUT: the ticket stays valid
+            raise DDError(st, "dd_server_wait", dd_last_error())
+        del self._pending[ticket]
+        it = res.iterations
+        for k in ("d_half", "d_full", "changed"):
+            out[k] = out[k][:it]
+        out.update(status=st, iterations=it, converged=bool(res.converged),
+                   stop_reason=res.stop_reason, cg_iterations=res.cg_iterations,
+                   cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
+        if st not in (DD_OK, 5) and raise_on_error:
+            raise DDError(st, "dd_server_wait", dd_last_error())
+        return out
+
+    def cancel(self, ticket: int):
+        _check(_lib.dd_server_cancel(self._h, ticket), "dd_server_cancel")
+
+    def stats(self) -> dict:
+        s = dd_server_stats()
+        _check(_lib.dd_server_get_stats(self._h, ctypes.byref(s)), "dd_server_get_stats")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.dd_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dd_server_create(ds: Dataset, hbm_budget_bytes: int = 0, **kw) -> DDServer:
+    return DDServer(ds, hbm_budget_bytes, **kw)
+
+
+def dd_server_destroy(srv: DDServer):
+    srv.close()
+
+
+def dd_server_submit(srv: DDServer, *a, **kw) -> int:
+    return srv.submit(*a, **kw)
+
+
+def dd_server_wait(srv: DDServer, ticket: int, timeout_s: float = -1.0):
+    return srv.wait(ticket, timeout_s)
+
+
+def dd_server_cancel(srv: DDServer, ticket: int):
+    srv.cancel(ticket)
+
+
+def dd_server_get_stats(srv: DDServer) -> dict:
+    return srv.stats()

@@ -34,6 +34,25 @@ class DDSolver {
   dd_status constraint_projection();
   dd_status cg_solve();
   dd_status run(int max_iter, dd_solve_result* res);
+  // u, final association and the raw state of the last P_C (host arrays, any
+  // may be NULL); synchronises st
+  dd_status fetch_results(double* u, int64_t* idx, double* eps, double* sig);
+
+  // Non-blocking stepping of one DD iteration, for callers that interleave many
+  // solves (the server).  Every call only enqueues work on st; completion is
+  // observed with hipEventQuery on the named event.
+  dd_status async_init();        // pinned host mirrors and events
+  dd_status pc_begin();          // gather z*, right-hand sides, CG start
+  dd_status cg_batch();          // kCgPoll CG iterations, then the CG state -> host (ev_cg)
+  bool cg_finished() const;      // after ev_cg: both systems converged or cg_max_iter reached
+  dd_status pc_end();            // CG statistics, admissible state y (ev_ready)
+  dd_status scalars_begin();     // after P_D: iteration scalars -> host (ev_scal)
+  // after ev_scal: (d_half, d_full, changed, bad flag); swaps in the new association
+  void scalars_end(double sc[3], int* bad);
+  static int64_t footprint_bytes(const dd_mesh& mesh);
+  hipEvent_t ev_cg = nullptr, ev_ready = nullptr, ev_scal = nullptr;
+  char* h_pin = nullptr;
+  int cg_it = 0;
 
   FEMesh M;
   const Dataset* ds = nullptr;

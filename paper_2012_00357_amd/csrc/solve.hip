@@ -615,6 +615,126 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
 
 DDSolver::~DDSolver() {
   if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+  for (hipEvent_t e : {ev_cg, ev_ready, ev_scal})
+    if (e) (void)hipEventDestroy(e);
+  if (h_pin) (void)hipHostFree(h_pin);
+}
+
+// Device bytes setup() allocates for a mesh (the CSR pattern bounded by 81
+// couplings per row: 27 nodes x 3 components).
+int64_t DDSolver::footprint_bytes(const dd_mesh& m) {
+  const int64_t nd = 3 * (int64_t)(m.nx + 1) * (m.ny + 1) * (m.nz + 1);
+  const int64_t nm = 8 * (int64_t)m.nx * m.ny * m.nz;
+  const int64_t nnz = 81 * nd;
+  const int64_t nb = (nd + kCgBlock - 1) / kCgBlock, nbs = (nd + kRowsPerBlock - 1) / kRowsPerBlock;
+  return 4 * (nd + 1) + 12 * nnz + (8 + 1 + 8 + 16 + 16 + 64) * nd + (8 + 8 + 8 + 3 * 96) * nm +
+         32 + 64 + 64 * (nb + nbs) + (int64_t)sizeof(CGState);
+}
+
+// Pinned layout: [0, 128) CG state, [128, 152) iteration scalars, [160, 164) bad flag.
+dd_status DDSolver::async_init() {
+  static_assert(sizeof(CGState) <= 128, "CG state mirror");
+  if (!h_pin) DD_HIP(hipHostMalloc((void**)&h_pin, 256, hipHostMallocDefault));
+  for (hipEvent_t* e : {&ev_cg, &ev_ready, &ev_scal})
+    if (!*e) DD_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return DD_OK;
+}
+
+dd_status DDSolver::pc_begin() {
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  Mat6 Lm;
+  std::memcpy(Lm.a, L, sizeof(L));
+  BOps Bo;
+  std::memcpy(Bo.B, M.B, sizeof(Bo.B));
+  hipLaunchKernelGGL(gather_z_kernel, dim3(g256(nm)), dim3(256), 0, st, d_idx.as<int64_t>(), nm,
+                     ds->N, ds->iperm.as<uint32_t>(), ds->w64.as<double>(), Lm, d_zw.as<double>(),
+                     d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
+  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
+                     Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
+                     d_b.as<double>(), d_b.as<double>() + nd);
+  const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
+  double* wk = d_work.as<double>();
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(kCgBlock), 0, st, nd, d_rowptr.as<int32_t>(),
+                     d_col.as<int32_t>(), d_val.as<double>(), d_dinv.as<double>(), d_b.as<double>(),
+                     d_x.as<double>(), wk, wk + 2 * nd, wk + 4 * nd, d_part.as<double>());
+  hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kCgBlock), 0, st, d_part.as<double>(), nb,
+                     cg_tol, d_cgstate.as<CGState>());
+  DD_HIP(hipGetLastError());
+  cg_it = 0;
+  return DD_OK;
+}
+
+dd_status DDSolver::cg_batch() {
+  const int64_t nd = M.n_dof;
+  const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
+  const int nbs = (int)((nd + kRowsPerBlock - 1) / kRowsPerBlock);
+  double* wk = d_work.as<double>();
+  double *r = wk, *z = wk + 2 * nd, *p = wk + 4 * nd, *q = wk + 6 * nd;
+  double* part = d_part.as<double>();
+  double* part2 = part + 8 * (int64_t)nb;
+  CGState* cs = d_cgstate.as<CGState>();
+  const int32_t *rp = d_rowptr.as<int32_t>(), *cl = d_col.as<int32_t>();
+  const double* vl = d_val.as<double>();
+  const int count = std::min(kCgPoll, cg_max_iter - cg_it);
+  for (int k = 0; k < count; ++k) {
+    const int par = (cg_it + k) & 1;
+    hipLaunchKernelGGL(cg_spmv_kernel, dim3(nbs), dim3(kCgBlock), 0, st, nd, rp, cl, vl, p, q, part2,
+                       cs, par);
+    hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(kCgBlock), 0, st, nd, nbs,
+                       d_dinv.as<double>(), d_x.as<double>(), r, z, p, q, part2, part, cs, par);
+    hipLaunchKernelGGL(cg_pupdate_kernel, dim3(nb), dim3(kCgBlock), 0, st, nd, nb, z, p, part, cs,
+                       par, cg_tol);
+  }
+  cg_it += count;
+  DD_HIP(hipGetLastError());
+  DD_HIP(hipMemcpyAsync(h_pin, cs, sizeof(CGState), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipEventRecord(ev_cg, st));
+  return DD_OK;
+}
+
+bool DDSolver::cg_finished() const {
+  CGState hs;
+  std::memcpy(&hs, h_pin, sizeof(hs));
+  return cg_it >= cg_max_iter || (!hs.active[cg_it & 1][0] && !hs.active[cg_it & 1][1]);
+}
+
+dd_status DDSolver::pc_end() {
+  CGState hs;
+  std::memcpy(&hs, h_pin, sizeof(hs));
+  cg_last_iters[0] = hs.iters[0];
+  cg_last_iters[1] = hs.iters[1];
+  cg_last_res[0] = hs.bb[0] > 0 ? std::sqrt(hs.rr[0] / hs.bb[0]) : 0.0;
+  cg_last_res[1] = hs.bb[1] > 0 ? std::sqrt(hs.rr[1] / hs.bb[1]) : 0.0;
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  Mat6 Lm, LTm;
+  std::memcpy(Lm.a, L, sizeof(L));
+  std::memcpy(LTm.a, Lt, sizeof(Lt));
+  BOps Bo;
+  std::memcpy(Bo.B, M.B, sizeof(Bo.B));
+  hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
+                     d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),
+                     (double*)nullptr, (double*)nullptr);
+  DD_HIP(hipGetLastError());
+  DD_HIP(hipEventRecord(ev_ready, st));
+  return DD_OK;
+}
+
+dd_status DDSolver::scalars_begin() {
+  const int64_t nm = M.n_mp;
+  hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
+                     d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
+                     d_idx.as<int64_t>(), d_scal.as<double>());
+  DD_HIP(hipGetLastError());
+  DD_HIP(hipMemcpyAsync(h_pin + 128, d_scal.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipMemcpyAsync(h_pin + 160, d_cgstat.as<char>() + 32, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipEventRecord(ev_scal, st));
+  return DD_OK;
+}
+
+void DDSolver::scalars_end(double sc[3], int* bad) {
+  std::memcpy(sc, h_pin + 128, 3 * sizeof(double));
+  std::memcpy(bad, h_pin + 160, sizeof(int));
+  std::swap(d_idx.p, d_idx_new.p);
 }
 
 dd_status DDSolver::set_assignment(const int64_t* idx_host) {
@@ -716,6 +836,33 @@ dd_status DDSolver::constraint_projection() {
   return DD_OK;
 }
 
+dd_status DDSolver::fetch_results(double* u, int64_t* idx, double* eps, double* sig) {
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  if (u) DD_HIP(hipMemcpyAsync(u, d_x.p, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
+  if (idx) DD_HIP(hipMemcpyAsync(idx, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
+  if (eps || sig) {
+    // raw admissible state of the last P_C, recomputed from u, eta and the z*
+    // that P_C used (kept in zc)
+    DevBuf er, sr;
+    DD_TRY(er.alloc(sizeof(double) * 6 * nm));
+    DD_TRY(sr.alloc(sizeof(double) * 6 * nm));
+    Mat6 Lm, LTm;
+    std::memcpy(Lm.a, L, sizeof(L));
+    std::memcpy(LTm.a, Lt, sizeof(Lt));
+    BOps Bo;
+    std::memcpy(Bo.B, M.B, sizeof(Bo.B));
+    hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm,
+                       Lm, d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(),
+                       d_yw.as<double>(), er.as<double>(), sr.as<double>());
+    DD_HIP(hipGetLastError());
+    if (eps) DD_HIP(hipMemcpyAsync(eps, er.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
+    if (sig) DD_HIP(hipMemcpyAsync(sig, sr.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+  }
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
 dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   const int64_t nm = M.n_mp, nd = M.n_dof;
   auto t0 = std::chrono::steady_clock::now();
@@ -779,29 +926,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     res->stop_reason = stop_reason;
     res->cg_iterations = cg_total;
     res->cg_max_residual = cg_res_max;
-    if (res->u) DD_HIP(hipMemcpyAsync(res->u, d_x.p, sizeof(double) * nd, hipMemcpyDeviceToHost, st));
-    if (res->idx) DD_HIP(hipMemcpyAsync(res->idx, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
-    if (res->eps || res->sig) {
-      // raw admissible state of the last P_C (recomputed from u, eta and z*)
-      DevBuf er, sr;
-      DD_TRY(er.alloc(sizeof(double) * 6 * nm));
-      DD_TRY(sr.alloc(sizeof(double) * 6 * nm));
-      Mat6 Lm, LTm;
-      std::memcpy(Lm.a, L, sizeof(L));
-      std::memcpy(LTm.a, Lt, sizeof(Lt));
-      BOps Bo;
-      std::memcpy(Bo.B, M.B, sizeof(Bo.B));
-      // z of the last P_C is the association before the final swap when not
-      // converged; at convergence both coincide.  Recompute from the stored zc.
-      hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm,
-                         Lm, d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(),
-                         d_yw.as<double>(), er.as<double>(), sr.as<double>());
-      DD_HIP(hipGetLastError());
-      if (res->eps) DD_HIP(hipMemcpyAsync(res->eps, er.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
-      if (res->sig) DD_HIP(hipMemcpyAsync(res->sig, sr.p, sizeof(double) * 6 * nm, hipMemcpyDeviceToHost, st));
-      DD_HIP(hipStreamSynchronize(st));
-    }
-    DD_HIP(hipStreamSynchronize(st));
+    DD_TRY(fetch_results(res->u, res->idx, res->eps, res->sig));
     res->elapsed_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }

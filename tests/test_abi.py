@@ -22,7 +22,9 @@ def declared_functions():
 
 def test_header_declares_api():
     names = declared_functions()
-    for must in ("dd_dataset_create", "dd_dataset_destroy", "dd_project", "dd_last_error"):
+    for must in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
+                 "dd_project", "dd_solve", "dd_server_create", "dd_server_submit", "dd_server_wait",
+                 "dd_server_cancel", "dd_server_get_stats", "dd_server_destroy", "dd_last_error"):
         assert must in names
 
 
@@ -47,3 +49,23 @@ def test_library_has_no_oracle_dependency():
     import subprocess
     out = subprocess.run(["ldd", LIB], capture_output=True, text=True).stdout
     assert "oracle" not in out
+
+
+def test_struct_layouts_match_header():
+    """The binding's ctypes structures have the sizes the C compiler gives the
+    header's structures (a mismatch would corrupt every call)."""
+    import subprocess
+    import tempfile
+    from paper_2012_00357_amd import _lib
+    names = ["dd_dataset_opts", "dd_project_stats", "dd_project_opts", "dd_mesh", "dd_solve_opts",
+             "dd_solve_result", "dd_server_opts", "dd_solve_request", "dd_server_stats"]
+    src = "#include <stdio.h>\n#include \"dd.h\"\nint main(void){\n" + "".join(
+        f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n"
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "sz.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "sz")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        sizes = [int(x) for x in subprocess.check_output([exe]).split()]
+    for n, sz in zip(names, sizes):
+        assert ctypes.sizeof(getattr(_lib, n)) == sz, n
