@@ -187,6 +187,91 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
     return out
 
 
+def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8):
+    """Serving: N = 2^26 resident data points (BF16 + FP64 packs); DD solves on
+    4^3, 8^3, 16^3 and 24^3 hexahedra in equal mix, clamp + normal traction drawn
+    in [50, 200] MPa, random initial associations.  Capacity = solves/s of a burst
+    of n_cap solves submitted at once; then Poisson arrivals at each fraction of
+    that capacity, n_solves per run, each run on a fresh server."""
+    import numpy as np
+    import torch
+
+    import ddsynth
+    N = 1 << 26
+    e, s = ddsynth.data_points(N, 1004)
+    ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
+                             packs=0x1 | 0x4)
+    del e, s
+    torch.cuda.empty_cache()
+    sizes = (4, 8, 16, 24)
+    rng = np.random.default_rng(4)
+    bcs = {n: ddsynth.box_bc(n, 1.0) for n in sizes}
+
+    def request(k):
+        n = sizes[k % 4]
+        t = float(rng.uniform(50.0, 200.0))
+        mask, unit = bcs[n]
+        return ((n, n, n), mask, unit * t, ddsynth.indices(8 * n ** 3, N, 40000 + k))
+
+    out = {"workload": "serving, N=2^26 resident (BF16 + FP64), DD solves on 4^3/8^3/16^3/24^3 hex "
+                       "(equal mix), traction U[50,200] MPa, BF16 projections batched across solves",
+           "N": N}
+    # warm-up: one solve of each size
+    srv = L.DDServer(ds, mode="bf16")
+    for t in [srv.submit(*request(k)) for k in range(4)]:
+        srv.wait(t)
+    srv.close()
+    # capacity: a burst submitted at once
+    srv = L.DDServer(ds, mode="bf16")
+    t0 = time.time()
+    for t in [srv.submit(*request(100 + k)) for k in range(n_cap)]:
+        srv.wait(t)
+    cap = n_cap / (time.time() - t0)
+    st = srv.stats()
+    srv.close()
+    out["capacity_solves_per_s"] = round(cap, 3)
+    out["capacity_queries_per_s"] = round(st["queries_per_s"], 1)
+    log(f"serving capacity: {cap:.3f} solves/s ({st['queries_per_s']:.0f} queries/s)")
+    out["runs"] = []
+    for frac in fracs:
+        lam = frac * cap
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_solves))
+        srv = L.DDServer(ds, mode="bf16")
+        tickets, lat, iters, conv = [], [], [], 0
+        t0 = time.time()
+        for k, ta in enumerate(arrivals):
+            dt = ta - (time.time() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(*request(1000 * (1 + int(frac * 10)) + k)))
+        for t in tickets:
+            r = srv.wait(t)
+            lat.append(r["elapsed_ms"])
+            iters.append(r["iterations"])
+            conv += int(r["converged"])
+        wall = time.time() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array(lat)
+        run = {"rate_fraction": frac, "lambda_solves_per_s": round(lam, 3), "solves": n_solves,
+               "solve_p50_ms": round(float(np.percentile(lat, 50)), 1),
+               "solve_p99_ms": round(float(np.percentile(lat, 99)), 1),
+               "projection_p50_ms": round(st["proj_p50_ms"], 2),
+               "projection_p99_ms": round(st["proj_p99_ms"], 2),
+               "queue_p50_ms": round(st["queue_p50_ms"], 2),
+               "queue_p99_ms": round(st["queue_p99_ms"], 2),
+               "queries_per_s": round(st["queries"] / wall, 1),
+               "batches": st["batches"], "mean_batch": round(st["queries"] / max(st["batches"], 1), 1),
+               "peak_active": st["peak_active"], "peak_hbm_bytes": st["peak_bytes"],
+               "mean_iterations": round(float(np.mean(iters)), 2), "converged": conv}
+        out["runs"].append(run)
+        log(f"serving at {frac} x capacity ({lam:.3f}/s): solve p50 {run['solve_p50_ms']} ms, "
+            f"p99 {run['solve_p99_ms']} ms, projection p50 {run['projection_p50_ms']} ms, "
+            f"p99 {run['projection_p99_ms']} ms, {run['queries_per_s']:.0f} queries/s")
+    ds.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +289,10 @@ def main():
     ap.add_argument("--dd-solves", type=int, default=20,
                     help="DD solves (8^3 hex, N=1e6) timed for the p50/p99 latency leg; 0 = skip")
     ap.add_argument("--skip-ann", action="store_true", help="skip the N=1e9 ANN leg")
+    ap.add_argument("--serve-solves", type=int, default=12,
+                    help="solves per Poisson run of the serving leg (N=2^26); 0 = skip")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg and print its JSON object")
     ap.add_argument("--ann-only", action="store_true",
                     help="run only the N=1e9 ANN leg and print its JSON object")
     ap.add_argument("--ann-no-solve", action="store_true",
@@ -225,6 +314,9 @@ def main():
     torch.cuda.set_device(0)
     N, m = 1 << args.log2n, args.m
     C = ddsynth.isotropic_stiffness()
+    if args.serve_only:
+        print(json.dumps({"serving": serve_leg(L, C, args.serve_solves)}), flush=True)
+        return
     if args.ann_only:
         print(json.dumps({"ann": ann_leg(L, C, args.steps, solve=not args.ann_no_solve)}),
               flush=True)
@@ -313,11 +405,14 @@ def main():
     if args.dd_solves > 0:
         dd = dd_solve_latency(L, C, args.dd_solves)
 
+    ds.close()
+    torch.cuda.empty_cache()
     ann = None
     if not args.skip_ann:
-        ds.close()
-        torch.cuda.empty_cache()
         ann = ann_leg(L, C, args.steps)
+    serving = None
+    if args.serve_solves > 0:
+        serving = serve_leg(L, C, args.serve_solves)
 
     cpu = None
     if not args.skip_cpu:
@@ -350,6 +445,7 @@ def main():
         "fp64_scan": fp64,
         "dd_solve": dd,
         "ann": ann,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
