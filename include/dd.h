@@ -221,12 +221,17 @@ typedef struct dd_solve_opts {
   int32_t max_iter;      /* 0 = 500 */
   int32_t mode;          /* projection mode (dd_mode), default DD_EXACT_FP64 */
   int32_t cg_max_iter;   /* 0 = 20000 */
-  int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one */
+  int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
   int32_t ann_budget;    /* DD_ANN: leaves per projection (0 = exact walk) */
   int32_t reserved;      /* must be 0 */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
+/* P_C by CG even for meshes of at most 8192 DOFs, where dd_solve otherwise
+ * forms K^-1 once (blocked Gauss-Jordan on the GPU), keeps it on the dataset
+ * for that mesh and Dirichlet pattern (at most 2 GiB of inverses per dataset)
+ * and applies it as one product per P_C. */
+#define DD_SOLVE_CG 0x2
 
 /* Results of dd_solve; every array is HOST memory provided by the caller and
  * may be NULL when not wanted. */

@@ -250,7 +250,8 @@ _lib.dd_solve.restype = ctypes.c_int
 
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
-             cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, stream=None):
+             cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, cg: bool = False,
+             stream=None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
@@ -274,7 +275,7 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
                           hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0)
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
-                         cg_max_iter, 0 if graph else 1, cg_tol, ann_budget, 0)
+                         cg_max_iter, (0 if graph else 1) | (2 if cg else 0), cg_tol, ann_budget, 0)
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):

@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <list>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dd.h"
 
@@ -62,6 +66,18 @@ constexpr int kAnnLeaf = 64;       // points per ANN leaf (one wavefront)
 constexpr int kAnnFan = 64;        // children per ANN tree node (one wavefront)
 constexpr int kAnnMaxLevels = 6;   // 64^6 leaves exceed any N <= 2^31 - 1
 
+// K^-1 of one mesh and Dirichlet pattern (P_C by a dense product), padded to
+// n_pad rows and columns, row-major.
+struct DenseInverse {
+  int nx = 0, ny = 0, nz = 0;
+  double hx = 0, hy = 0, hz = 0;
+  std::vector<uint8_t> mask;
+  int64_t n = 0, n_pad = 0;
+  DevBuf inv;
+};
+constexpr int64_t kDenseMaxDof = 8192;                // meshes up to here use K^-1
+constexpr int64_t kDenseCacheBytes = (int64_t)2 << 30;  // inverses kept per dataset
+
 struct Dataset {
   int device = 0;
   int64_t N = 0;
@@ -101,6 +117,10 @@ struct Dataset {
   DevBuf ann_box[kAnnMaxLevels];
   int64_t ann_n[kAnnMaxLevels] = {0};
   int ann_levels = 0;
+
+  // inverses of K for dd_solve, most recently used first (see DenseInverse)
+  mutable std::mutex cache_mu;
+  mutable std::list<std::shared_ptr<DenseInverse>> pc_cache;
 
   int64_t device_bytes() const;
 };

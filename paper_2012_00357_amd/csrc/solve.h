@@ -22,6 +22,14 @@ dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
                            double* dist_out, hipStream_t st);
 
+// K^-1 for the mesh and Dirichlet pattern, formed on st from the CSR matrix on
+// first use and cached on the dataset.
+dd_status dense_inverse_for(const Dataset& ds, const FEMesh& M, const uint8_t* mask,
+                            const int32_t* rowptr, const int32_t* col, const double* val,
+                            std::shared_ptr<DenseInverse>& out, hipStream_t st);
+// x[0..n) = K^-1 b[0..n), x[n..2n) = K^-1 b[n..2n).
+dd_status dense_apply(const DenseInverse& D, const double* b, double* x, hipStream_t st);
+
 class DDSolver {
  public:
   DDSolver() = default;
@@ -67,6 +75,7 @@ class DDSolver {
   DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
   DevBuf d_part, d_cgstate;
   bool use_graph = true;
+  std::shared_ptr<DenseInverse> dense;   // set: P_C is a product with K^-1
   hipGraphExec_t cg_graph = nullptr;
   int cg_last_iters[2] = {0, 0};
   double cg_last_res[2] = {0.0, 0.0};

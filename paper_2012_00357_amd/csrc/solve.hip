@@ -610,6 +610,9 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   DD_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double) * 2 * nd, st));
   DD_HIP(hipMemsetAsync(d_cgstat.p, 0, 64, st));
   DD_HIP(hipStreamSynchronize(st));
+  if (nd <= kDenseMaxDof && !(opts && (opts->flags & DD_SOLVE_CG)))
+    DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
+                             d_val.as<double>(), dense, st));
   return DD_OK;
 }
 
@@ -652,6 +655,11 @@ dd_status DDSolver::pc_begin() {
   hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
                      d_b.as<double>(), d_b.as<double>() + nd);
+  cg_it = 0;
+  if (dense) {
+    DD_TRY(dense_apply(*dense, d_b.as<double>(), d_x.as<double>(), st));
+    return DD_OK;
+  }
   const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
   double* wk = d_work.as<double>();
   hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(kCgBlock), 0, st, nd, d_rowptr.as<int32_t>(),
@@ -665,6 +673,10 @@ dd_status DDSolver::pc_begin() {
 }
 
 dd_status DDSolver::cg_batch() {
+  if (dense) {   // the product was enqueued by pc_begin
+    DD_HIP(hipEventRecord(ev_cg, st));
+    return DD_OK;
+  }
   const int64_t nd = M.n_dof;
   const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
   const int nbs = (int)((nd + kRowsPerBlock - 1) / kRowsPerBlock);
@@ -693,18 +705,24 @@ dd_status DDSolver::cg_batch() {
 }
 
 bool DDSolver::cg_finished() const {
+  if (dense) return true;
   CGState hs;
   std::memcpy(&hs, h_pin, sizeof(hs));
   return cg_it >= cg_max_iter || (!hs.active[cg_it & 1][0] && !hs.active[cg_it & 1][1]);
 }
 
 dd_status DDSolver::pc_end() {
-  CGState hs;
-  std::memcpy(&hs, h_pin, sizeof(hs));
-  cg_last_iters[0] = hs.iters[0];
-  cg_last_iters[1] = hs.iters[1];
-  cg_last_res[0] = hs.bb[0] > 0 ? std::sqrt(hs.rr[0] / hs.bb[0]) : 0.0;
-  cg_last_res[1] = hs.bb[1] > 0 ? std::sqrt(hs.rr[1] / hs.bb[1]) : 0.0;
+  if (dense) {
+    cg_last_iters[0] = cg_last_iters[1] = 0;
+    cg_last_res[0] = cg_last_res[1] = 0.0;
+  } else {
+    CGState hs;
+    std::memcpy(&hs, h_pin, sizeof(hs));
+    cg_last_iters[0] = hs.iters[0];
+    cg_last_iters[1] = hs.iters[1];
+    cg_last_res[0] = hs.bb[0] > 0 ? std::sqrt(hs.rr[0] / hs.bb[0]) : 0.0;
+    cg_last_res[1] = hs.bb[1] > 0 ? std::sqrt(hs.rr[1] / hs.bb[1]) : 0.0;
+  }
   const int64_t nd = M.n_dof, nm = M.n_mp;
   Mat6 Lm, LTm;
   std::memcpy(Lm.a, L, sizeof(L));
@@ -746,6 +764,12 @@ dd_status DDSolver::set_assignment(const int64_t* idx_host) {
 }
 
 dd_status DDSolver::cg_solve() {
+  if (dense) {
+    DD_TRY(dense_apply(*dense, d_b.as<double>(), d_x.as<double>(), st));
+    cg_last_iters[0] = cg_last_iters[1] = 0;
+    cg_last_res[0] = cg_last_res[1] = 0.0;
+    return DD_OK;
+  }
   const int64_t nd = M.n_dof;
   const int nb = (int)((nd + kCgBlock - 1) / kCgBlock);
   const int nbs = (int)((nd + kRowsPerBlock - 1) / kRowsPerBlock);   // SpMV blocks

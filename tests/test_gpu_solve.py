@@ -110,8 +110,25 @@ def test_dd_solve_graph_replays_equal_eager(L, C0):
     and synchronisations between replays) give bitwise the eager result."""
     e, s, m, mask, f, init = _problem(4, 30000, 71)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
-    a = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=True)
-    b = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=False)
+    a = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=True, cg=True)
+    b = L.dd_solve(ds, (4, 4, 4), mask, f, init, history=True, graph=False, cg=True)
     assert a["cg_iterations"] > 100
     assert np.array_equal(a["history"], b["history"])
     assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["d_half"], b["d_half"])
+
+
+@pytest.mark.parametrize("n", [3, 8])
+def test_dd_solve_inverse_equals_cg(L, C0, n):
+    """P_C by the cached K^-1 and by CG give the same trajectory; u agrees to the
+    CG tolerance.  The second solve on the same mesh reuses the inverse."""
+    e, s, m, mask, f, init = _problem(n, 100000, 81 + n)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
+    cg = L.dd_solve(ds, (n, n, n), mask, f, init, mode="bf16", history=True, cg=True)
+    inv1 = L.dd_solve(ds, (n, n, n), mask, f, init, mode="bf16", history=True)
+    inv2 = L.dd_solve(ds, (n, n, n), mask, f, init, mode="bf16", history=True)
+    print(f"{n}^3: cg {cg['elapsed_ms']:.1f} ms ({cg['cg_iterations']} CG iterations), inverse "
+          f"{inv1['elapsed_ms']:.1f} ms first, {inv2['elapsed_ms']:.1f} ms cached", flush=True)
+    assert inv1["cg_iterations"] == 0 and cg["cg_iterations"] > 0
+    assert np.array_equal(cg["history"], inv1["history"])
+    assert np.array_equal(inv1["history"], inv2["history"]) and np.array_equal(inv1["u"], inv2["u"])
+    np.testing.assert_allclose(inv1["u"], cg["u"], rtol=0, atol=1e-10 * np.abs(cg["u"]).max())
