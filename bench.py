@@ -79,11 +79,12 @@ def dd_solve_latency(L, C, R):
     N, n = 1_000_000, 8
     e, s = ddsynth.data_points(N, 1001)
     ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
-                             packs=0x1 | 0x4)
+                             packs=0x1 | 0x4 | 0x10)
     mask, force = ddsynth.box_bc(n, 100.0)
-    out = {"workload": "DD solve, 8^3 hex (4096 material points), N=1e6, clamp + 100 MPa",
+    out = {"workload": "DD solve, 8^3 hex (4096 material points), N=1e6, clamp + 100 MPa; "
+                       "P_C by the cached K^-1, P_D exact in every mode",
            "solves": R}
-    for mode in ("bf16", "fp64"):
+    for mode in ("bf16", "fp64", "ann"):
         L.dd_solve(ds, (n, n, n), mask, force, ddsynth.indices(8 * n ** 3, N, 999), mode=mode)
         lat, iters, conv = [], [], 0
         for seed in range(R):
@@ -381,6 +382,32 @@ def main():
                 "flops_per_pair": FLOPS_PER_PAIR,
                 "issued_frac": round(achieved * 32.0 / FLOPS_PER_PAIR / peak, 4)}
 
+    walk = None
+    if not args.skip_ann:
+        # the exact tree walk on the same dataset and queries (its own pack and tree)
+        torch.cuda.synchronize()
+        t = time.time()
+        dsa = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
+                                  packs=0x1 | 0x10)
+        torch.cuda.synchronize()
+        walk_build = time.time() - t
+        L.dd_project(dsa, states, mode="ann")
+        torch.cuda.synchronize()
+        w_ms, tot = [], []
+        for _ in range(args.steps):
+            iw, dw, st = L.dd_project(dsa, states, mode="ann", stats=True)
+            w_ms.append(st["scan_ms"])
+            tot.append(st["total_ms"])
+        same = bool(np.array_equal(iw.cpu().numpy(), idx_mixed))
+        walk = {"proj_per_s": round(m / (sum(tot) / len(tot) / 1e3), 1),
+                "walk_ms": round(sum(w_ms) / len(w_ms), 3), "total_ms": round(sum(tot) / len(tot), 3),
+                "points_per_query": round(st["visited"] / m, 1),
+                "dataset_build_s": round(walk_build, 3), "indices_equal_mixed": same}
+        log(f"exact tree walk at N=2^{args.log2n}: {walk['total_ms']} ms/step "
+            f"({walk['proj_per_s']:.4g} proj/s), indices equal to {args.mode}: {same}")
+        dsa.close()
+        torch.cuda.empty_cache()
+
     fp64 = None
     if not args.skip_fp64 and args.mode != "fp64":
         if not (packs & 0x1):
@@ -443,6 +470,7 @@ def main():
                    "slow_tiles_per_step": slow / args.steps, "tile": args.tile},
         "roofline": roofline,
         "fp64_scan": fp64,
+        "exact_tree_walk": walk,
         "dd_solve": dd,
         "ann": ann,
         "serving": serving,

@@ -37,11 +37,18 @@ dd_status set_error(dd_status st, const std::string& msg);
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;   // false: a view into memory another DevBuf owns
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   dd_status alloc(size_t n);
+  void view(void* ptr, size_t n) {
+    release();
+    p = ptr;
+    bytes = n;
+    owned = false;
+  }
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };

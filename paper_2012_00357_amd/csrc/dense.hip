@@ -222,25 +222,30 @@ static dd_status form_inverse(const int32_t* rowptr, const int32_t* col, const d
   return DD_OK;
 }
 
-dd_status dense_inverse_for(const Dataset& ds, const FEMesh& M, const uint8_t* mask,
-                            const int32_t* rowptr, const int32_t* col, const double* val,
-                            std::shared_ptr<DenseInverse>& out, hipStream_t st) {
+std::shared_ptr<DenseInverse> dense_inverse_cached(const Dataset& ds, const FEMesh& M,
+                                                   const uint8_t* mask) {
   const int64_t n = M.n_dof;
   auto same = [&](const DenseInverse& d) {
     return d.nx == M.nx && d.ny == M.ny && d.nz == M.nz && d.hx == M.hx && d.hy == M.hy &&
            d.hz == M.hz && (int64_t)d.mask.size() == n &&
            std::memcmp(d.mask.data(), mask, (size_t)n) == 0;
   };
-  {
-    std::lock_guard<std::mutex> lk(ds.cache_mu);
-    for (auto it = ds.pc_cache.begin(); it != ds.pc_cache.end(); ++it) {
-      if (same(**it)) {
-        out = *it;
-        ds.pc_cache.splice(ds.pc_cache.begin(), ds.pc_cache, it);   // most recently used first
-        return DD_OK;
-      }
+  std::lock_guard<std::mutex> lk(ds.cache_mu);
+  for (auto it = ds.pc_cache.begin(); it != ds.pc_cache.end(); ++it) {
+    if (same(**it)) {
+      ds.pc_cache.splice(ds.pc_cache.begin(), ds.pc_cache, it);   // most recently used first
+      return ds.pc_cache.front();
     }
   }
+  return nullptr;
+}
+
+dd_status dense_inverse_for(const Dataset& ds, const FEMesh& M, const uint8_t* mask,
+                            const int32_t* rowptr, const int32_t* col, const double* val,
+                            std::shared_ptr<DenseInverse>& out, hipStream_t st) {
+  const int64_t n = M.n_dof;
+  out = dense_inverse_cached(ds, M, mask);
+  if (out) return DD_OK;
   auto d = std::make_shared<DenseInverse>();
   d->nx = M.nx;
   d->ny = M.ny;

@@ -15,6 +15,7 @@ dd_status set_error(dd_status st, const std::string& msg) {
 
 dd_status DevBuf::alloc(size_t n) {
   release();
+  owned = true;
   if (n == 0) return DD_OK;
   hipError_t e = hipMalloc(&p, n);
   if (e != hipSuccess) {
@@ -27,9 +28,10 @@ dd_status DevBuf::alloc(size_t n) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && owned) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+  owned = true;
 }
 
 bool cholesky6(const double* C, double* L) {

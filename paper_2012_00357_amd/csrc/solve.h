@@ -27,6 +27,9 @@ dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
 dd_status dense_inverse_for(const Dataset& ds, const FEMesh& M, const uint8_t* mask,
                             const int32_t* rowptr, const int32_t* col, const double* val,
                             std::shared_ptr<DenseInverse>& out, hipStream_t st);
+// The cached K^-1 for the mesh and Dirichlet pattern, or null.
+std::shared_ptr<DenseInverse> dense_inverse_cached(const Dataset& ds, const FEMesh& M,
+                                                   const uint8_t* mask);
 // x[0..n) = K^-1 b[0..n), x[n..2n) = K^-1 b[n..2n).
 dd_status dense_apply(const DenseInverse& D, const double* b, double* x, hipStream_t st);
 
@@ -74,6 +77,7 @@ class DDSolver {
   DevBuf d_rowptr, d_col, d_val, d_dinv, d_mask, d_f, d_b, d_x, d_work;
   DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
   DevBuf d_part, d_cgstate;
+  DevBuf arena;   // one allocation holding every buffer above
   bool use_graph = true;
   std::shared_ptr<DenseInverse> dense;   // set: P_C is a product with K^-1
   hipGraphExec_t cg_graph = nullptr;

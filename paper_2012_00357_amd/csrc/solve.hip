@@ -571,48 +571,67 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
     for (int c = 0; c < 6; ++c) LT[6 * r + c] = Lm[6 * c + r];
   std::memcpy(L, Lm, sizeof(L));
   std::memcpy(Lt, LT, sizeof(Lt));
+  const int64_t nd = M.n_dof, nm = M.n_mp;
+  const bool want_dense = nd <= kDenseMaxDof && !(opts && (opts->flags & DD_SOLVE_CG));
+  if (want_dense) dense = dense_inverse_cached(D, M, mask);
+  // the CSR matrix is needed by CG, or once to form K^-1
+  const bool need_csr = !dense;
   std::vector<int32_t> rowptr, col;
   std::vector<double> val, dinv;
-  assemble_csr(M, D.C, mask, rowptr, col, val, dinv);
+  if (need_csr) assemble_csr(M, D.C, mask, rowptr, col, val, dinv);
   nnz = (int64_t)col.size();
-  const int64_t nd = M.n_dof, nm = M.n_mp;
-  DD_TRY(d_rowptr.alloc(sizeof(int32_t) * (nd + 1)));
-  DD_TRY(d_col.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-  DD_TRY(d_val.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)));
-  DD_TRY(d_dinv.alloc(sizeof(double) * nd));
-  DD_TRY(d_mask.alloc(nd));
-  DD_TRY(d_f.alloc(sizeof(double) * nd));
-  DD_TRY(d_b.alloc(sizeof(double) * 2 * nd));
-  DD_TRY(d_x.alloc(sizeof(double) * 2 * nd));
-  DD_TRY(d_work.alloc(sizeof(double) * 8 * nd));
-  DD_TRY(d_idx.alloc(sizeof(int64_t) * nm));
-  DD_TRY(d_idx_new.alloc(sizeof(int64_t) * nm));
-  DD_TRY(d_dist.alloc(sizeof(double) * nm));
-  DD_TRY(d_zw.alloc(sizeof(double) * 12 * nm));
-  DD_TRY(d_zc.alloc(sizeof(double) * 12 * nm));
-  DD_TRY(d_yw.alloc(sizeof(double) * 12 * nm));
-  DD_TRY(d_scal.alloc(sizeof(double) * 4));
-  DD_TRY(d_cgstat.alloc(64));
+  const int64_t nb = (nd + kCgBlock - 1) / kCgBlock;
+  const int64_t nbs = (nd + kRowsPerBlock - 1) / kRowsPerBlock;
+  // one device allocation carved into the solver's buffers (256-byte aligned)
+  struct Part {
+    DevBuf* buf;
+    size_t bytes;
+  };
+  std::vector<Part> parts = {
+      {&d_mask, (size_t)nd}, {&d_f, sizeof(double) * nd}, {&d_b, sizeof(double) * 2 * nd},
+      {&d_x, sizeof(double) * 2 * nd}, {&d_idx, sizeof(int64_t) * nm},
+      {&d_idx_new, sizeof(int64_t) * nm}, {&d_dist, sizeof(double) * nm},
+      {&d_zw, sizeof(double) * 12 * nm}, {&d_zc, sizeof(double) * 12 * nm},
+      {&d_yw, sizeof(double) * 12 * nm}, {&d_scal, sizeof(double) * 4}, {&d_cgstat, 64}};
+  if (need_csr) {
+    parts.push_back({&d_rowptr, sizeof(int32_t) * (nd + 1)});
+    parts.push_back({&d_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)});
+    parts.push_back({&d_val, sizeof(double) * std::max<int64_t>(nnz, 1)});
+  }
+  if (!want_dense) {   // CG state
+    parts.push_back({&d_dinv, sizeof(double) * nd});
+    parts.push_back({&d_work, sizeof(double) * 8 * nd});
+    parts.push_back({&d_part, sizeof(double) * 8 * (nb + nbs)});
+    parts.push_back({&d_cgstate, sizeof(CGState)});
+  }
+  size_t total = 0;
+  for (const Part& q : parts) total += (q.bytes + 255) / 256 * 256;
+  DD_TRY(arena.alloc(total));
   {
-    const int64_t nb = (M.n_dof + kCgBlock - 1) / kCgBlock;
-    const int64_t nbs = (M.n_dof + kRowsPerBlock - 1) / kRowsPerBlock;
-    DD_TRY(d_part.alloc(sizeof(double) * 8 * (nb + nbs)));
-    DD_TRY(d_cgstate.alloc(sizeof(CGState)));
+    char* base = arena.as<char>();
+    for (const Part& q : parts) {
+      q.buf->view(base, q.bytes);
+      base += (q.bytes + 255) / 256 * 256;
+    }
   }
-  DD_HIP(hipMemcpyAsync(d_rowptr.p, rowptr.data(), sizeof(int32_t) * (nd + 1), hipMemcpyHostToDevice, st));
-  if (nnz) {
-    DD_HIP(hipMemcpyAsync(d_col.p, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
-    DD_HIP(hipMemcpyAsync(d_val.p, val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  if (need_csr) {
+    DD_HIP(hipMemcpyAsync(d_rowptr.p, rowptr.data(), sizeof(int32_t) * (nd + 1),
+                          hipMemcpyHostToDevice, st));
+    if (nnz) {
+      DD_HIP(hipMemcpyAsync(d_col.p, col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+      DD_HIP(hipMemcpyAsync(d_val.p, val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+    }
   }
-  DD_HIP(hipMemcpyAsync(d_dinv.p, dinv.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  if (!want_dense)
+    DD_HIP(hipMemcpyAsync(d_dinv.p, dinv.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemcpyAsync(d_mask.p, mask, nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemcpyAsync(d_f.p, force, sizeof(double) * nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double) * 2 * nd, st));
   DD_HIP(hipMemsetAsync(d_cgstat.p, 0, 64, st));
-  DD_HIP(hipStreamSynchronize(st));
-  if (nd <= kDenseMaxDof && !(opts && (opts->flags & DD_SOLVE_CG)))
+  if (want_dense && !dense)
     DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
                              d_val.as<double>(), dense, st));
+  DD_HIP(hipStreamSynchronize(st));
   return DD_OK;
 }
 
