@@ -227,10 +227,10 @@ typedef struct dd_solve_opts {
   int32_t reserved;      /* must be 0 */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
-/* P_C by CG even for meshes of at most 8192 DOFs, where dd_solve otherwise
+/* P_C by CG even for meshes of at most 16384 DOFs, where dd_solve otherwise
  * forms K^-1 once (blocked Gauss-Jordan on the GPU), keeps it on the dataset
- * for that mesh and Dirichlet pattern (at most 2 GiB of inverses per dataset)
- * and applies it as one product per P_C. */
+ * for that mesh and Dirichlet pattern (at most 4 GiB of inverses per dataset,
+ * least recently used dropped first) and applies it as one product per P_C. */
 #define DD_SOLVE_CG 0x2
 
 /* Results of dd_solve; every array is HOST memory provided by the caller and

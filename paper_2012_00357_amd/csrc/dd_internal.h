@@ -82,8 +82,8 @@ struct DenseInverse {
   int64_t n = 0, n_pad = 0;
   DevBuf inv;
 };
-constexpr int64_t kDenseMaxDof = 8192;                // meshes up to here use K^-1
-constexpr int64_t kDenseCacheBytes = (int64_t)2 << 30;  // inverses kept per dataset
+constexpr int64_t kDenseMaxDof = 16384;               // meshes up to here use K^-1
+constexpr int64_t kDenseCacheBytes = (int64_t)4 << 30;  // inverses kept per dataset
 
 struct Dataset {
   int device = 0;

@@ -117,7 +117,7 @@ def test_dd_solve_graph_replays_equal_eager(L, C0):
     assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["d_half"], b["d_half"])
 
 
-@pytest.mark.parametrize("n", [3, 8])
+@pytest.mark.parametrize("n", [3, 8, 16])
 def test_dd_solve_inverse_equals_cg(L, C0, n):
     """P_C by the cached K^-1 and by CG give the same trajectory; u agrees to the
     CG tolerance.  The second solve on the same mesh reuses the inverse."""
