@@ -184,6 +184,28 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
                               "ms": round(solve_ms, 1), "iterations": r["iterations"],
                               "converged": bool(r["converged"])}
     log(f"ann 1e9 dd_solve 16^3: {solve_ms:.0f} ms, {r['iterations']} iterations")
+    t = time.time()
+    rs = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", skip=True)
+    skip_ms = (time.time() - t) * 1e3
+    out["dd_solve_16cube_skip"] = {
+        "ms": round(skip_ms, 1), "iterations": rs["iterations"],
+        "projections_skipped": rs["skipped"], "projections": rs["iterations"] * 8 * n ** 3,
+        "same_u_as_without": bool(np.array_equal(rs["u"], r["u"]))}
+    log(f"ann 1e9 dd_solve 16^3 with skipping: {skip_ms:.0f} ms, skipped {rs['skipped']} of "
+        f"{rs['iterations'] * 8 * n ** 3} projections")
+    sched = []
+    for budget, ramp in ((4, 0), (4, 10), (16, 10)):
+        t = time.time()
+        rb = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", ann_budget=budget,
+                        ann_ramp=ramp)
+        ms_b = (time.time() - t) * 1e3
+        err = float(np.linalg.norm(rb["u"] - r["u"]) / np.linalg.norm(r["u"]))
+        sched.append({"budget": budget, "ramp": ramp, "ms": round(ms_b, 1),
+                      "iterations": rb["iterations"], "stop_reason": rb["stop_reason"],
+                      "u_rel_err_vs_exact": err})
+        log(f"ann 1e9 dd_solve 16^3 budget {budget} ramp {ramp}: {ms_b:.0f} ms, "
+            f"{rb['iterations']} iterations, u rel err {err:.3e}")
+    out["dd_solve_16cube_budgeted"] = sched
     ds.close()
     return out
 

@@ -224,7 +224,9 @@ typedef struct dd_solve_opts {
   int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
   int32_t ann_budget;    /* DD_ANN: leaves per projection (0 = exact walk) */
-  int32_t reserved;      /* must be 0 */
+  int32_t ann_ramp;      /* DD_ANN with a budget: > 0 = accuracy schedule, iteration i <= ann_ramp
+                            uses ann_budget * i leaves, later iterations walk exactly (the paper's
+                            search accuracy growing over the iterations, Section 4.5) */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
 /* P_C by CG even for meshes of at most 16384 DOFs, where dd_solve otherwise
@@ -232,6 +234,12 @@ typedef struct dd_solve_opts {
  * for that mesh and Dirichlet pattern (at most 4 GiB of inverses per dataset,
  * least recently used dropped first) and applies it as one product per P_C. */
 #define DD_SOLVE_CG 0x2
+/* Exact DD_ANN solves: skip the projection of material points whose state
+ * moved less than half the certified gap between their nearest and second
+ * nearest data points since that gap was measured (the association cannot
+ * change, by the triangle inequality: the paper's criterion for unmoved
+ * queries).  The walk then certifies two neighbours; results are unchanged. */
+#define DD_SOLVE_SKIP 0x4
 
 /* Results of dd_solve; every array is HOST memory provided by the caller and
  * may be NULL when not wanted. */
@@ -252,6 +260,7 @@ typedef struct dd_solve_result {
   int64_t cg_iterations;    /* out: total CG iterations (both systems) */
   double cg_max_residual;   /* out: largest final relative CG residual */
   double elapsed_ms;        /* out: host wall time of the loop */
+  int64_t skipped;          /* out: projections skipped as unmoved (exact DD_ANN) */
 } dd_solve_result;
 
 /*
@@ -260,10 +269,12 @@ typedef struct dd_solve_result {
  * K = A_e{w B^T C B} assembled once, E = A_e{w B^T C eps*},
  * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
  * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
- * exact projections).  With an approximate projection (DD_ANN with a budget)
- * the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer decreases,
- * since the alternating-minimisation descent no longer holds (Section 4.1);
- * each projection is warm-started from the current association.
+ * exact projections).  With an approximate projection (DD_ANN with a budget,
+ * no ramp) the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer
+ * decreases, since the alternating-minimisation descent no longer holds
+ * (Section 4.1); with an accuracy schedule (ann_ramp) the stopping rules apply
+ * once the walk has become exact.  Each projection is warm-started from the
+ * current association.
  *   mesh            structured box mesh (see dd_mesh)
  *   dirichlet_mask  host uint8 [ndof]: 1 = homogeneous Dirichlet DOF (u = eta = 0)
  *   nodal_force     host float64 [ndof]: consistent nodal forces f

@@ -229,7 +229,7 @@ class dd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("cg_max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("ann_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("ann_ramp", ctypes.c_int32)]
 
 
 class dd_solve_result(ctypes.Structure):
@@ -239,7 +239,7 @@ class dd_solve_result(ctypes.Structure):
                 ("history_capacity", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
                 ("cg_iterations", ctypes.c_int64), ("cg_max_residual", ctypes.c_double),
-                ("elapsed_ms", ctypes.c_double)]
+                ("elapsed_ms", ctypes.c_double), ("skipped", ctypes.c_int64)]
 
 
 _lib.dd_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_mesh), ctypes.c_void_p, ctypes.c_void_p,
@@ -251,7 +251,7 @@ _lib.dd_solve.restype = ctypes.c_int
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
              cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, cg: bool = False,
-             stream=None):
+             ann_ramp: int = 0, skip: bool = False, stream=None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
@@ -273,9 +273,10 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
     res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
                           out["sig"].ctypes.data, out["d_half"].ctypes.data,
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
-                          hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0)
+                          hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0, 0)
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
-                         cg_max_iter, (0 if graph else 1) | (2 if cg else 0), cg_tol, ann_budget, 0)
+                         cg_max_iter, (0 if graph else 1) | (2 if cg else 0) | (4 if skip else 0),
+                         cg_tol, ann_budget, ann_ramp)
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):
@@ -286,7 +287,7 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
     if history:
         out["history"] = hist[:it + 1]
     out.update(iterations=it, converged=bool(res.converged), stop_reason=res.stop_reason,
-               cg_iterations=res.cg_iterations,
+               skipped=res.skipped, cg_iterations=res.cg_iterations,
                cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
     return out
 
@@ -371,7 +372,7 @@ class DDServer:
         res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
                               out["sig"].ctypes.data, out["d_half"].ctypes.data,
                               out["d_full"].ctypes.data, out["changed"].ctypes.data, None, cap,
-                              0, 0, 0, 0, 0.0, 0.0)
+                              0, 0, 0, 0, 0.0, 0.0, 0)
         st = _lib.dd_server_wait(self._h, ticket, ctypes.byref(res), float(timeout_s))
         if st == 9:   # DD_ERR_TIMEOUT: the ticket stays valid
             raise DDError(st, "dd_server_wait", dd_last_error())

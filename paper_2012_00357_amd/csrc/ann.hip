@@ -56,6 +56,7 @@ struct AnnArgs {
   const int* invalid;
   const int64_t* warm;
   Outputs out;
+  double* dist2;                  // TOP2: distance to the second nearest point (1/2 d^2)
   int* fb_list;
   int* fb_count;
   unsigned long long* counters;   // [0] points visited, [1] boxes tested, [2] leaves, [3] candidates
@@ -119,6 +120,10 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
   }
 }
 
+// TOP2: certify the two nearest points instead of the nearest: the pruning
+// bound is the second smallest of the per-point upper bounds seen (U2), so the
+// candidates hold every point within the second-smallest distance.
+template <bool TOP2>
 __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
   __shared__ float s_lb[kWaves][kStack];
@@ -133,6 +138,7 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     if (lane == 0) {
       A.out.idx[q] = -1;
       if (A.out.dist) A.out.dist[q] = NAN;
+      if (TOP2) A.dist2[q] = NAN;
     }
     return;
   }
@@ -155,12 +161,16 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
   const float qnorm = (float)sqrt(A.qn2[q]);
   const float ebase = kEps20 * (qnorm + A.xmax);
   const float slack = kEps22 * (qnorm + A.xmax) + 1e-30f;
-  float U = A.u32[q];
+  // U: pruning bound (the smallest upper bound seen; with TOP2 the second
+  // smallest over distinct points, U1 tracking the smallest)
+  float U = TOP2 ? INFINITY : A.u32[q];
+  float U1 = INFINITY;
   int nc = 0;
   bool ovf = false;
 
-  // the warm-start point is the first candidate
-  if (A.warm) {
+  // the warm-start point is the first candidate (TOP2: it is found by the walk,
+  // which then counts it once)
+  if (A.warm && !TOP2) {
     const int64_t wi = A.warm[q];
     if (wi >= 0 && wi < A.N) {
       const int64_t pos = A.iperm[wi];
@@ -228,7 +238,20 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
       s = __builtin_sqrtf(leaf_dist(A.w32, pos, qf));
       E = ebase + kEps20 * s;
     }
-    U = fminf(U, wave_min_f(v ? s + E : INFINITY));
+    if (TOP2) {
+      const float h = v ? s + E : INFINITY;
+      const float m1 = wave_min_f(h);
+      const uint64_t at1 = __ballot(h == m1);
+      const int l1 = at1 ? __ffsll((long long)at1) - 1 : 0;
+      const float m2 = wave_min_f(lane == l1 ? INFINITY : h);
+      // the two smallest of {U1, U, m1, m2}
+      const float lo = fminf(U1, m1);
+      const float hi = fminf(fmaxf(U1, m1), fminf(U, m2));
+      U1 = lo;
+      U = hi;
+    } else {
+      U = fminf(U, wave_min_f(v ? s + E : INFINITY));
+    }
     const bool keep = v && (s - E <= U);
     const uint64_t km = __ballot(keep);
     const int cnt = __popcll(km);
@@ -276,6 +299,7 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     if (lane == 0) {
       const int k = atomicAdd(A.fb_count, 1);
       A.fb_list[k] = (int)q;
+      if (TOP2) A.dist2[q] = -1.0;   // no second distance: never skipped
     }
     return;
   }
@@ -295,6 +319,8 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     o = A.perm[j];
   }
   if (lane == 0) atomicAdd(A.counters + 3, (unsigned long long)__popcll(__ballot(mine)));
+  const double dm = d;
+  const uint32_t om = o;
   for (int off = 32; off > 0; off >>= 1) {
     const double od = __shfl_xor(d, off);
     const uint32_t oo = __shfl_xor(o, off);
@@ -302,6 +328,12 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
       d = od;
       o = oo;
     }
+  }
+  if (TOP2) {
+    // second smallest: the minimum over the other candidates (points are distinct)
+    double d2 = (om == o) ? INFINITY : dm;
+    for (int off = 32; off > 0; off >>= 1) d2 = fmin(d2, __shfl_xor(d2, off));
+    if (lane == 0) A.dist2[q] = 0.5 * d2;
   }
   if (lane == 0) {
     A.out.idx[q] = (int64_t)o;
@@ -313,7 +345,8 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
 
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
                           const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
-                          unsigned long long* counters, hipStream_t st) {
+                          unsigned long long* counters, double* dist2, hipStream_t st) {
+  if (dist2 && budget != 0) return set_error(DD_ERR_ARG, "second distances need the exact walk");
   if (len_max <= 0) return DD_OK;
   if (D.ann_levels < 1 || D.ann_levels > kAnnMaxLevels || D.ann_n[D.ann_levels - 1] > kAnnFan)
     return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
@@ -342,7 +375,11 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
   A.fb_count = fb_count;
   A.counters = counters;
   const unsigned blocks = (unsigned)((len_max + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(ann_walk_kernel, dim3(blocks), dim3(kWaves * 64), 0, st, A);
+  A.dist2 = dist2;
+  if (dist2)
+    hipLaunchKernelGGL(ann_walk_kernel<true>, dim3(blocks), dim3(kWaves * 64), 0, st, A);
+  else
+    hipLaunchKernelGGL(ann_walk_kernel<false>, dim3(blocks), dim3(kWaves * 64), 0, st, A);
   DD_HIP(hipGetLastError());
   return DD_OK;
 }

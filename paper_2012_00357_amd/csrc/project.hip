@@ -102,9 +102,24 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
 
 namespace dd {
 
+dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
+                          const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                          int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
+                          hipStream_t st);
+
 dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                        const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
                        int64_t* idx_out_dev, double* dist_out_dev, hipStream_t st) {
+  return project_impl_ex(D, states_dev, whitened, m, warm_start_idx_dev, opts, idx_out_dev,
+                         dist_out_dev, nullptr, st);
+}
+
+// As project_impl; dist2_out_dev (exact DD_ANN only) receives the distance to
+// the second nearest point, -1 where it is not certified.
+dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
+                          const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                          int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
+                          hipStream_t st) {
   if (m < 0 || m > 0x7FFFFFFFll) return set_error(DD_ERR_ARG, "m must be in [0, 2^31-1]");
   if (m == 0) return DD_OK;
   if (!states_dev || !idx_out_dev) return set_error(DD_ERR_ARG, "NULL states or idx_out");
@@ -168,7 +183,10 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
     DD_TRY(sc.get(fb, (size_t)m));
     ann = reinterpret_cast<unsigned long long*>(counters + 6);
     DD_TRY(timing.mark(1, st));
-    DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann, st));
+    if (dist2_out_dev && budget != 0)
+      return set_error(DD_ERR_ARG, "second distances need the exact walk");
+    DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann,
+                           dist2_out_dev, st));
     DD_TRY(timing.mark(2, st));
     int h = 0;
     DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -270,11 +288,11 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
 
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
-                           double* dist_out, hipStream_t st) {
+                           double* dist_out, hipStream_t st, double* dist2_out) {
   dd_project_opts o{};
   o.mode = mode;
   o.ann_budget = ann_budget;
-  return project_impl(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, st);
+  return project_impl_ex(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, dist2_out, st);
 }
 
 }  // namespace dd

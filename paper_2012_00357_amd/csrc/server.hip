@@ -666,6 +666,7 @@ extern "C" dd_status dd_server_wait(dd_server* h, uint64_t ticket, dd_solve_resu
     res->iterations = n;
     res->converged = j->stop_reason == 1 ? 1 : 0;
     res->stop_reason = j->stop_reason;
+    res->skipped = 0;
     res->cg_iterations = j->cg_total;
     res->cg_max_residual = j->cg_res_max;
     res->elapsed_ms = j->phase == Job::kDone ? ms_since(j->t_submit, j->t_done) : 0.0;

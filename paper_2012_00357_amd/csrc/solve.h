@@ -18,9 +18,11 @@ struct FEMesh {
 };
 
 // P_D of whitened states (already in the dataset's coordinates).
+// dist2_out (exact DD_ANN only): distance to the second nearest point, -1
+// where not certified.
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
-                           double* dist_out, hipStream_t st);
+                           double* dist_out, hipStream_t st, double* dist2_out = nullptr);
 
 // K^-1 for the mesh and Dirichlet pattern, formed on st from the CSR matrix on
 // first use and cached on the dataset.
@@ -70,6 +72,13 @@ class DDSolver {
   hipStream_t st = nullptr;
   int mode = DD_EXACT_FP64;
   int ann_budget = 0;
+  int ann_ramp = 0;
+  // leaves per projection at DD iteration it (1-based); 0 = exact
+  int budget_at(int it) const {
+    if (mode != DD_ANN || ann_budget <= 0) return 0;
+    if (ann_ramp <= 0) return ann_budget;
+    return it <= ann_ramp ? ann_budget * it : 0;
+  }
   double cg_tol = 1e-13;
   int cg_max_iter = 20000;
   int64_t nnz = 0;
@@ -78,6 +87,12 @@ class DDSolver {
   DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
   DevBuf d_part, d_cgstate;
   DevBuf arena;   // one allocation holding every buffer above
+  // skipping of unmoved material points (exact DD_ANN): reference state, half
+  // gap, compacted list and its projection buffers
+  bool skip_on = false;
+  DevBuf d_qref, d_gap, d_list, d_cnt, d_qc, d_wc, d_ic, d_dc, d_d2c;
+  int64_t skipped_total = 0;
+  dd_status project_step(int it);   // P_D of the current states into d_idx_new / d_dist
   bool use_graph = true;
   std::shared_ptr<DenseInverse> dense;   // set: P_C is a product with K^-1
   hipGraphExec_t cg_graph = nullptr;

@@ -540,6 +540,66 @@ __global__ __launch_bounds__(1024) void iter_scalars_kernel(
   }
 }
 
+// Unmoved material points (exact ANN projections).  If the state y moved by
+// delta < (d2 - d1)/2 from the reference state q at which the nearest (d1) and
+// second nearest (d2) distances were certified, every other data point stays
+// farther from y than the nearest one: d(y, x) >= d2 - delta > d1 + delta >=
+// d(y, p1).  gap holds (d2 - d1)/2 less a margin far above the FP64 rounding of
+// the distances; NaN or negative = no certified gap.  Skipped points keep their
+// association and get the FP64 direct-form distance of the projection's rerank;
+// the others are compacted (list order does not affect any result).
+__global__ void skip_kernel(int64_t nm, const double* __restrict__ yw,
+                            const double* __restrict__ qref, const double* __restrict__ gap,
+                            const int64_t* __restrict__ idx, const uint32_t* __restrict__ iperm,
+                            const double* __restrict__ w64, int64_t* __restrict__ idx_new,
+                            double* __restrict__ dist, int* __restrict__ list, int* __restrict__ cnt,
+                            double* __restrict__ qc, int64_t* __restrict__ wc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nm) return;
+  double y[12], dl = 0.0;
+  for (int k = 0; k < 12; ++k) {
+    y[k] = yw[12 * e + k];
+    const double t = y[k] - qref[12 * e + k];
+    dl = fma(t, t, dl);
+  }
+  const double g = gap[e];
+  if (g > 0.0 && dl < g * g) {
+    const int64_t j = idx[e];
+    const int64_t p = iperm[j];
+    double d = 0.0;
+    for (int k = 0; k < 12; ++k) {
+      const double t = y[k] - w64[12 * p + k];
+      d = fma(t, t, d);
+    }
+    idx_new[e] = j;
+    dist[e] = 0.5 * d;
+  } else {
+    const int k = atomicAdd(cnt, 1);
+    list[k] = (int)e;
+    for (int c = 0; c < 12; ++c) qc[12 * (int64_t)k + c] = y[c];
+    wc[k] = idx[e];
+  }
+}
+
+__global__ void unskip_kernel(int n, const int* __restrict__ list, const int64_t* __restrict__ ic,
+                              const double* __restrict__ dc, const double* __restrict__ d2c,
+                              const double* __restrict__ qc, int64_t* __restrict__ idx_new,
+                              double* __restrict__ dist, double* __restrict__ qref,
+                              double* __restrict__ gap) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t e = list[k];
+  idx_new[e] = ic[k];
+  dist[e] = dc[k];
+  for (int c = 0; c < 12; ++c) qref[12 * e + c] = qc[12 * (int64_t)k + c];
+  if (d2c[k] >= 0.0 && ic[k] >= 0) {
+    const double d1 = sqrt(2.0 * dc[k]), d2 = sqrt(2.0 * d2c[k]);
+    gap[e] = 0.5 * (d2 - d1) - 1e-9 * d2 - 1e-12;
+  } else {
+    gap[e] = -1.0;
+  }
+}
+
 static unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ---------------------------------------------------------------------------
@@ -559,8 +619,9 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   this->st = st;
   mode = opts ? opts->mode : DD_EXACT_FP64;
   ann_budget = opts ? opts->ann_budget : 0;
-  if (ann_budget < 0 || (opts && opts->reserved != 0))
-    return set_error(DD_ERR_ARG, "dd_solve_opts: ann_budget must be >= 0 and reserved 0");
+  ann_ramp = opts ? opts->ann_ramp : 0;
+  if (ann_budget < 0 || ann_ramp < 0)
+    return set_error(DD_ERR_ARG, "dd_solve_opts: ann_budget and ann_ramp must be >= 0");
   use_graph = !(opts && (opts->flags & DD_SOLVE_NO_GRAPH));
   cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
   cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
@@ -631,7 +692,48 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   if (want_dense && !dense)
     DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
                              d_val.as<double>(), dense, st));
+  skip_on = (mode == DD_ANN && ann_budget == 0 && opts && (opts->flags & DD_SOLVE_SKIP));
+  if (skip_on) {
+    DD_TRY(d_qref.alloc(sizeof(double) * 12 * nm));
+    DD_TRY(d_gap.alloc(sizeof(double) * nm));
+    DD_TRY(d_list.alloc(sizeof(int) * nm));
+    DD_TRY(d_cnt.alloc(sizeof(int)));
+    DD_TRY(d_qc.alloc(sizeof(double) * 12 * nm));
+    DD_TRY(d_wc.alloc(sizeof(int64_t) * nm));
+    DD_TRY(d_ic.alloc(sizeof(int64_t) * nm));
+    DD_TRY(d_dc.alloc(sizeof(double) * nm));
+    DD_TRY(d_d2c.alloc(sizeof(double) * nm));
+    DD_HIP(hipMemsetAsync(d_gap.p, 0xFF, sizeof(double) * nm, st));   // NaN: no gap yet
+    DD_HIP(hipMemsetAsync(d_qref.p, 0, sizeof(double) * 12 * nm, st));
+  }
   DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+dd_status DDSolver::project_step(int it) {
+  const int64_t nm = M.n_mp;
+  if (!skip_on)
+    return project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, budget_at(it),
+                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st);
+  DD_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(skip_kernel, dim3(g256(nm)), dim3(256), 0, st, nm, d_yw.as<double>(),
+                     d_qref.as<double>(), d_gap.as<double>(), d_idx.as<int64_t>(),
+                     ds->iperm.as<uint32_t>(), ds->w64.as<double>(), d_idx_new.as<int64_t>(),
+                     d_dist.as<double>(), d_list.as<int>(), d_cnt.as<int>(), d_qc.as<double>(),
+                     d_wc.as<int64_t>());
+  DD_HIP(hipGetLastError());
+  int n = 0;
+  DD_HIP(hipMemcpyAsync(&n, d_cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  skipped_total += nm - n;
+  if (n == 0) return DD_OK;
+  DD_TRY(project_whitened(*ds, d_qc.as<double>(), n, d_wc.as<int64_t>(), mode, 0,
+                          d_ic.as<int64_t>(), d_dc.as<double>(), st, d_d2c.as<double>()));
+  hipLaunchKernelGGL(unskip_kernel, dim3(g256(n)), dim3(256), 0, st, n, d_list.as<int>(),
+                     d_ic.as<int64_t>(), d_dc.as<double>(), d_d2c.as<double>(), d_qc.as<double>(),
+                     d_idx_new.as<int64_t>(), d_dist.as<double>(), d_qref.as<double>(),
+                     d_gap.as<double>());
+  DD_HIP(hipGetLastError());
   return DD_OK;
 }
 
@@ -921,8 +1023,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   }
   for (it = 1; it <= max_iter; ++it) {
     DD_TRY(constraint_projection());
-    DD_TRY(project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, ann_budget,
-                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st));
+    DD_TRY(project_step(it));
     hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
                        d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
                        d_idx.as<int64_t>(), d_scal.as<double>());
@@ -949,14 +1050,16 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     }
     // the new association becomes the current one
     std::swap(d_idx.p, d_idx_new.p);
-    if (sc[2] == 0.0) {
+    // under an accuracy schedule the stopping rules wait for the exact walk
+    const bool scheduled = approximate && ann_ramp > 0 && it <= ann_ramp;
+    if (sc[2] == 0.0 && !scheduled) {
       converged = true;
       stop_reason = 1;
       break;
     }
     // an approximate projection gives no descent guarantee: stop once the
     // distance to the data stops decreasing
-    if (approximate && it > 1 && !(sc[1] < prev_full)) {
+    if (approximate && ann_ramp == 0 && it > 1 && !(sc[1] < prev_full)) {
       stop_reason = 2;
       break;
     }
@@ -967,6 +1070,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     res->iterations = it;
     res->converged = converged ? 1 : 0;
     res->stop_reason = stop_reason;
+    res->skipped = skipped_total;
     res->cg_iterations = cg_total;
     res->cg_max_residual = cg_res_max;
     DD_TRY(fetch_results(res->u, res->idx, res->eps, res->sig));

@@ -120,3 +120,48 @@ def test_ann_budget_is_never_worse_than_warm_start(L, config0, C0):
         assert np.all(got <= wd * (1 + 1e-12))                    # never worse than warm
         assert np.all(got >= config0["od"] * (1 - 1e-12))         # never better than exact
     assert recalls[-1] >= recalls[0] and recalls[-1] > 0.9
+
+
+def test_dd_solve_accuracy_schedule(L, C0):
+    """Budgeted walks whose budget grows over the first iterations, then exact
+    walks: the solve ends at an exact fixed point (the last, exact projection
+    leaves every association unchanged) and reports its displacement error
+    against the exact solve from the same start."""
+    import torch
+    e, s = ddsynth.data_points(65536, 1000)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN)
+    n = 4
+    mask, force = ddsynth.box_bc(n, 100.0)
+    init = ddsynth.indices(8 * n ** 3, 65536, 9)
+    exact = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann")
+    ramp = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", ann_budget=1, ann_ramp=6)
+    err = np.linalg.norm(ramp["u"] - exact["u"]) / np.linalg.norm(exact["u"])
+    _say(f"schedule: {ramp['iterations']} iterations (exact {exact['iterations']}), "
+         f"|u - u_exact| / |u_exact| = {err:.3e}")
+    assert exact["converged"] and ramp["converged"] and ramp["stop_reason"] == 1
+    assert ramp["iterations"] > 6
+    states = to_dev(np.concatenate([ramp["eps"], ramp["sig"]], axis=1))
+    idx, _ = L.dd_project(ds, states, mode="fp64")
+    assert np.array_equal(idx.cpu().numpy(), ramp["idx"])
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_dd_solve_skips_unmoved_points_exactly(L, C0, n):
+    """Skipping material points that moved less than half their certified gap
+    leaves the trajectory bitwise unchanged (same associations, distances and
+    u as projecting every point, and as the FP64 scan)."""
+    e, s = ddsynth.data_points(200000, 1010)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN)
+    mask, force = ddsynth.box_bc(n, 100.0)
+    init = ddsynth.indices(8 * n ** 3, 200000, 11)
+    a = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", history=True, skip=True)
+    b = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", history=True)
+    c = L.dd_solve(ds, (n, n, n), mask, force, init, mode="fp64", history=True)
+    total = a["iterations"] * 8 * n ** 3
+    _say(f"{n}^3: {a['iterations']} iterations, skipped {a['skipped']} of {total} projections, "
+         f"{a['elapsed_ms']:.1f} ms (no skip {b['elapsed_ms']:.1f} ms)")
+    assert a["skipped"] > 0 and b["skipped"] == 0
+    for r in (b, c):
+        assert np.array_equal(a["history"], r["history"])
+        assert np.array_equal(a["u"], r["u"])
+        assert np.array_equal(a["d_full"], r["d_full"]) and np.array_equal(a["d_half"], r["d_half"])
