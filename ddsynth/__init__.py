@@ -80,10 +80,13 @@ def _load():
         lib.ddsynth_uniform.argtypes = [u64, i64, dbl, dbl, vp]
         lib.ddsynth_box_muller.argtypes = [vp, vp, i64, vp]
         lib.ddsynth_queries_gen.argtypes = [u64, i64, u64, i64, dbl, vp, dbl, dbl, dbl, vp, vp, vp]
+        lib.ddsynth_points_nonlinear.argtypes = [u64, i64, i64, dbl, dbl, dbl, vp, vp]
+        lib.ddsynth_nonlinear_stress.argtypes = [vp, i64, dbl, dbl, vp]
         lib.ddsynth_elementary.argtypes = [vp, i64, vp]
         for f in ("ddsynth_philox", "ddsynth_philox_many", "ddsynth_points",
                   "ddsynth_queries", "ddsynth_indices", "ddsynth_uniform",
-                  "ddsynth_box_muller", "ddsynth_elementary", "ddsynth_queries_gen"):
+                  "ddsynth_box_muller", "ddsynth_elementary", "ddsynth_queries_gen",
+                  "ddsynth_points_nonlinear", "ddsynth_nonlinear_stress"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -166,6 +169,52 @@ def queries(strain: np.ndarray, stress: np.ndarray, m: int, seed: int,
     return qe, qs, base
 
 
+# The paper's example (Section 3): nonlinear isotropic law, strains in +-0.025.
+PAPER_E = 1000.0
+PAPER_ALPHA = 500.0
+PAPER_EPS_AMP = 0.025
+
+
+def data_points_nonlinear(n: int, seed: int, first: int = 0, eps_amp: float = PAPER_EPS_AMP,
+                          E: float = PAPER_E, alpha: float = PAPER_ALPHA):
+    """(strain[n][6], stress[n][6]) of the paper's example: Voigt strains uniform in
+    [-eps_amp, eps_amp], stress from the nonlinear reference law (no noise)."""
+    strain = np.empty((n, 6), dtype=np.float64)
+    stress = np.empty((n, 6), dtype=np.float64)
+    _load().ddsynth_points_nonlinear(seed, first, n, eps_amp, E, alpha, _ptr(strain), _ptr(stress))
+    return strain, stress
+
+
+def nonlinear_stress(strain: np.ndarray, E: float = PAPER_E, alpha: float = PAPER_ALPHA):
+    strain = np.ascontiguousarray(strain, dtype=np.float64).reshape(-1, 6)
+    out = np.empty_like(strain)
+    _load().ddsynth_nonlinear_stress(_ptr(strain), strain.shape[0], E, alpha, _ptr(out))
+    return out
+
+
+def torsion_bc(n: int, size: float = 10.0, theta_deg: float = 2.0):
+    """The paper's boundary conditions on an n^3 cube of edge `size` (Section 3):
+    nodes on z = 0 fixed; nodes on z = size rotated by theta about the vertical
+    axis through the face centre and fixed in z.  Returns (mask uint8 [ndof],
+    prescribed displacement float64 [ndof], zero nodal force [ndof])."""
+    n1 = n + 1
+    ndof = 3 * n1 ** 3
+    mask = np.zeros(ndof, dtype=np.uint8)
+    val = np.zeros(ndof)
+    h = size / n
+    th = np.deg2rad(theta_deg)
+    c, s = np.cos(th), np.sin(th)
+    for j in range(n1):
+        for i in range(n1):
+            mask[3 * (i + n1 * j) + np.arange(3)] = 1                  # z = 0
+            nid = i + n1 * (j + n1 * n)                                # z = size
+            x, y = i * h - 0.5 * size, j * h - 0.5 * size
+            mask[3 * nid + np.arange(3)] = 1
+            val[3 * nid] = (c - 1.0) * x - s * y
+            val[3 * nid + 1] = s * x + (c - 1.0) * y
+    return mask, val, np.zeros(ndof)
+
+
 def queries_generated(n_data: int, data_seed: int, m: int, seed: int,
                       S0: np.ndarray | None = None, eps_amp: float = EPS_AMP,
                       noise_std: float = DATA_NOISE_STD, eps_std: float = QUERY_EPS_STD,
@@ -217,8 +266,14 @@ class _PointParams(ctypes.Structure):
                 ("S0", ctypes.c_double * 36), ("noise_std", ctypes.c_double)]
 
 
+class _NonlinearParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("eps_amp", ctypes.c_double), ("E", ctypes.c_double),
+                ("alpha", ctypes.c_double)]
+
+
 class DevicePoints:
-    """The data-point recipe on the GPU (same bits as `data_points`).
+    """The data-point recipe on the GPU (same bits as `data_points`, or as
+    `data_points_nonlinear` with law="nonlinear").
 
     `fill_fn` / `user` form a producer for dd_dataset_create_streamed:
     fill(user, first, count, strain_dev, stress_dev, hip_stream) -> 0 on success.
@@ -226,7 +281,7 @@ class DevicePoints:
     """
 
     def __init__(self, seed: int, S0: np.ndarray | None = None, eps_amp: float = EPS_AMP,
-                 noise_std: float = DATA_NOISE_STD):
+                 noise_std: float = DATA_NOISE_STD, law: str = "linear"):
         global _dev_lib
         if _dev_lib is None:
             if not os.path.exists(_DEV_LIB_PATH):
@@ -237,14 +292,22 @@ class DevicePoints:
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
             lib.ddsynth_dev_fill.restype = ctypes.c_int
             lib.ddsynth_dev_params_bytes.restype = ctypes.c_int
+            lib.ddsynth_dev_fill_nonlinear.argtypes = lib.ddsynth_dev_fill.argtypes
+            lib.ddsynth_dev_fill_nonlinear.restype = ctypes.c_int
             if lib.ddsynth_dev_params_bytes() != ctypes.sizeof(_PointParams):
                 raise RuntimeError("libddsynth_dev.so parameter layout mismatch")
             _dev_lib = lib
-        S0 = isotropic_stiffness() if S0 is None else np.asarray(S0, dtype=np.float64)
-        self.params = _PointParams(seed, eps_amp, (ctypes.c_double * 36)(*S0.ravel().tolist()),
-                                   noise_std)
         self.lib = _dev_lib
-        self.fill_fn = ctypes.cast(_dev_lib.ddsynth_dev_fill, ctypes.c_void_p).value
+        if law == "nonlinear":
+            self.params = _NonlinearParams(seed, PAPER_EPS_AMP if eps_amp == EPS_AMP else eps_amp,
+                                           PAPER_E, PAPER_ALPHA)
+            self._fill = _dev_lib.ddsynth_dev_fill_nonlinear
+        else:
+            S0 = isotropic_stiffness() if S0 is None else np.asarray(S0, dtype=np.float64)
+            self.params = _PointParams(seed, eps_amp,
+                                       (ctypes.c_double * 36)(*S0.ravel().tolist()), noise_std)
+            self._fill = _dev_lib.ddsynth_dev_fill
+        self.fill_fn = ctypes.cast(self._fill, ctypes.c_void_p).value
         self.user = ctypes.addressof(self.params)
 
     def generate(self, first: int, n: int, stream: int = 0):
@@ -253,7 +316,7 @@ class DevicePoints:
         s = torch.empty((n, 6), dtype=torch.float64, device="cuda")
         if stream == 0:
             stream = torch.cuda.current_stream().cuda_stream
-        rc = self.lib.ddsynth_dev_fill(self.user, first, n, e.data_ptr(), s.data_ptr(), stream)
+        rc = self._fill(self.user, first, n, e.data_ptr(), s.data_ptr(), stream)
         if rc != 0:
             raise RuntimeError(f"ddsynth_dev_fill failed ({rc})")
         return e, s

@@ -50,6 +50,19 @@ void ddsynth_points(uint64_t seed, int64_t first, int64_t n, double eps_amp,
     dds_point(seed, (uint64_t)(first + i), eps_amp, S0, noise_std, strain + 6 * i, stress + 6 * i);
 }
 
+/* Data points of the paper's example (nonlinear law, no noise), items first .. first+n-1. */
+void ddsynth_points_nonlinear(uint64_t seed, int64_t first, int64_t n, double eps_amp, double E,
+                              double a, double* strain, double* stress) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    dds_point_nonlinear(seed, (uint64_t)(first + i), eps_amp, E, a, strain + 6 * i, stress + 6 * i);
+}
+
+/* The nonlinear reference law applied to given strains (exported for the tests). */
+void ddsynth_nonlinear_stress(const double* strain, int64_t n, double E, double a, double* stress) {
+  for (int64_t i = 0; i < n; ++i) dds_nonlinear_stress(strain + 6 * i, E, a, stress + 6 * i);
+}
+
 /*
  * Query states: base point j uniform over [0, n_data) (stream 16), then
  * strain + eps_std * N(0,1) and stress + sig_std * N(0,1) (streams 18..23).

@@ -188,4 +188,49 @@ DDS_FN void dds_point(uint64_t seed, uint64_t item, double eps_amp, const double
   }
 }
 
+/* Stress of the nonlinear isotropic reference law of the paper's example
+ * (Section 3): sig = E (eps + a eps^3 + 0.5 (tr eps + a (tr eps)^3) I) with the
+ * tensor strain eps (off-diagonal = half the engineering shear) and eps^3 its
+ * matrix cube; Voigt order (11, 22, 33, 23, 13, 12). */
+DDS_FN void dds_nonlinear_stress(const double* e, double E, double a, double* s) {
+  double m[3][3];
+  m[0][0] = e[0]; m[1][1] = e[1]; m[2][2] = e[2];
+  m[1][2] = m[2][1] = 0.5 * e[3];
+  m[0][2] = m[2][0] = 0.5 * e[4];
+  m[0][1] = m[1][0] = 0.5 * e[5];
+  double m2[3][3], m3[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += m[i][k] * m[k][j];
+      m2[i][j] = acc;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) acc += m2[i][k] * m[k][j];
+      m3[i][j] = acc;
+    }
+  const double tr = m[0][0] + m[1][1] + m[2][2];
+  const double vol = 0.5 * (tr + a * tr * tr * tr);
+  double t[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) t[i][j] = E * (m[i][j] + a * m3[i][j] + (i == j ? vol : 0.0));
+  s[0] = t[0][0]; s[1] = t[1][1]; s[2] = t[2][2];
+  s[3] = t[1][2]; s[4] = t[0][2]; s[5] = t[0][1];
+}
+
+/* One data point of the paper's example: the 6 Voigt strain components uniform
+ * in [-eps_amp, eps_amp] (streams 48..51), the stress from the nonlinear law
+ * (no noise). */
+DDS_FN void dds_point_nonlinear(uint64_t seed, uint64_t item, double eps_amp, double E, double a,
+                                double* se, double* ss) {
+  double ua[4], ub[4];
+  dds_uniforms4(seed, item, 48u, ua);
+  dds_uniforms4(seed, item, 50u, ub);
+  const double u[6] = {ua[0], ua[1], ua[2], ua[3], ub[0], ub[1]};
+  for (int k = 0; k < 6; ++k) se[k] = -eps_amp + 2.0 * eps_amp * u[k];
+  dds_nonlinear_stress(se, E, a, ss);
+}
+
 #endif /* DDSYNTH_GEN_CORE_H */

@@ -227,12 +227,16 @@ typedef struct dd_solve_opts {
   int32_t ann_ramp;      /* DD_ANN with a budget: > 0 = accuracy schedule, iteration i <= ann_ramp
                             uses ann_budget * i leaves, later iterations walk exactly (the paper's
                             search accuracy growing over the iterations, Section 4.5) */
+  const double* dirichlet_values;  /* host [ndof] or NULL: prescribed displacements at the
+                                      Dirichlet DOFs (e.g. the rotated face of Section 3's
+                                      example); eta stays homogeneous there */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
 /* P_C by CG even for meshes of at most 16384 DOFs, where dd_solve otherwise
- * forms K^-1 once (blocked Gauss-Jordan on the GPU), keeps it on the dataset
- * for that mesh and Dirichlet pattern (at most 4 GiB of inverses per dataset,
- * least recently used dropped first) and applies it as one product per P_C. */
+ * forms K^-1 once (blocked Gauss-Jordan on the GPU, about 0.4 s at 16384),
+ * keeps it on the dataset for that mesh and Dirichlet pattern (at most 4 GiB
+ * of inverses per dataset, least recently used dropped first) and applies it
+ * as one product per P_C. */
 #define DD_SOLVE_CG 0x2
 /* Exact DD_ANN solves: skip the projection of material points whose state
  * moved less than half the certified gap between their nearest and second
@@ -364,6 +368,22 @@ dd_status dd_server_get_stats(dd_server* srv, dd_server_stats* stats);
 /* Stop the threads; unfinished solves end as DD_ERR_CANCELLED (their tickets
  * become invalid). */
 dd_status dd_server_destroy(dd_server* srv);
+
+/*
+ * The metric of the paper's example (Section 3): principal component analysis
+ * of the data set -- the 12 components centred and scaled by their standard
+ * deviations, the 6 leading principal vectors unscaled into the columns of
+ * A = [A_eps; A_sig] -- and C = sym(A_sig A_eps^-1), the slope of the
+ * principal subspace read as a stiffness (on data lying on sig = C0 eps it
+ * returns C0).
+ *   strain_dev, stress_dev  device float64 [N][6] (borrowed), N >= 12
+ *   C_out                   host float64 [36], row-major
+ * Errors: DD_ERR_ARG (N, pointers, a component with zero variance, a singular
+ * A_eps), DD_ERR_NOT_SPD (sym(A_sig A_eps^-1) not positive definite),
+ * DD_ERR_DEVICE.  Synchronises hip_stream.
+ */
+dd_status dd_metric_pca(const double* strain_dev, const double* stress_dev, int64_t N,
+                        double* C_out, void* hip_stream);
 
 /* Thread-local message for the calling thread's last non-OK status. */
 const char* dd_last_error(void);

@@ -153,4 +153,24 @@ def pair_dist_raw(a_eps, a_sig, b_eps, b_sig, C):
     return out
 
 
+def pca_metric(eps, sig):
+    """The metric of the paper's example (Section 3): principal components of
+    the data, the 12 components centred and scaled by their standard
+    deviations; the 6 leading principal vectors, unscaled, are the columns of
+    A = [A_eps; A_sig]; C = sym(A_sig A_eps^-1).  The paper writes the product
+    as A_eps^-1 A_sig, a similar matrix but not the slope: on data lying on
+    sig = C0 eps the principal subspace is {(v, C0 v)}, so that A_sig = C0 A_eps
+    and only A_sig A_eps^-1 returns C0."""
+    X = np.concatenate([_c(eps), _c(sig)], axis=1)
+    X = X - X.mean(axis=0)
+    cov = X.T @ X / X.shape[0]
+    sd = np.sqrt(np.diag(cov))
+    R = cov / np.outer(sd, sd)
+    w, V = np.linalg.eigh(R)                 # ascending
+    A = V[:, np.argsort(w)[::-1][:6]] * sd[:, None]
+    Ae, As = A[:6], A[6:]
+    C = As @ np.linalg.inv(Ae)
+    return 0.5 * (C + C.T)
+
+
 from . import fe  # noqa: E402,F401  (finite elements, P_C and the DD loop)

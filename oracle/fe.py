@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE: part of the oracle package; never used by the GPU library.
 
 Discretisation (the paper's setting of Section 2 on a structured cube):
-  * unit cube [0,1]^3 split into n^3 trilinear hexahedra of edge h = 1/n;
+  * cube [0,L]^3 (L = 1 unless given) split into n^3 trilinear hexahedra of edge h = L/n;
     node (i, j, k) has id i + (n+1)(j + (n+1)k); DOF = 3 * node + component;
   * element (ex, ey, ez) has id ex + n(ey + n ez);
   * 2x2x2 Gauss points at +-1/sqrt(3) with unit weights, point a + 2(b + 2c)
@@ -17,7 +17,9 @@ P_C (Section 2, eqs. "KuE" and "KeS"): given data states z* = (eps*, sig*),
     K u   = E = A_e { w B^T C eps* }
     K eta = S = f - A_e { w B^T sig* }
     eps = B u,  sig = sig* + C B eta
-with homogeneous Dirichlet conditions on u and eta at the constrained DOFs.
+with the prescribed displacements (zero unless given) on u and homogeneous
+conditions on eta at the constrained DOFs: the free part of u solves
+K_ff u_f = E_f - K_fd u_D.
 K = A_e { w B^T C B } is factorised once (Section 2, after eq. "KeS"); the
 factorisation is a library sparse LU (SuperLU through scipy), used only as the
 "solve K x = b" step.
@@ -76,8 +78,9 @@ def strain_operators(h: float) -> np.ndarray:
 
 @dataclass
 class Mesh:
-    """Structured n^3 hexahedral mesh of the unit cube."""
+    """Structured n^3 hexahedral mesh of the cube [0, size]^3."""
     n: int
+    size: float = 1.0
     h: float = field(init=False)
     n_nodes: int = field(init=False)
     n_dof: int = field(init=False)
@@ -90,7 +93,7 @@ class Mesh:
 
     def __post_init__(self):
         n = self.n
-        self.h = 1.0 / n
+        self.h = self.size / n
         self.n_nodes = (n + 1) ** 3
         self.n_dof = 3 * self.n_nodes
         self.n_el = n ** 3
@@ -132,6 +135,25 @@ class Mesh:
             mask[3 * nodes + c] = True
         return mask
 
+    def torsion(self, theta_deg: float):
+        """The paper's boundary conditions (Section 3): the face z = 0 fixed, the
+        face z = size rotated by theta about the vertical axis through its
+        centre and fixed in z.  Returns (mask, prescribed displacement)."""
+        mask = np.zeros(self.n_dof, dtype=bool)
+        val = np.zeros(self.n_dof)
+        th = np.deg2rad(theta_deg)
+        rot = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        for z, turn in ((0.0, False), (self.size, True)):
+            nodes = np.where(np.isclose(self.coords[:, 2], z))[0]
+            for c in range(3):
+                mask[3 * nodes + c] = True
+            if turn:
+                r = self.coords[nodes, :2] - 0.5 * self.size
+                d = r @ rot.T - r
+                val[3 * nodes] = d[:, 0]
+                val[3 * nodes + 1] = d[:, 1]
+        return mask, val
+
     def traction_x1(self, t: float) -> np.ndarray:
         """Consistent nodal forces of a uniform normal traction t (+x) on the face x = 1."""
         f = np.zeros(self.n_dof)
@@ -166,9 +188,11 @@ class Mesh:
 
 
 class ConstraintProjector:
-    """P_C for a fixed mesh, metric C, Dirichlet mask and load f (K factorised once)."""
+    """P_C for a fixed mesh, metric C, Dirichlet mask (with prescribed
+    displacements u_D, zero by default) and load f (K factorised once)."""
 
-    def __init__(self, mesh: Mesh, C: np.ndarray, mask: np.ndarray, f: np.ndarray):
+    def __init__(self, mesh: Mesh, C: np.ndarray, mask: np.ndarray, f: np.ndarray,
+                 u_dirichlet: np.ndarray | None = None):
         self.mesh = mesh
         self.C = np.asarray(C, dtype=np.float64)
         self.mask = np.asarray(mask, dtype=bool)
@@ -178,10 +202,18 @@ class ConstraintProjector:
         self.K = K
         Kff = K[self.free][:, self.free].tocsc()
         self.lu = spla.splu(Kff)
+        self.uD = np.zeros(mesh.n_dof)
+        if u_dirichlet is not None:
+            self.uD[self.mask] = np.asarray(u_dirichlet, dtype=np.float64)[self.mask]
+        self.lift = K @ self.uD      # K_fd u_D on the free rows
 
-    def solve(self, rhs: np.ndarray) -> np.ndarray:
+    def solve(self, rhs: np.ndarray, prescribed: np.ndarray | None = None) -> np.ndarray:
         x = np.zeros(self.mesh.n_dof)
-        x[self.free] = self.lu.solve(rhs[self.free])
+        if prescribed is None:
+            x[self.free] = self.lu.solve(rhs[self.free])
+        else:
+            x[self.free] = self.lu.solve(rhs[self.free] - self.lift[self.free])
+            x[self.mask] = prescribed[self.mask]
         return x
 
     def __call__(self, eps_star: np.ndarray, sig_star: np.ndarray):
@@ -189,7 +221,7 @@ class ConstraintProjector:
         m = self.mesh
         E = m.assemble_vector(eps_star @ self.C.T)
         S = self.f - m.assemble_vector(sig_star)
-        u = self.solve(E)
+        u = self.solve(E, self.uD)
         eta = self.solve(S)
         eps = m.strains(u)
         sig = sig_star + m.strains(eta) @ self.C.T
@@ -211,7 +243,7 @@ class DDResult:
 
 
 def dd_solve(data_eps, data_sig, C, mesh: Mesh, mask, f, init_idx, max_iter=500,
-             project=None, record_history=False) -> DDResult:
+             project=None, record_history=False, u_dirichlet=None) -> DDResult:
     """Plain DD fixed-point loop (Section 2): z_{i+1} = P_D(P_C(z_i)).
 
     project(eps, sig) -> (idx, dist) is the P_D step; by default the brute-force
@@ -232,7 +264,7 @@ def dd_solve(data_eps, data_sig, C, mesh: Mesh, mask, f, init_idx, max_iter=500,
         def project(e, s):
             i, d, _ = pd_raw(data_eps, data_sig, C, e, s)
             return i, d
-    pc = ConstraintProjector(mesh, C, mask, f)
+    pc = ConstraintProjector(mesh, C, mask, f, u_dirichlet)
     idx = np.asarray(init_idx, dtype=np.int64).copy()
     d_half, d_full, changed, hist = [], [], [], []
     if record_history:

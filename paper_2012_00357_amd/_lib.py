@@ -67,8 +67,9 @@ def _load():
     lib.dd_dataset_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.dd_project.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_project_opts), vp, vp, vp]
     lib.dd_selftest_mfma.argtypes = [i32, vp, vp, vp]
+    lib.dd_metric_pca.argtypes = [vp, vp, i64, vp, vp]
     for f in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
-              "dd_dataset_info", "dd_project", "dd_selftest_mfma"):
+              "dd_dataset_info", "dd_project", "dd_selftest_mfma", "dd_metric_pca"):
         getattr(lib, f).restype = ctypes.c_int
     lib.dd_last_error.restype = ctypes.c_char_p
     lib.dd_version.restype = ctypes.c_char_p
@@ -205,6 +206,17 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
     return idx_out, dist_out
 
 
+def dd_metric_pca(strain, stress, stream=None) -> np.ndarray:
+    """dd_metric_pca: device float64 [N][6] strain/stress -> the 6x6 PCA metric (host)."""
+    import torch
+    n = int(strain.shape[0])
+    ps = _dev_ptr(strain, torch.float64, (6,), "strain")
+    pt = _dev_ptr(stress, torch.float64, (6,), "stress")
+    C = np.zeros(36)
+    _check(_lib.dd_metric_pca(ps, pt, n, C.ctypes.data, _stream(stream)), "dd_metric_pca")
+    return C.reshape(6, 6)
+
+
 def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
     A = np.ascontiguousarray(A, dtype=np.float64)
     B = np.ascontiguousarray(np.zeros(1) if B is None else B, dtype=np.float64)
@@ -229,7 +241,7 @@ class dd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("cg_max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("ann_budget", ctypes.c_int32),
-                ("ann_ramp", ctypes.c_int32)]
+                ("ann_ramp", ctypes.c_int32), ("dirichlet_values", ctypes.c_void_p)]
 
 
 class dd_solve_result(ctypes.Structure):
@@ -251,7 +263,7 @@ _lib.dd_solve.restype = ctypes.c_int
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
              cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, cg: bool = False,
-             ann_ramp: int = 0, skip: bool = False, stream=None):
+             ann_ramp: int = 0, skip: bool = False, dirichlet_values=None, stream=None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
@@ -274,9 +286,12 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
                           out["sig"].ctypes.data, out["d_half"].ctypes.data,
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
                           hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0, 0)
+    dv = None
+    if dirichlet_values is not None:
+        dv = np.ascontiguousarray(np.asarray(dirichlet_values, dtype=np.float64).reshape(n_dof))
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
                          cg_max_iter, (0 if graph else 1) | (2 if cg else 0) | (4 if skip else 0),
-                         cg_tol, ann_budget, ann_ramp)
+                         cg_tol, ann_budget, ann_ramp, dv.ctypes.data if dv is not None else None)
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):

@@ -86,6 +86,7 @@ class DDSolver {
   DevBuf d_rowptr, d_col, d_val, d_dinv, d_mask, d_f, d_b, d_x, d_work;
   DevBuf d_idx, d_idx_new, d_dist, d_zw, d_zc, d_yw, d_scal, d_cgstat;
   DevBuf d_part, d_cgstate;
+  DevBuf d_uD, d_lift;   // prescribed displacements and K_fd u_D (empty: homogeneous)
   DevBuf arena;   // one allocation holding every buffer above
   // skipping of unmoved material points (exact DD_ANN): reference state, half
   // gap, compacted list and its projection buffers

@@ -202,15 +202,20 @@ __global__ void gather_z_kernel(const int64_t* __restrict__ idx, int64_t n_mp, i
 // RHS by gathering, per DOF, the contributions of its (<= 8) elements and their
 // Gauss points in a fixed order:  E = A{ w B^T C eps* },  S = f - A{ w B^T sig* }.
 // Dirichlet DOFs get 0.
+// E = A_e{w B^T C eps*} - K_fd u_D on free DOFs and u_D on Dirichlet DOFs (the
+// identity rows of K carry the prescribed displacement), S = f - A_e{w B^T sig*}
+// on free DOFs and 0 on Dirichlet DOFs (eta vanishes there).  uD and lift may be
+// null (homogeneous conditions).
 __global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
                                     const double* __restrict__ zc, const uint8_t* __restrict__ mask,
-                                    const double* __restrict__ f, double* __restrict__ E,
+                                    const double* __restrict__ f, const double* __restrict__ uD,
+                                    const double* __restrict__ lift, double* __restrict__ E,
                                     double* __restrict__ S) {
   const int64_t dof = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n_dof = 3 * (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   if (dof >= n_dof) return;
   if (mask[dof]) {
-    E[dof] = 0.0;
+    E[dof] = uD ? uD[dof] : 0.0;
     S[dof] = 0.0;
     return;
   }
@@ -235,7 +240,7 @@ __global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
           }
         }
       }
-  E[dof] = w * se;
+  E[dof] = lift ? w * se - lift[dof] : w * se;
   S[dof] = f[dof] - w * ss;
 }
 
@@ -648,12 +653,60 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
     DevBuf* buf;
     size_t bytes;
   };
+  // prescribed displacements: u_D on Dirichlet DOFs and the lifting K_fd u_D
+  std::vector<double> uD, lift;
+  const double* vals = opts ? opts->dirichlet_values : nullptr;
+  if (vals) {
+    uD.assign(nd, 0.0);
+    lift.assign(nd, 0.0);
+    bool any = false;
+    for (int64_t d = 0; d < nd; ++d) {
+      if (!std::isfinite(vals[d])) return set_error(DD_ERR_ARG, "non-finite Dirichlet value");
+      if (mask[d] && vals[d] != 0.0) {
+        uD[d] = vals[d];
+        any = true;
+      }
+    }
+    if (any) {
+      double Ke[24 * 24];
+      element_stiffness(M, D.C, Ke);
+      for (int ez = 0; ez < M.nz; ++ez)
+        for (int ey = 0; ey < M.ny; ++ey)
+          for (int ex = 0; ex < M.nx; ++ex) {
+            int64_t g[24];
+            double ue[24];
+            bool nz = false;
+            for (int a = 0; a < 8; ++a) {
+              const int64_t nid = M.node(ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
+              for (int c = 0; c < 3; ++c) {
+                g[3 * a + c] = 3 * nid + c;
+                ue[3 * a + c] = uD[3 * nid + c];
+                nz = nz || ue[3 * a + c] != 0.0;
+              }
+            }
+            if (!nz) continue;
+            for (int i = 0; i < 24; ++i) {
+              if (mask[g[i]]) continue;
+              double acc = 0.0;
+              for (int j = 0; j < 24; ++j) acc += Ke[24 * i + j] * ue[j];
+              lift[g[i]] += acc;
+            }
+          }
+    } else {
+      uD.clear();
+      lift.clear();
+    }
+  }
   std::vector<Part> parts = {
       {&d_mask, (size_t)nd}, {&d_f, sizeof(double) * nd}, {&d_b, sizeof(double) * 2 * nd},
       {&d_x, sizeof(double) * 2 * nd}, {&d_idx, sizeof(int64_t) * nm},
       {&d_idx_new, sizeof(int64_t) * nm}, {&d_dist, sizeof(double) * nm},
       {&d_zw, sizeof(double) * 12 * nm}, {&d_zc, sizeof(double) * 12 * nm},
       {&d_yw, sizeof(double) * 12 * nm}, {&d_scal, sizeof(double) * 4}, {&d_cgstat, 64}};
+  if (!uD.empty()) {
+    parts.push_back({&d_uD, sizeof(double) * nd});
+    parts.push_back({&d_lift, sizeof(double) * nd});
+  }
   if (need_csr) {
     parts.push_back({&d_rowptr, sizeof(int32_t) * (nd + 1)});
     parts.push_back({&d_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)});
@@ -685,6 +738,10 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   }
   if (!want_dense)
     DD_HIP(hipMemcpyAsync(d_dinv.p, dinv.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  if (!uD.empty()) {
+    DD_HIP(hipMemcpyAsync(d_uD.p, uD.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+    DD_HIP(hipMemcpyAsync(d_lift.p, lift.data(), sizeof(double) * nd, hipMemcpyHostToDevice, st));
+  }
   DD_HIP(hipMemcpyAsync(d_mask.p, mask, nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemcpyAsync(d_f.p, force, sizeof(double) * nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double) * 2 * nd, st));
@@ -775,7 +832,8 @@ dd_status DDSolver::pc_begin() {
                      d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
   hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
-                     d_b.as<double>(), d_b.as<double>() + nd);
+                     d_uD.as<double>(), d_lift.as<double>(), d_b.as<double>(),
+                     d_b.as<double>() + nd);
   cg_it = 0;
   if (dense) {
     DD_TRY(dense_apply(*dense, d_b.as<double>(), d_x.as<double>(), st));
@@ -972,7 +1030,8 @@ dd_status DDSolver::constraint_projection() {
                      d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
   hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
-                     d_b.as<double>(), d_b.as<double>() + nd);
+                     d_uD.as<double>(), d_lift.as<double>(), d_b.as<double>(),
+                     d_b.as<double>() + nd);
   DD_TRY(cg_solve());
   hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
                      d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),

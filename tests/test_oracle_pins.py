@@ -375,3 +375,99 @@ def test_input_bc_matches_oracle_mesh():
         m = fe.Mesh(n)
         assert np.array_equal(mask.astype(bool), m.clamp_mask())
         np.testing.assert_allclose(f, m.traction_x1(100.0), rtol=1e-15, atol=0)
+
+
+# ----------------------------------------------------------------------------
+# The paper's example (Section 3): nonlinear law, PCA metric, torsion
+# ----------------------------------------------------------------------------
+def test_nonlinear_law_closed_forms():
+    """Uniaxial strain and simple shear of the reference law, by hand."""
+    E, a = ddsynth.PAPER_E, ddsynth.PAPER_ALPHA
+    x = 0.02
+    s = ddsynth.nonlinear_stress(np.array([x, 0, 0, 0, 0, 0]))[0]
+    k = x + a * x ** 3
+    np.testing.assert_allclose(s, [1.5 * E * k, 0.5 * E * k, 0.5 * E * k, 0, 0, 0], rtol=1e-14,
+                               atol=1e-12)
+    g = 0.03                                 # engineering shear 12: tensor component g/2
+    s = ddsynth.nonlinear_stress(np.array([0, 0, 0, 0, 0, g]))[0]
+    np.testing.assert_allclose(s, [0, 0, 0, 0, 0, E * (g / 2 + a * (g / 2) ** 3)], rtol=1e-14,
+                               atol=1e-12)
+    e, s = ddsynth.data_points_nonlinear(1000, 3)
+    assert np.abs(e).max() <= 0.025 and np.array_equal(ddsynth.nonlinear_stress(e), s)
+
+
+def test_pca_metric_closed_forms(C0):
+    """Linear noise-free data give back their stiffness; at vanishing amplitude
+    the nonlinear law gives its tangent E (I + 1/2 11^T) (normal) and E/2
+    (shear); the metric is invariant under reordering and scales with stress."""
+    e, s = ddsynth.data_points(40000, 5, noise_std=0.0)
+    np.testing.assert_allclose(oracle.pca_metric(e, s), C0, rtol=0, atol=1e-9 * C0.max())
+    E = ddsynth.PAPER_E
+    T = np.zeros((6, 6))
+    T[:3, :3] = 0.5 * E
+    T[:3, :3] += E * np.eye(3)
+    T[3:, 3:] = 0.5 * E * np.eye(3)
+    e, s = ddsynth.data_points_nonlinear(40000, 6, eps_amp=1e-6)
+    np.testing.assert_allclose(oracle.pca_metric(e, s), T, rtol=0, atol=1e-6 * E)
+    e, s = ddsynth.data_points_nonlinear(20000, 7)
+    C = oracle.pca_metric(e, s)
+    p = np.random.default_rng(0).permutation(20000)
+    tol = 1e-12 * np.abs(C).max()
+    np.testing.assert_allclose(oracle.pca_metric(e[p], s[p]), C, rtol=0, atol=tol)
+    np.testing.assert_allclose(oracle.pca_metric(e, 3.0 * s), 3.0 * C, rtol=0, atol=3 * tol)
+    assert np.allclose(C, C.T) and np.linalg.eigvalsh(C).min() > 0
+
+
+def test_torsion_boundary_conditions():
+    m = fe.Mesh(4, size=10.0)
+    mask, val = m.torsion(2.0)
+    top = np.where(np.isclose(m.coords[:, 2], 10.0))[0]
+    bot = np.where(np.isclose(m.coords[:, 2], 0.0))[0]
+    assert mask.sum() == 3 * (len(top) + len(bot))
+    th = np.deg2rad(2.0)
+    corner = top[np.argmax(m.coords[top, 0] + m.coords[top, 1])]   # (10, 10, 10)
+    want = np.array([5 * np.cos(th) - 5 * np.sin(th) - 5, 5 * np.sin(th) + 5 * np.cos(th) - 5, 0])
+    np.testing.assert_allclose(val[3 * corner:3 * corner + 3], want, rtol=1e-14, atol=1e-15)
+    assert np.all(val[3 * bot[0]:3 * bot[0] + 3] == 0)
+    gm, gv, gf = ddsynth.torsion_bc(4, 10.0, 2.0)
+    assert np.array_equal(gm.astype(bool), mask) and np.allclose(gv, val, rtol=0, atol=1e-14)
+    assert not gf.any()
+
+
+def test_pc_with_prescribed_affine_displacement(C0):
+    """Patch test with prescribed displacements: u = G x on every boundary node
+    and data planted at the uniform strain of G; P_C returns u = G x at every
+    node (interior included) and that strain at every material point."""
+    m = fe.Mesh(3, size=2.0)
+    G = np.array([[1e-3, 2e-4, -1e-4], [3e-4, -5e-4, 2e-4], [-2e-4, 1e-4, 7e-4]])
+    exact = (m.coords @ G.T).ravel()
+    bnd = np.any(np.isclose(m.coords, 0.0) | np.isclose(m.coords, 2.0), axis=1)
+    mask = np.repeat(bnd, 3)
+    eps = np.array([G[0, 0], G[1, 1], G[2, 2], G[1, 2] + G[2, 1], G[0, 2] + G[2, 0],
+                    G[0, 1] + G[1, 0]])
+    es, ss = np.tile(eps, (m.n_mp, 1)), np.tile(C0 @ eps, (m.n_mp, 1))
+    f = np.zeros(m.n_dof)
+    pc = fe.ConstraintProjector(m, C0, mask, f, exact)
+    u, eta, e_out, s_out = pc(es, ss)
+    np.testing.assert_allclose(u, exact, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(e_out, es, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(s_out, ss, rtol=0, atol=1e-9)
+
+
+def test_dd_torsion_descends():
+    """The DD loop on the paper's problem (nonlinear data, PCA metric, torsion)
+    decreases the global distance monotonically and converges."""
+    m = fe.Mesh(2, size=10.0)
+    mask, val = m.torsion(2.0)
+    e, s = ddsynth.data_points_nonlinear(3000, 12)
+    C = oracle.pca_metric(e, s)
+    r = fe.dd_solve(e, s, C, m, mask, np.zeros(m.n_dof), ddsynth.indices(m.n_mp, 3000, 13),
+                    u_dirichlet=val)
+    assert r.converged
+    tol = 1e-12 * r.d_half[0]
+    for i in range(r.iterations):
+        assert r.d_full[i] <= r.d_half[i] + tol
+        if i:
+            assert r.d_half[i] <= r.d_full[i - 1] + tol
+    top = np.where(np.isclose(m.coords[:, 2], 10.0))[0]
+    np.testing.assert_allclose(r.u[3 * top], val[3 * top], rtol=0, atol=1e-15)
