@@ -295,6 +295,65 @@ def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8):
     return out
 
 
+def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_000_000_000),
+              seeds=5, mode="ann"):
+    """The paper's own example (Section 3): cube of edge 10 mm, 20^3 hexahedra
+    (64000 material points), bottom fixed, top rotated by 2 degrees; data from
+    the nonlinear law with strains in +-0.025; metric from the PCA of the data;
+    exact projections.  Per data-set size: iterations, final global distance
+    and solve time over `seeds` random initial associations."""
+    import numpy as np
+    import torch
+
+    import ddsynth
+    n, size = 20, 10.0
+    mask, val, force = ddsynth.torsion_bc(n, size, 2.0)
+    out = {"workload": "paper example: 20^3 hex cube (edge 10 mm, 64000 material points), bottom "
+                       "fixed, top rotated 2 deg; nonlinear law E=1000 MPa, alpha=500, strains "
+                       "+-0.025; PCA metric; exact " + mode + " projections",
+           "runs": []}
+    for N in Ns:
+        seed = 3000 + N % 997
+        t = time.time()
+        if N <= 1_000_000:
+            e, s = ddsynth.data_points_nonlinear(N, seed)
+            de, dsg = torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda()
+            C = L.dd_metric_pca(de, dsg)
+            ds = L.dd_dataset_create(de, dsg, C, packs=0x1 | 0x4 | 0x10)
+            del de, dsg
+        else:
+            # generated on the device and streamed into the dataset; the metric
+            # from the PCA of the first 2^24 points (a uniform sample of the set)
+            gen = ddsynth.DevicePoints(seed, law="nonlinear")
+            se, ss = gen.generate(0, 1 << 24)
+            C = L.dd_metric_pca(se, ss)
+            del se, ss
+            torch.cuda.empty_cache()
+            ds = L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user, packs=0x1 | 0x10)
+        torch.cuda.synchronize()
+        build_s = time.time() - t
+        its, dist, ms = [], [], []
+        for seed in range(seeds):
+            init = ddsynth.indices(8 * n ** 3, N, 5000 + seed)
+            t = time.time()
+            r = L.dd_solve(ds, (n, n, n, size, size, size), mask, force, init, mode=mode,
+                           dirichlet_values=val)
+            ms.append((time.time() - t) * 1e3)
+            its.append(r["iterations"])
+            dist.append(float(r["d_full"][-1]))
+        run = {"N": N, "dataset_build_s": round(build_s, 2),
+               "mean_iterations": round(float(np.mean(its)), 2),
+               "mean_final_global_distance": float(np.mean(dist)),
+               "mean_solve_ms": round(float(np.mean(ms)), 1),
+               "p50_solve_ms": round(float(np.percentile(ms, 50)), 1)}
+        out["runs"].append(run)
+        log(f"paper example N={N}: {run['mean_iterations']} iterations, final distance "
+            f"{run['mean_final_global_distance']:.4g}, {run['mean_solve_ms']} ms")
+        ds.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +373,10 @@ def main():
     ap.add_argument("--skip-ann", action="store_true", help="skip the N=1e9 ANN leg")
     ap.add_argument("--serve-solves", type=int, default=12,
                     help="solves per Poisson run of the serving leg (N=2^26); 0 = skip")
+    ap.add_argument("--paper-seeds", type=int, default=3,
+                    help="random starts per data-set size in the paper-example leg; 0 = skip")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run only the paper-example leg and print its JSON object")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg and print its JSON object")
     ap.add_argument("--ann-only", action="store_true",
@@ -337,6 +400,10 @@ def main():
     torch.cuda.set_device(0)
     N, m = 1 << args.log2n, args.m
     C = ddsynth.isotropic_stiffness()
+    if args.paper_only:
+        print(json.dumps({"paper_example": paper_leg(L, seeds=max(args.paper_seeds, 1))}),
+              flush=True)
+        return
     if args.serve_only:
         print(json.dumps({"serving": serve_leg(L, C, args.serve_solves)}), flush=True)
         return
@@ -462,6 +529,9 @@ def main():
     serving = None
     if args.serve_solves > 0:
         serving = serve_leg(L, C, args.serve_solves)
+    paper = None
+    if args.paper_seeds > 0:
+        paper = paper_leg(L, seeds=args.paper_seeds)
 
     cpu = None
     if not args.skip_cpu:
@@ -496,6 +566,7 @@ def main():
         "dd_solve": dd,
         "ann": ann,
         "serving": serving,
+        "paper_example": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
