@@ -210,7 +210,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
     return out
 
 
-def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8):
+def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8, modes=("bf16", "ann")):
     """Serving: N = 2^26 resident data points (BF16 + FP64 packs); DD solves on
     4^3, 8^3, 16^3 and 24^3 hexahedra in equal mix, clamp + normal traction drawn
     in [50, 200] MPa, random initial associations.  Capacity = solves/s of a burst
@@ -223,7 +223,7 @@ def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8):
     N = 1 << 26
     e, s = ddsynth.data_points(N, 1004)
     ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
-                             packs=0x1 | 0x4)
+                             packs=0x1 | 0x4 | 0x10)
     del e, s
     torch.cuda.empty_cache()
     sizes = (4, 8, 16, 24)
@@ -236,61 +236,67 @@ def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8):
         mask, unit = bcs[n]
         return ((n, n, n), mask, unit * t, ddsynth.indices(8 * n ** 3, N, 40000 + k))
 
-    out = {"workload": "serving, N=2^26 resident (BF16 + FP64), DD solves on 4^3/8^3/16^3/24^3 hex "
-                       "(equal mix), traction U[50,200] MPa, BF16 projections batched across solves",
+    out = {"workload": "serving, N=2^26 resident (BF16 + FP64 packs and the tree), DD solves on "
+                       "4^3/8^3/16^3/24^3 hex (equal mix), traction U[50,200] MPa, projections "
+                       "batched across solves (exact in every mode)",
            "N": N}
-    # warm-up: one solve of each size
-    srv = L.DDServer(ds, mode="bf16")
-    for t in [srv.submit(*request(k)) for k in range(4)]:
-        srv.wait(t)
-    srv.close()
-    # capacity: a burst submitted at once
-    srv = L.DDServer(ds, mode="bf16")
-    t0 = time.time()
-    for t in [srv.submit(*request(100 + k)) for k in range(n_cap)]:
-        srv.wait(t)
-    cap = n_cap / (time.time() - t0)
-    st = srv.stats()
-    srv.close()
-    out["capacity_solves_per_s"] = round(cap, 3)
-    out["capacity_queries_per_s"] = round(st["queries_per_s"], 1)
-    log(f"serving capacity: {cap:.3f} solves/s ({st['queries_per_s']:.0f} queries/s)")
-    out["runs"] = []
-    for frac in fracs:
-        lam = frac * cap
-        arrivals = np.cumsum(rng.exponential(1.0 / lam, n_solves))
-        srv = L.DDServer(ds, mode="bf16")
-        tickets, lat, iters, conv = [], [], [], 0
+    for mode in modes:
+        res = {}
+        # warm-up: one solve of each size (forms the cached inverses)
+        srv = L.DDServer(ds, mode=mode)
+        for t in [srv.submit(*request(k)) for k in range(4)]:
+            srv.wait(t)
+        srv.close()
+        # capacity: a burst submitted at once
+        srv = L.DDServer(ds, mode=mode)
         t0 = time.time()
-        for k, ta in enumerate(arrivals):
-            dt = ta - (time.time() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(srv.submit(*request(1000 * (1 + int(frac * 10)) + k)))
-        for t in tickets:
-            r = srv.wait(t)
-            lat.append(r["elapsed_ms"])
-            iters.append(r["iterations"])
-            conv += int(r["converged"])
-        wall = time.time() - t0
+        for t in [srv.submit(*request(100 + k)) for k in range(n_cap)]:
+            srv.wait(t)
+        cap = n_cap / (time.time() - t0)
         st = srv.stats()
         srv.close()
-        lat = np.array(lat)
-        run = {"rate_fraction": frac, "lambda_solves_per_s": round(lam, 3), "solves": n_solves,
-               "solve_p50_ms": round(float(np.percentile(lat, 50)), 1),
-               "solve_p99_ms": round(float(np.percentile(lat, 99)), 1),
-               "projection_p50_ms": round(st["proj_p50_ms"], 2),
-               "projection_p99_ms": round(st["proj_p99_ms"], 2),
-               "queue_p50_ms": round(st["queue_p50_ms"], 2),
-               "queue_p99_ms": round(st["queue_p99_ms"], 2),
-               "queries_per_s": round(st["queries"] / wall, 1),
-               "batches": st["batches"], "mean_batch": round(st["queries"] / max(st["batches"], 1), 1),
-               "peak_active": st["peak_active"], "peak_hbm_bytes": st["peak_bytes"],
-               "mean_iterations": round(float(np.mean(iters)), 2), "converged": conv}
-        out["runs"].append(run)
-        log(f"serving at {frac} x capacity ({lam:.3f}/s): solve p50 {run['solve_p50_ms']} ms, "
-            f"p99 {run['solve_p99_ms']} ms, projection p50 {run['projection_p50_ms']} ms, "
-            f"p99 {run['projection_p99_ms']} ms, {run['queries_per_s']:.0f} queries/s")
+        res["capacity_solves_per_s"] = round(cap, 3)
+        res["capacity_queries_per_s"] = round(st["queries_per_s"], 1)
+        log(f"serving ({mode}) capacity: {cap:.3f} solves/s ({st['queries_per_s']:.0f} queries/s)")
+        res["runs"] = []
+        for frac in fracs:
+            lam = frac * cap
+            arrivals = np.cumsum(rng.exponential(1.0 / lam, n_solves))
+            srv = L.DDServer(ds, mode=mode)
+            tickets, lat, iters, conv = [], [], [], 0
+            t0 = time.time()
+            for k, ta in enumerate(arrivals):
+                dt = ta - (time.time() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(srv.submit(*request(1000 * (1 + int(frac * 10)) + k)))
+            for t in tickets:
+                r = srv.wait(t)
+                lat.append(r["elapsed_ms"])
+                iters.append(r["iterations"])
+                conv += int(r["converged"])
+            wall = time.time() - t0
+            st = srv.stats()
+            srv.close()
+            lat = np.array(lat)
+            run = {"rate_fraction": frac, "lambda_solves_per_s": round(lam, 3), "solves": n_solves,
+                   "solve_p50_ms": round(float(np.percentile(lat, 50)), 1),
+                   "solve_p99_ms": round(float(np.percentile(lat, 99)), 1),
+                   "projection_p50_ms": round(st["proj_p50_ms"], 2),
+                   "projection_p99_ms": round(st["proj_p99_ms"], 2),
+                   "queue_p50_ms": round(st["queue_p50_ms"], 2),
+                   "queue_p99_ms": round(st["queue_p99_ms"], 2),
+                   "queries_per_s": round(st["queries"] / wall, 1),
+                   "batches": st["batches"],
+                   "mean_batch": round(st["queries"] / max(st["batches"], 1), 1),
+                   "peak_active": st["peak_active"], "peak_hbm_bytes": st["peak_bytes"],
+                   "mean_iterations": round(float(np.mean(iters)), 2), "converged": conv}
+            res["runs"].append(run)
+            log(f"serving ({mode}) at {frac} x capacity ({lam:.3f}/s): solve p50 "
+                f"{run['solve_p50_ms']} ms, p99 {run['solve_p99_ms']} ms, projection p50 "
+                f"{run['projection_p50_ms']} ms, p99 {run['projection_p99_ms']} ms, "
+                f"{run['queries_per_s']:.0f} queries/s")
+        out[mode] = res
     ds.close()
     return out
 
