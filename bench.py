@@ -105,8 +105,10 @@ def dd_solve_latency(L, C, R):
     return out
 
 
-ANN_BYTES_PER_POINT = 48.0    # FP32 whitened row read per visited point
-ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per tested box
+ANN_BYTES_PER_POINT = 24.0    # FP16 scaled offsets (12) read per visited point
+ANN_BYTES_PER_LEAF = 64.0     # leaf centre, radius (FP32) read per visited leaf
+ANN_BYTES_PER_LEAF_BOX = 24.0  # quantised leaf box (lo[12], hi[12] as bytes) per test
+ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per test of a higher box
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 
 
@@ -133,7 +135,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
            "dataset_gb": round(ds.info()[1] / 1e9, 2)}
 
     def run(warm, budget):
-        walk, tot, vis, box = [], [], 0, 0
+        walk, tot, vis, box, lvs, lbox = [], [], 0, 0, 0, 0
         L.dd_project(ds, states, warm_start_idx=warm, mode="ann", ann_budget=budget)
         for _ in range(steps):
             i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode="ann",
@@ -142,12 +144,17 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
             tot.append(st["total_ms"])
             vis += st["visited"]
             box += st["boxes"]
+            lvs += st["leaves"]
+            lbox += st["leaf_boxes"]
         w, tt = sum(walk) / steps, sum(tot) / steps
-        byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_BOX * box) / steps
+        byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
+                + ANN_BYTES_PER_LEAF_BOX * lbox + ANN_BYTES_PER_BOX * (box - lbox)) / steps
         return i, d, {"walk_ms": round(w, 3), "total_ms": round(tt, 3),
                       "proj_per_s": round(m / (tt / 1e3), 1),
                       "points_per_query": round(vis / steps / m, 1),
                       "boxes_per_query": round(box / steps / m, 1),
+                      "leaves_per_query": round(lvs / steps / m, 1),
+                      "leaf_boxes_per_query": round(lbox / steps / m, 1),
                       "algorithmic_bytes_per_launch": round(byts), "achieved_gbs": round(byts / w / 1e6, 1)}
 
     ie, de, cold = run(None, 0)
@@ -158,7 +165,9 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
                        "traffic": profile_traffic("ann_walk_N1e9_m32768.md",
                                                   f"N={N} m={m} exact warm"),
                        "kernel": "ann_walk_kernel (exact, warm-started)",
-                       "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_box": ANN_BYTES_PER_BOX}
+                       "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_leaf": ANN_BYTES_PER_LEAF,
+                       "bytes_per_leaf_box": ANN_BYTES_PER_LEAF_BOX,
+                       "bytes_per_box": ANN_BYTES_PER_BOX}
     log(f"ann 1e9: create {create_s:.2f}s, exact cold {cold['walk_ms']} ms, warm {warm['walk_ms']} ms "
         f"({warm['achieved_gbs']} GB/s)")
     wb = torch.from_numpy(base).cuda()

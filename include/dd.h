@@ -114,6 +114,8 @@ typedef struct dd_project_stats {
   int64_t slow_tiles;       /* 16-bit scans: (32-query group, tile) items recomputed for candidates */
   int64_t boxes;            /* DD_ANN: tree boxes tested */
   int64_t leaves;           /* DD_ANN: leaves (64-point blocks) visited */
+  int64_t leaf_boxes;       /* DD_ANN: of the boxes tested, leaf boxes (read quantised, 24 bytes;
+                               the others are 96-byte FP32 boxes) */
 } dd_project_stats;
 
 typedef struct dd_project_opts {

@@ -40,7 +40,8 @@ class dd_project_stats(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int64), ("overflowed", ctypes.c_int64),
                 ("visited", ctypes.c_int64), ("scan_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("slow_tiles", ctypes.c_int64),
-                ("boxes", ctypes.c_int64), ("leaves", ctypes.c_int64)]
+                ("boxes", ctypes.c_int64), ("leaves", ctypes.c_int64),
+                ("leaf_boxes", ctypes.c_int64)]
 
 
 class dd_project_opts(ctypes.Structure):
@@ -202,7 +203,8 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
         return idx_out, dist_out, {"candidates": st.candidates, "overflowed": st.overflowed,
                                    "visited": st.visited, "scan_ms": st.scan_ms,
                                    "total_ms": st.total_ms, "slow_tiles": st.slow_tiles,
-                                   "boxes": st.boxes, "leaves": st.leaves}
+                                   "boxes": st.boxes, "leaves": st.leaves,
+                                   "leaf_boxes": st.leaf_boxes}
     return idx_out, dist_out
 
 

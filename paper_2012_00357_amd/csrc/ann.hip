@@ -11,11 +11,17 @@
 // pushed farthest-first, so the nearest box is always expanded next; a box is
 // skipped when its lower bound exceeds the current bound U.
 //
-// Certification.  Leaf points are read from the FP32 pack; s~ = sqrt(sum (q_f -
-// x_f)^2) in FP32 differs from the exact whitened distance by at most
-// E = 2^-20 (s~ + |q| + max|x|) (rounding of the stored and query operands,
-// 12 fused multiply-adds and the square root, with a wide margin).  U is the
-// minimum of s~ + E over everything seen (and the exact warm-start distance);
+// Leaves are stored compactly: per leaf its centre c and radius r (FP32), per
+// point the FP16 offset (x - c) / r; a leaf's box is read quantised to 8 bits
+// inside its parent's box, decoded outward.
+//
+// Certification.  s~ = r sqrt(sum (q'' - x'')^2) in FP32 with q'' = (q - c)/r
+// differs from the exact whitened distance by at most
+// E = r (2^-11 + 2^-22) 1.001 + 2^-20 (2 s~ + |q| + 2 r): the FP16 rounding of
+// the offsets (2^-11 relative, 2^-25 absolute below the normal range, times r)
+// plus the FP32 rounding of the query, the centring, 12 fused multiply-adds and
+// the square root, with a wide margin.  U is the minimum of s~ + E over
+// everything seen (and the exact warm-start distance);
 // a point is kept as a candidate while s~ - E <= U.  Every point of a skipped
 // box, and every dropped candidate, is strictly farther than U, which is at
 // least the true minimum, so the kept candidates always contain every exact
@@ -33,15 +39,20 @@ namespace {
 constexpr int kWaves = 4;                          // queries (wavefronts) per block
 constexpr int kStack = kAnnFan * kAnnMaxLevels;    // depth-first stack entries per wave
 constexpr int kCand = 64;                          // candidate list entries per wave
+constexpr int kBatch = 2;                          // leaves whose loads are issued together
+constexpr int kRankSort = 16;                      // children ordered by rank up to this many
 constexpr float kEps20 = 9.5367431640625e-07f;     // 2^-20
 constexpr float kEps22 = 2.384185791015625e-07f;   // 2^-22
 constexpr float kLbShrink = 1.0f - 1.9073486328125e-06f;   // 1 - 2^-19
+constexpr float kLeafRel = (4.8828125e-04f + 2.384185791015625e-07f) * 1.001f;   // (2^-11 + 2^-22)
 
 struct AnnArgs {
   const float* box[kAnnMaxLevels];
   int64_t n[kAnnMaxLevels];
   int levels;
-  const float* w32;
+  const float* meta;       // [n_leaf][16]: c[12], r, 1/r
+  const uint8_t* q0;       // [n_leaf][24] quantised leaf boxes (levels >= 2)
+  const uint16_t* h16;     // [n_leaf*64][12] FP16 scaled offsets
   const double* w64;
   const uint32_t* perm;
   const uint32_t* iperm;
@@ -59,30 +70,107 @@ struct AnnArgs {
   double* dist2;                  // TOP2: distance to the second nearest point (1/2 d^2)
   int* fb_list;
   int* fb_count;
-  unsigned long long* counters;   // [0] points visited, [1] boxes tested, [2] leaves, [3] candidates
+  // kCounterSlots slots of 8: [0] points visited, [1] boxes tested, [2] leaves,
+  // [3] candidates, [4] leaf boxes tested; block b adds into slot b % kCounterSlots
+  // (one cache line each, so the per-wave atomics do not all meet on one line)
+  unsigned long long* counters;
 };
 
+// v from another lane of the same row of 16 (DPP control C); every lane active
+template <int C>
+__device__ inline float dpp_f(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), C, 0xF, 0xF, false));
+}
+
+__device__ inline float lane_f(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Minimum over the wavefront (every lane active): within rows of 16 by DPP
+// (quad xor 1, quad xor 2, half-row mirror, row mirror), then the four rows.
 __device__ inline float wave_min_f(float v) {
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
-  return v;
+  v = fminf(v, dpp_f<0xB1>(v));
+  v = fminf(v, dpp_f<0x4E>(v));
+  v = fminf(v, dpp_f<0x141>(v));
+  v = fminf(v, dpp_f<0x140>(v));
+  return fminf(fminf(lane_f(v, 0), lane_f(v, 16)), fminf(lane_f(v, 32), lane_f(v, 48)));
 }
 
 __device__ inline int lanes_below(uint64_t mask, int lane) {
   return __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
 }
 
-// FP32 distance of the query to stored row pos (direct form, fixed order).
-__device__ inline float leaf_dist(const float* __restrict__ w32, int64_t pos, const float qf[12]) {
-  const float4* r = reinterpret_cast<const float4*>(w32 + 12 * pos);
-  const float4 a = r[0], b = r[1], c = r[2];
-  const float x[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+__device__ inline float half_lo(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu));
+}
+__device__ inline float half_hi(uint32_t w) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+// Centred, scaled query of a leaf: qs = (q - c) / r.
+__device__ inline void leaf_query(const float* __restrict__ meta, int64_t leaf, const float qf[12],
+                                  float qs[12], float& r) {
+  const float4* m = reinterpret_cast<const float4*>(meta + 16 * leaf);
+  const float4 a = m[0], b = m[1], c = m[2], e = m[3];
+  const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  r = e.x;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) qs[k] = (qf[k] - cc[k]) * e.y;
+}
+
+// s~ of stored point pos (FP16 scaled offsets, direct form, fixed order).
+__device__ inline float leaf_point_dist(const uint16_t* __restrict__ h16, int64_t pos,
+                                        const float qs[12], float r) {
+  const uint2* p = reinterpret_cast<const uint2*>(h16 + 12 * pos);
+  const uint2 a = p[0], b = p[1], c = p[2];
+  const float x[12] = {half_lo(a.x), half_hi(a.x), half_lo(a.y), half_hi(a.y),
+                       half_lo(b.x), half_hi(b.x), half_lo(b.y), half_hi(b.y),
+                       half_lo(c.x), half_hi(c.x), half_lo(c.y), half_hi(c.y)};
   float d = 0.0f;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    const float t = qf[k] - x[k];
+    const float t = qs[k] - x[k];
     d = fmaf(t, t, d);
   }
-  return d;
+  return r * __builtin_sqrtf(d);
+}
+
+// s~ from a point's preloaded FP16 scaled offsets.
+__device__ inline float leaf_point_dist_r(const uint2 (&xr)[3], const float qs[12], float r) {
+  const uint2 a = xr[0], b = xr[1], c = xr[2];
+  const float x[12] = {half_lo(a.x), half_hi(a.x), half_lo(a.y), half_hi(a.y),
+                       half_lo(b.x), half_hi(b.x), half_lo(b.y), half_hi(b.y),
+                       half_lo(c.x), half_hi(c.x), half_lo(c.y), half_hi(c.y)};
+  float d = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const float t = qs[k] - x[k];
+    d = fmaf(t, t, d);
+  }
+  return r * __builtin_sqrtf(d);
+}
+
+// Lower bound from a leaf box quantised inside its parent box (plo, step),
+// decoded outward by delta, which exceeds the FP32 rounding of the decoding.
+__device__ inline float qbox_lb(const uint8_t* __restrict__ q, const float plo[12],
+                                const float step[12], float delta, const float yq[12],
+                                float slack) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(q);
+  uint32_t v[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = w[i];
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const float ql = (float)((v[a >> 2] >> (8 * (a & 3))) & 0xFFu);
+    const float qh = (float)((v[3 + (a >> 2)] >> (8 * (a & 3))) & 0xFFu);
+    const float lo = fmaf(ql, step[a], plo[a]) - delta;
+    const float hi = fmaf(qh, step[a], plo[a]) + delta;
+    const float g = fmaxf(fmaxf(lo - yq[a], yq[a] - hi), 0.0f);
+    s = fmaf(g, g, s);
+  }
+  return __builtin_sqrtf(s) * kLbShrink - slack;
 }
 
 // Lower bound of the whitened distance from the query to box b, minus the slack
@@ -124,7 +212,7 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
 // bound is the second smallest of the per-point upper bounds seen (U2), so the
 // candidates hold every point within the second-smallest distance.
 template <bool TOP2>
-__global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
+__global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
   __shared__ float s_lb[kWaves][kStack];
   __shared__ uint32_t s_cpos[kWaves][kCand];
@@ -159,7 +247,7 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     }
   }
   const float qnorm = (float)sqrt(A.qn2[q]);
-  const float ebase = kEps20 * (qnorm + A.xmax);
+  const float ebase = kEps20 * qnorm;
   const float slack = kEps22 * (qnorm + A.xmax) + 1e-30f;
   // U: pruning bound (the smallest upper bound seen; with TOP2 the second
   // smallest over distinct points, U1 tracking the smallest)
@@ -174,8 +262,10 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     const int64_t wi = A.warm[q];
     if (wi >= 0 && wi < A.N) {
       const int64_t pos = A.iperm[wi];
-      const float s = __builtin_sqrtf(leaf_dist(A.w32, pos, qf));
-      const float E = ebase + kEps20 * s;
+      float qs[12], r;
+      leaf_query(A.meta, pos / kAnnLeaf, qf, qs, r);
+      const float s = leaf_point_dist(A.h16, pos, qs, r);
+      const float E = ebase + kEps20 * (2.0f * s + 2.0f * r) + kLeafRel * r;
       U = fminf(U, s + E);
       if (lane == 0) {
         s_cpos[wv][0] = (uint32_t)pos;
@@ -188,11 +278,28 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
   // push the children [c0, c0 + cnt) of level lv that may hold candidates,
   // farthest first (so the nearest is on top of the stack)
   int sp = 0;
-  unsigned long long boxes = 0, leaves = 0, visited = 0;
+  unsigned long long boxes = 0, leaves = 0, visited = 0, leaf_boxes = 0;
   auto expand = [&](int lv, int64_t c0, int cnt) {
     float key = INFINITY;
     uint32_t val = 0;
-    if (lane < cnt) {
+    if (lv == 0 && A.levels >= 2) {
+      // leaf boxes quantised inside their parent (the node being expanded)
+      const float* pb = A.box[1] + 24 * (c0 / kAnnFan);
+      float plo[12], step[12], amax = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        const float lo = pb[a], hi = pb[12 + a];
+        plo[a] = lo;
+        step[a] = (hi - lo) * (1.0f / 255.0f);
+        amax = fmaxf(amax, fabsf(lo) + fabsf(hi));
+      }
+      const float delta = kEps20 * amax + 1e-30f;
+      if (lane < cnt) {
+        const float lb = qbox_lb(A.q0 + 24 * (c0 + lane), plo, step, delta, yq, slack);
+        if (lb <= U) key = fmaxf(lb, 0.0f);
+        val = (uint32_t)(c0 + lane);
+      }
+    } else if (lane < cnt) {
       const float lb = box_lb(A.box[lv] + 24 * (c0 + lane), yq, slack);
       if (lb <= U) key = fmaxf(lb, 0.0f);
       val = (uint32_t)(c0 + lane);
@@ -205,38 +312,42 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
       ovf = true;
       k = 0;
     }
-    wave_sort64(key, val, lane);
-    if (lane < k) {
-      s_code[wv][sp + k - 1 - lane] = ((uint32_t)lv << 28) | val;
-      s_lb[wv][sp + k - 1 - lane] = key;
+    if (k <= kRankSort) {
+      // few survivors: each takes its rank among them (ties by child order)
+      int rank = 0;
+      for (uint64_t m = pass; m != 0; m &= m - 1) {
+        const int j = __builtin_ctzll(m);
+        const float kj = lane_f(key, j);
+        rank += (int)(kj < key) | ((int)(kj == key) & (int)(j < lane));
+      }
+      if (k > 0 && key != INFINITY) {
+        s_code[wv][sp + k - 1 - rank] = ((uint32_t)lv << 28) | val;
+        s_lb[wv][sp + k - 1 - rank] = key;
+      }
+    } else {
+      wave_sort64(key, val, lane);
+      if (lane < k) {
+        s_code[wv][sp + k - 1 - lane] = ((uint32_t)lv << 28) | val;
+        s_lb[wv][sp + k - 1 - lane] = key;
+      }
     }
     __builtin_amdgcn_wave_barrier();
     sp += k;
     boxes += (unsigned long long)cnt;
+    if (lv == 0) leaf_boxes += (unsigned long long)cnt;
   };
 
-  expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
-  while (sp > 0 && !ovf) {
-    --sp;
-    const uint32_t code = s_code[wv][sp];
-    const float lb = s_lb[wv][sp];
-    if (lb > U) continue;
-    const int lv = (int)(code >> 28);
-    const int64_t idx = (int64_t)(code & 0x0FFFFFFFu);
-    if (lv > 0) {
-      const int64_t c0 = idx * kAnnFan;
-      const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
-      expand(lv - 1, c0, cnt);
-      if (ovf) break;
-      continue;
-    }
-    // leaf: 64 consecutive sorted points, one per lane
+  // one leaf: 64 consecutive sorted points, one per lane, data already loaded
+  bool stop = false;
+  auto leaf_step = [&](int64_t idx, const uint2 (&xr)[3]) {
     const int64_t pos = idx * kAnnLeaf + lane;
     const bool v = pos < A.N;
+    float qs[12], r;
+    leaf_query(A.meta, idx, qf, qs, r);
     float s = INFINITY, E = 0.0f;
     if (v) {
-      s = __builtin_sqrtf(leaf_dist(A.w32, pos, qf));
-      E = ebase + kEps20 * s;
+      s = leaf_point_dist_r(xr, qs, r);
+      E = ebase + kEps20 * (2.0f * s + 2.0f * r) + kLeafRel * r;
     }
     if (TOP2) {
       const float h = v ? s + E : INFINITY;
@@ -277,7 +388,8 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
       nc = __popcll(sm);
       if (nc + cnt > kCand) {
         ovf = true;
-        break;
+        stop = true;
+        return;
       }
     }
     if (keep) {
@@ -287,13 +399,67 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     }
     __builtin_amdgcn_wave_barrier();
     nc += cnt;
-    if (A.budget > 0 && leaves >= (unsigned long long)A.budget) break;
+    if (A.budget > 0 && leaves >= (unsigned long long)A.budget) stop = true;
+  };
+
+  expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
+  while (sp > 0 && !ovf && !stop) {
+    // stack entries are the same in every lane: keep them in scalar registers
+    const uint32_t code = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_code[wv][sp - 1]);
+    const float lb = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, s_lb[wv][sp - 1])));
+    if (lb > U) {
+      --sp;
+      continue;
+    }
+    const int lv = (int)(code >> 28);
+    if (lv > 0) {
+      --sp;
+      const int64_t c0 = (int64_t)(code & 0x0FFFFFFFu) * kAnnFan;
+      const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
+      expand(lv - 1, c0, cnt);
+      continue;
+    }
+    // a batch of up to kBatch leaves from the top of the stack (nearest first):
+    // their loads are issued together, then they are evaluated in order, each
+    // against the bound as it stands
+    int64_t bidx[kBatch];
+    float blb[kBatch];
+    int nb = 0;
+    while (nb < kBatch && sp > 0) {
+      const uint32_t c2 = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_code[wv][sp - 1]);
+      if ((c2 >> 28) != 0) break;
+      bidx[nb] = (int64_t)(c2 & 0x0FFFFFFFu);
+      blb[nb] = __builtin_bit_cast(
+          float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, s_lb[wv][sp - 1])));
+      ++nb;
+      --sp;
+    }
+    uint2 xr[kBatch][3];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int64_t pos = bidx[b < nb ? b : 0] * kAnnLeaf + lane;
+      if (b < nb && pos < A.N) {
+        const uint2* p = reinterpret_cast<const uint2*>(A.h16 + 12 * pos);
+        xr[b][0] = p[0];
+        xr[b][1] = p[1];
+        xr[b][2] = p[2];
+      } else {
+        xr[b][0] = xr[b][1] = xr[b][2] = make_uint2(0u, 0u);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (b < nb && !stop && blb[b] <= U) leaf_step(bidx[b], xr[b]);
+    }
   }
 
   if (lane == 0) {
-    atomicAdd(A.counters + 0, visited);
-    atomicAdd(A.counters + 1, boxes);
-    atomicAdd(A.counters + 2, leaves);
+    unsigned long long* c = A.counters + 8 * (blockIdx.x % kCounterSlots);
+    atomicAdd(c + 0, visited);
+    atomicAdd(c + 1, boxes);
+    atomicAdd(c + 2, leaves);
+    atomicAdd(c + 4, leaf_boxes);
   }
   if (ovf) {
     if (lane == 0) {
@@ -318,7 +484,10 @@ __global__ __launch_bounds__(256) void ann_walk_kernel(AnnArgs A) {
     d = acc;
     o = A.perm[j];
   }
-  if (lane == 0) atomicAdd(A.counters + 3, (unsigned long long)__popcll(__ballot(mine)));
+  const uint64_t mine_mask = __ballot(mine);
+  if (lane == 0)
+    atomicAdd(A.counters + 8 * (blockIdx.x % kCounterSlots) + 3,
+              (unsigned long long)__popcll(mine_mask));
   const double dm = d;
   const uint32_t om = o;
   for (int off = 32; off > 0; off >>= 1) {
@@ -356,7 +525,9 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
     A.n[l] = D.ann_n[l];
   }
   A.levels = D.ann_levels;
-  A.w32 = D.w32.as<float>();
+  A.meta = D.ann_meta.as<float>();
+  A.q0 = D.ann_q0.as<uint8_t>();
+  A.h16 = D.ann_h16.as<uint16_t>();
   A.w64 = D.w64.as<double>();
   A.perm = D.perm.as<uint32_t>();
   A.iperm = D.iperm.as<uint32_t>();

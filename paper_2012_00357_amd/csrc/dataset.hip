@@ -307,6 +307,70 @@ __global__ __launch_bounds__(256) void ann_node_box_kernel(const float* __restri
   }
 }
 
+// Compact leaf of the walk (one wavefront per leaf): centre, radius and the
+// scaled FP16 offsets of its points.
+__global__ __launch_bounds__(256) void ann_leaf_pack_kernel(const double* __restrict__ w64,
+                                                            int64_t N, int64_t n_leaf,
+                                                            float* __restrict__ meta,
+                                                            _Float16* __restrict__ h16) {
+  const int lane = threadIdx.x & 63;
+  const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (leaf >= n_leaf) return;
+  const int64_t i = leaf * kAnnLeaf + lane;
+  const bool v = i < N;
+  int cnt = __popcll(__ballot(v));
+  double x[12];
+  for (int k = 0; k < 12; ++k) x[k] = v ? w64[12 * i + k] : 0.0;
+  float c[12];
+  for (int k = 0; k < 12; ++k) {
+    double sum = x[k];
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    sum = __shfl(sum, 0);   // one value for every lane (the butterfly order differs per lane)
+    c[k] = (float)(sum / (double)cnt);
+  }
+  double d2 = 0.0;
+  for (int k = 0; k < 12; ++k) {
+    const double t = x[k] - (double)c[k];
+    d2 = fma(t, t, d2);
+  }
+  double r = v ? sqrt(d2) : 0.0;
+  r = wave_max_d(r);
+  float rf = __double2float_ru(r * (1.0 + 1e-12));
+  rf = fmaxf(rf, 9.5367431640625e-07f);   // 2^-20: bounded scaled offsets for tiny leaves
+  const double inv = 1.0 / (double)rf;
+  for (int k = 0; k < 12; ++k)
+    h16[12 * i + k] = v ? (_Float16)((x[k] - (double)c[k]) * inv) : (_Float16)0.0f;
+  if (lane == 0) {
+    float* m = meta + 16 * leaf;
+    for (int k = 0; k < 12; ++k) m[k] = c[k];
+    m[12] = rf;
+    m[13] = (float)inv;
+    m[14] = 0.0f;
+    m[15] = 0.0f;
+  }
+}
+
+// Leaf boxes quantised inside their level-1 parent box: lo rounded down, hi up.
+__global__ void ann_qbox_kernel(const float* __restrict__ box0, const float* __restrict__ box1,
+                                int64_t n_leaf, uint8_t* __restrict__ q0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_leaf) return;
+  const float* b = box0 + 24 * t;
+  const float* p = box1 + 24 * (t / kAnnFan);
+  for (int a = 0; a < 12; ++a) {
+    const double plo = p[a], ext = (double)p[12 + a] - plo;
+    int ql = 0, qh = 255;
+    if (ext > 0.0) {
+      ql = (int)floor(((double)b[a] - plo) / ext * 255.0);
+      qh = (int)ceil(((double)b[12 + a] - plo) / ext * 255.0);
+      ql = ql < 0 ? 0 : (ql > 255 ? 255 : ql);
+      qh = qh < 0 ? 0 : (qh > 255 ? 255 : qh);
+    }
+    q0[24 * t + a] = (uint8_t)ql;
+    q0[24 * t + 12 + a] = (uint8_t)qh;
+  }
+}
+
 static unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 // Chunked access to the caller's raw (strain, stress) rows.  Creation reads
@@ -365,9 +429,9 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
   if (opts && opts->reserved != 0) return set_error(DD_ERR_ARG, "dd_dataset_opts.reserved must be 0");
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN))
     return set_error(DD_ERR_ARG, "unknown pack bits");
-  // the ANN walk reads the FP32 pack, its boxes and rerank the FP64 pack; the
-  // 16-bit packs are built from the sorted FP64 pack and reranked against it
-  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP32 | DD_PACK_FP64;
+  // the ANN tree and its compact leaves are built from the sorted FP64 pack,
+  // which also serves its rerank; so are the 16-bit packs
+  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP64;
   if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) packs |= DD_PACK_FP64;
   if (!(packs & (DD_PACK_FP64 | DD_PACK_FP32))) packs |= DD_PACK_FP64;
   D.N = N;
@@ -567,6 +631,23 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
       n = m;
     }
     D.ann_levels = l + 1;
+    const int64_t nl = D.ann_n[0];
+    DD_TRY(D.ann_meta.alloc(sizeof(float) * 16 * (size_t)nl));
+    DD_TRY(D.ann_h16.alloc(sizeof(uint16_t) * 12 * (size_t)(nl * kAnnLeaf)));
+    hipLaunchKernelGGL(ann_leaf_pack_kernel, dim3(grid_for(nl, 4)), dim3(256), 0, st,
+                       D.w64.as<double>(), N, nl, D.ann_meta.as<float>(),
+                       D.ann_h16.as<_Float16>());
+    DD_HIP(hipGetLastError());
+    if (D.ann_levels >= 2) {
+      DD_TRY(D.ann_q0.alloc(24 * (size_t)nl));
+      hipLaunchKernelGGL(ann_qbox_kernel, dim3(grid_for(nl)), dim3(256), 0, st,
+                         D.ann_box[0].as<float>(), D.ann_box[1].as<float>(), nl,
+                         D.ann_q0.as<uint8_t>());
+      DD_HIP(hipGetLastError());
+      // the walk reads leaf boxes only in quantised form from here on
+      DD_HIP(hipStreamSynchronize(st));
+      D.ann_box[0].release();
+    }
   }
   DD_HIP(hipStreamSynchronize(st));
   return DD_OK;

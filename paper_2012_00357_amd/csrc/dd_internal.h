@@ -71,6 +71,7 @@ constexpr int kDim = 12;           // phase-space dimension 2M (M = 6 Voigt comp
 constexpr int kKeyAxes = 6;        // principal axes used for the spatial order
 constexpr int kAnnLeaf = 64;       // points per ANN leaf (one wavefront)
 constexpr int kAnnFan = 64;        // children per ANN tree node (one wavefront)
+constexpr int kCounterSlots = 8;   // ANN walk statistics: slots of 8 u64, one per cache line
 constexpr int kAnnMaxLevels = 6;   // 64^6 leaves exceed any N <= 2^31 - 1
 
 // K^-1 of one mesh and Dirichlet pattern (P_C by a dense product), padded to
@@ -124,6 +125,13 @@ struct Dataset {
   DevBuf ann_box[kAnnMaxLevels];
   int64_t ann_n[kAnnMaxLevels] = {0};
   int ann_levels = 0;
+  // compact leaves read by the walk: per leaf the FP32 centre c (mean of its
+  // points), radius r (max |x - c|, rounded up, at least 2^-20) and its box
+  // quantised to 8 bits inside its parent's box (rounded outward); per point the
+  // FP16 scaled offset (x - c) / r (round to nearest)
+  DevBuf ann_meta;   // float [n_leaf][16]: c[12], r, 1/r, 0, 0
+  DevBuf ann_q0;     // uint8 [n_leaf][24]: lo[12], hi[12] in 1/255 of the parent box
+  DevBuf ann_h16;    // uint16 [n_leaf*64][12]
 
   // inverses of K for dd_solve, most recently used first (see DenseInverse)
   mutable std::mutex cache_mu;

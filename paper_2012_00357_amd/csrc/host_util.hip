@@ -123,6 +123,7 @@ int64_t Dataset::device_bytes() const {
   int64_t b = (int64_t)(perm.bytes + iperm.bytes + w64.bytes + n64.bytes + w32.bytes + n32.bytes +
                         centre.bytes + radius.bytes + wbf16.bytes + wfp16.bytes);
   for (int l = 0; l < kAnnMaxLevels; ++l) b += (int64_t)ann_box[l].bytes;
+  b += (int64_t)(ann_meta.bytes + ann_q0.bytes + ann_h16.bytes);
   return b;
 }
 
