@@ -84,7 +84,15 @@ typedef enum dd_mode {
   /* Plain FP64 direct-form scan (VALU), the simplest exact kernel. */
   DD_DIRECT_FP64 = 4,
   /* As DD_MIXED_BF16 with IEEE half precision instead of bfloat16. */
-  DD_MIXED_FP16 = 5
+  DD_MIXED_FP16 = 5,
+  /* Warm-started walk over the k-means tree of Section 4 (recursive 4-means,
+   * pack DD_PACK_KMEANS): every stored node holds up to 64 children (three
+   * 4-means levels), each with the ball (centroid, radius) of its points; a
+   * child is pruned when |q - c| - f_d r exceeds the best certified distance
+   * so far.  Same certified FP32 arithmetic, FP64 rerank, budget and
+   * warm-start rules as DD_ANN; exact with ann_budget = 0 and f_d = 1
+   * (dd_project_opts.ann_fd = 0 or 1), approximate otherwise. */
+  DD_KMEANS = 6
 } dd_mode;
 
 /* Packs a dataset can hold (dd_dataset_opts.packs bit mask). */
@@ -92,7 +100,8 @@ typedef enum dd_mode {
 #define DD_PACK_FP32 0x2u   /* whitened FP32 [N][12] + norms: DD_MIXED_FP32 */
 #define DD_PACK_BF16 0x4u   /* tile-centred BF16 [N][16] + tile centres/radii: DD_MIXED_BF16 */
 #define DD_PACK_FP16 0x8u   /* tile-centred FP16 [N][16]: DD_MIXED_FP16 */
-#define DD_PACK_ANN 0x10u   /* box tree over the sorted FP32 pack (implies FP32 and FP64): DD_ANN */
+#define DD_PACK_ANN 0x10u   /* box tree over the sorted order, compact leaves (implies FP64): DD_ANN */
+#define DD_PACK_KMEANS 0x20u /* k-means tree, compact leaves (implies FP64): DD_KMEANS */
 #define DD_PACK_DEFAULT (DD_PACK_FP64 | DD_PACK_BF16)
 
 typedef struct dd_dataset dd_dataset;
@@ -107,25 +116,28 @@ typedef struct dd_dataset_opts {
 typedef struct dd_project_stats {
   int64_t candidates;       /* candidates reranked in FP64 (mixed modes) */
   int64_t overflowed;       /* queries rescanned by the FP64 fallback */
-  int64_t visited;          /* data points visited (DD_ANN) */
+  int64_t visited;          /* data points visited (DD_ANN, DD_KMEANS) */
   double scan_ms;           /* device time of the main scan kernel, the one pass over every
                                (query, data point) pair (HIP events on the call's stream) */
   double total_ms;          /* device time from the first to the last kernel of the call */
   int64_t slow_tiles;       /* 16-bit scans: (32-query group, tile) items recomputed for candidates */
-  int64_t boxes;            /* DD_ANN: tree boxes tested */
-  int64_t leaves;           /* DD_ANN: leaves (64-point blocks) visited */
+  int64_t boxes;            /* DD_ANN: tree boxes tested; DD_KMEANS: child balls tested */
+  int64_t leaves;           /* DD_ANN, DD_KMEANS: leaves (blocks of up to 64 points) visited */
   int64_t leaf_boxes;       /* DD_ANN: of the boxes tested, leaf boxes (read quantised, 24 bytes;
-                               the others are 96-byte FP32 boxes) */
+                               the others are 96-byte FP32 boxes); DD_KMEANS: of the balls
+                               tested, leaf balls */
 } dd_project_stats;
 
 typedef struct dd_project_opts {
   int32_t mode;             /* dd_mode; default DD_EXACT_FP64 */
   int32_t splits;           /* data splits per query block; 0 = automatic */
-  int32_t ann_budget;       /* DD_ANN: max leaves (64-point blocks) visited per query;
+  int32_t ann_budget;       /* DD_ANN, DD_KMEANS: max leaves visited per query;
                                0 = unlimited (exact) */
   int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
                                every 16th tile first; 0 = automatic (2 without a warm start) */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
+  double ann_fd;            /* DD_KMEANS: radius factor f_d in (0, 1] of the ball test;
+                               0 = 1 (exact) */
 } dd_project_opts;
 
 /*
@@ -173,6 +185,17 @@ dd_status dd_dataset_destroy(dd_dataset* ds);
 
 /* Number of points, and bytes of device memory the dataset holds. */
 dd_status dd_dataset_info(const dd_dataset* ds, int64_t* n_points, int64_t* device_bytes);
+
+/* Shape of a dataset's search trees (zeros for a tree it does not hold). */
+typedef struct dd_index_info {
+  int32_t ann_levels;       /* box tree levels (level 0: leaves of 64 consecutive points) */
+  int32_t kmeans_levels;    /* 4-means levels of the k-means tree (depth of its deepest leaf) */
+  int64_t ann_leaves;       /* box tree leaves */
+  int64_t kmeans_nodes;     /* stored k-means tree nodes (every third 4-means level) */
+  int64_t kmeans_leaves;    /* k-means tree leaves (at most 64 points each) */
+  int64_t kmeans_records;   /* child records (balls) of the stored nodes */
+} dd_index_info;
+dd_status dd_dataset_index_info(const dd_dataset* ds, dd_index_info* info);
 
 /*
  * P_D (Section 2): for each of m states find the data point nearest under the
@@ -225,8 +248,8 @@ typedef struct dd_solve_opts {
   int32_t cg_max_iter;   /* 0 = 20000 */
   int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
-  int32_t ann_budget;    /* DD_ANN: leaves per projection (0 = exact walk) */
-  int32_t ann_ramp;      /* DD_ANN with a budget: > 0 = accuracy schedule, iteration i <= ann_ramp
+  int32_t ann_budget;    /* DD_ANN, DD_KMEANS: leaves per projection (0 = exact walk) */
+  int32_t ann_ramp;      /* DD_ANN, DD_KMEANS with a budget: > 0 = accuracy schedule, iteration i <= ann_ramp
                             uses ann_budget * i leaves, later iterations walk exactly (the paper's
                             search accuracy growing over the iterations, Section 4.5) */
   const double* dirichlet_values;  /* host [ndof] or NULL: prescribed displacements at the
@@ -240,7 +263,7 @@ typedef struct dd_solve_opts {
  * of inverses per dataset, least recently used dropped first) and applies it
  * as one product per P_C. */
 #define DD_SOLVE_CG 0x2
-/* Exact DD_ANN solves: skip the projection of material points whose state
+/* Exact DD_ANN and DD_KMEANS solves: skip the projection of material points whose state
  * moved less than half the certified gap between their nearest and second
  * nearest data points since that gap was measured (the association cannot
  * change, by the triangle inequality: the paper's criterion for unmoved
@@ -266,7 +289,7 @@ typedef struct dd_solve_result {
   int64_t cg_iterations;    /* out: total CG iterations (both systems) */
   double cg_max_residual;   /* out: largest final relative CG residual */
   double elapsed_ms;        /* out: host wall time of the loop */
-  int64_t skipped;          /* out: projections skipped as unmoved (exact DD_ANN) */
+  int64_t skipped;          /* out: projections skipped as unmoved (exact DD_ANN, DD_KMEANS) */
 } dd_solve_result;
 
 /*
@@ -275,7 +298,7 @@ typedef struct dd_solve_result {
  * K = A_e{w B^T C B} assembled once, E = A_e{w B^T C eps*},
  * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
  * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
- * exact projections).  With an approximate projection (DD_ANN with a budget,
+ * exact projections).  With an approximate projection (a walk with a budget,
  * no ramp) the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer
  * decreases, since the alternating-minimisation descent no longer holds
  * (Section 4.1); with an accuracy schedule (ann_ramp) the stopping rules apply
@@ -311,7 +334,7 @@ typedef struct dd_server_opts {
   int32_t max_active;    /* solves admitted at once; 0 = 64 */
   int32_t max_batch;     /* queries per projection batch; 0 = 65536 */
   int32_t max_queue;     /* submitted, not yet admitted solves; 0 = 4096 */
-  int32_t ann_budget;    /* DD_ANN budget (0 = exact walk) */
+  int32_t ann_budget;    /* DD_ANN, DD_KMEANS budget (0 = exact walk) */
   int32_t reserved;      /* must be 0 */
 } dd_server_opts;
 

@@ -19,11 +19,13 @@ STATUS = {0: "DD_OK", 1: "DD_ERR_ARG", 2: "DD_ERR_NOT_SPD", 3: "DD_ERR_OOM", 4: 
           5: "DD_ERR_NOT_CONVERGED", 6: "DD_ERR_TOO_LARGE", 7: "DD_ERR_CANCELLED",
           8: "DD_ERR_UNSUPPORTED", 9: "DD_ERR_TIMEOUT"}
 
-DD_EXACT_FP64, DD_MIXED_FP32, DD_MIXED_BF16, DD_ANN, DD_DIRECT_FP64, DD_MIXED_FP16 = range(6)
+(DD_EXACT_FP64, DD_MIXED_FP32, DD_MIXED_BF16, DD_ANN, DD_DIRECT_FP64, DD_MIXED_FP16,
+ DD_KMEANS) = range(7)
 MODES = {"fp64": DD_EXACT_FP64, "fp32": DD_MIXED_FP32, "bf16": DD_MIXED_BF16, "ann": DD_ANN,
-         "direct": DD_DIRECT_FP64, "fp16": DD_MIXED_FP16}
+         "direct": DD_DIRECT_FP64, "fp16": DD_MIXED_FP16, "kmeans": DD_KMEANS}
 
-DD_PACK_FP64, DD_PACK_FP32, DD_PACK_BF16, DD_PACK_FP16, DD_PACK_ANN = 0x1, 0x2, 0x4, 0x8, 0x10
+DD_PACK_FP64, DD_PACK_FP32, DD_PACK_BF16, DD_PACK_FP16, DD_PACK_ANN, DD_PACK_KMEANS = (
+    0x1, 0x2, 0x4, 0x8, 0x10, 0x20)
 
 
 class DDError(RuntimeError):
@@ -44,9 +46,16 @@ class dd_project_stats(ctypes.Structure):
                 ("leaf_boxes", ctypes.c_int64)]
 
 
+class dd_index_info(ctypes.Structure):
+    _fields_ = [("ann_levels", ctypes.c_int32), ("kmeans_levels", ctypes.c_int32),
+                ("ann_leaves", ctypes.c_int64), ("kmeans_nodes", ctypes.c_int64),
+                ("kmeans_leaves", ctypes.c_int64), ("kmeans_records", ctypes.c_int64)]
+
+
 class dd_project_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("splits", ctypes.c_int32), ("ann_budget", ctypes.c_int32),
-                ("passes", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats))]
+                ("passes", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats)),
+                ("ann_fd", ctypes.c_double)]
 
 
 def _load():
@@ -66,11 +75,13 @@ def _load():
                                                vp, ctypes.POINTER(vp)]
     lib.dd_dataset_destroy.argtypes = [vp]
     lib.dd_dataset_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.dd_dataset_index_info.argtypes = [vp, ctypes.POINTER(dd_index_info)]
     lib.dd_project.argtypes = [vp, vp, i64, vp, ctypes.POINTER(dd_project_opts), vp, vp, vp]
     lib.dd_selftest_mfma.argtypes = [i32, vp, vp, vp]
     lib.dd_metric_pca.argtypes = [vp, vp, i64, vp, vp]
     for f in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
-              "dd_dataset_info", "dd_project", "dd_selftest_mfma", "dd_metric_pca"):
+              "dd_dataset_info", "dd_dataset_index_info", "dd_project", "dd_selftest_mfma",
+              "dd_metric_pca"):
         getattr(lib, f).restype = ctypes.c_int
     lib.dd_last_error.restype = ctypes.c_char_p
     lib.dd_version.restype = ctypes.c_char_p
@@ -180,7 +191,7 @@ def dd_dataset_destroy(ds: Dataset):
 
 def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: int = 0,
                ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False,
-               passes: int = 0):
+               passes: int = 0, ann_fd: float = 0.0):
     """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats])."""
     import torch
     m = int(states.shape[0])
@@ -196,7 +207,7 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
         pw = _dev_ptr(warm_start_idx, torch.int64, None, "warm_start_idx")
     st = dd_project_stats()
     opts = dd_project_opts(MODES[mode] if isinstance(mode, str) else int(mode), splits, ann_budget,
-                           passes, ctypes.pointer(st) if stats else None)
+                           passes, ctypes.pointer(st) if stats else None, float(ann_fd))
     _check(_lib.dd_project(ds.handle, ps, m, pw, ctypes.byref(opts), pi, pd, _stream(stream)),
            "dd_project")
     if stats:
@@ -232,6 +243,13 @@ def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
 def dd_dataset_info(ds: Dataset):
     """dd_dataset_info: (number of points, device bytes held)."""
     return ds.info()
+
+
+def dd_dataset_index_info(ds: Dataset) -> dict:
+    """dd_dataset_index_info: shape of the dataset's search trees."""
+    info = dd_index_info()
+    _check(_lib.dd_dataset_index_info(ds.handle, ctypes.byref(info)), "dd_dataset_index_info")
+    return {k: getattr(info, k) for k, _ in info._fields_}
 
 
 class dd_mesh(ctypes.Structure):

@@ -67,6 +67,12 @@ struct AnnArgs {
   const int* invalid;
   const int64_t* warm;
   Outputs out;
+  // k-means tree (KMT): nodes, child records, slot <-> sorted position, f_d
+  const int2* kmt_node;
+  const float* kmt_child;
+  const uint32_t* slot_pos;
+  const uint32_t* pos_slot;
+  float fd;
   double* dist2;                  // TOP2: distance to the second nearest point (1/2 d^2)
   int* fb_list;
   int* fb_count;
@@ -110,11 +116,12 @@ __device__ inline float half_hi(uint32_t w) {
 
 // Centred, scaled query of a leaf: qs = (q - c) / r.
 __device__ inline void leaf_query(const float* __restrict__ meta, int64_t leaf, const float qf[12],
-                                  float qs[12], float& r) {
+                                  float qs[12], float& r, uint32_t& count) {
   const float4* m = reinterpret_cast<const float4*>(meta + 16 * leaf);
   const float4 a = m[0], b = m[1], c = m[2], e = m[3];
   const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
   r = e.x;
+  count = __builtin_bit_cast(uint32_t, e.z);
 #pragma unroll
   for (int k = 0; k < 12; ++k) qs[k] = (qf[k] - cc[k]) * e.y;
 }
@@ -189,6 +196,25 @@ __device__ inline float box_lb(const float* __restrict__ b, const float yq[12], 
   return __builtin_sqrtf(s) * kLbShrink - slack;
 }
 
+// Lower bound of the whitened distance from the query to the points of a ball
+// (centre c, radius r >= max |x - c|): |q - c| - f_d r, with |q - c| shrunk by
+// the slack that covers the rounding of the query and of this sum.  Exact
+// bound for f_d = 1; f_d < 1 is the approximate test of Section 4.
+__device__ inline float ball_lb(const float* __restrict__ rec, const float qf[12], float slack,
+                                float fd, uint32_t& code) {
+  const float4* m = reinterpret_cast<const float4*>(rec);
+  const float4 a = m[0], b = m[1], c = m[2], e = m[3];
+  const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const float t = qf[k] - cc[k];
+    s = fmaf(t, t, s);
+  }
+  code = __builtin_bit_cast(uint32_t, e.y);
+  return __builtin_sqrtf(s) * kLbShrink - slack - fd * e.x;
+}
+
 // Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront.
 __device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
 #pragma unroll
@@ -211,7 +237,10 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
 // TOP2: certify the two nearest points instead of the nearest: the pruning
 // bound is the second smallest of the per-point upper bounds seen (U2), so the
 // candidates hold every point within the second-smallest distance.
-template <bool TOP2>
+//
+// KMT: walk the k-means tree instead of the box tree (ball bounds, padded
+// leaf blocks addressed by slot).
+template <bool TOP2, bool KMT>
 __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
   __shared__ float s_lb[kWaves][kStack];
@@ -241,8 +270,10 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
       double y = 0.0;
+      if (!KMT) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
+        for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
+      }
       yq[a] = (float)y;
     }
   }
@@ -261,9 +292,10 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   if (A.warm && !TOP2) {
     const int64_t wi = A.warm[q];
     if (wi >= 0 && wi < A.N) {
-      const int64_t pos = A.iperm[wi];
+      const int64_t pos = KMT ? (int64_t)A.pos_slot[A.iperm[wi]] : (int64_t)A.iperm[wi];
       float qs[12], r;
-      leaf_query(A.meta, pos / kAnnLeaf, qf, qs, r);
+      uint32_t count;
+      leaf_query(A.meta, pos / kAnnLeaf, qf, qs, r, count);
       const float s = leaf_point_dist(A.h16, pos, qs, r);
       const float E = ebase + kEps20 * (2.0f * s + 2.0f * r) + kLeafRel * r;
       U = fminf(U, s + E);
@@ -282,7 +314,14 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   auto expand = [&](int lv, int64_t c0, int cnt) {
     float key = INFINITY;
     uint32_t val = 0;
-    if (lv == 0 && A.levels >= 2) {
+    if (KMT) {
+      // child records [c0, c0 + cnt) of a k-means tree node; val is the code
+      if (lane < cnt) {
+        const float lb = ball_lb(A.kmt_child + 16 * (c0 + lane), qf, slack, A.fd, val);
+        if (lb <= U) key = fmaxf(lb, 0.0f);
+      }
+      leaf_boxes += (unsigned long long)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
+    } else if (lv == 0 && A.levels >= 2) {
       // leaf boxes quantised inside their parent (the node being expanded)
       const float* pb = A.box[1] + 24 * (c0 / kAnnFan);
       float plo[12], step[12], amax = 0.0f;
@@ -297,12 +336,12 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       if (lane < cnt) {
         const float lb = qbox_lb(A.q0 + 24 * (c0 + lane), plo, step, delta, yq, slack);
         if (lb <= U) key = fmaxf(lb, 0.0f);
-        val = (uint32_t)(c0 + lane);
+        val = ((uint32_t)lv << 28) | (uint32_t)(c0 + lane);
       }
     } else if (lane < cnt) {
       const float lb = box_lb(A.box[lv] + 24 * (c0 + lane), yq, slack);
       if (lb <= U) key = fmaxf(lb, 0.0f);
-      val = (uint32_t)(c0 + lane);
+      val = ((uint32_t)lv << 28) | (uint32_t)(c0 + lane);
     }
     const uint64_t pass = __ballot(key != INFINITY);
     int k = __popcll(pass);
@@ -321,29 +360,30 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
         rank += (int)(kj < key) | ((int)(kj == key) & (int)(j < lane));
       }
       if (k > 0 && key != INFINITY) {
-        s_code[wv][sp + k - 1 - rank] = ((uint32_t)lv << 28) | val;
+        s_code[wv][sp + k - 1 - rank] = val;
         s_lb[wv][sp + k - 1 - rank] = key;
       }
     } else {
       wave_sort64(key, val, lane);
       if (lane < k) {
-        s_code[wv][sp + k - 1 - lane] = ((uint32_t)lv << 28) | val;
+        s_code[wv][sp + k - 1 - lane] = val;
         s_lb[wv][sp + k - 1 - lane] = key;
       }
     }
     __builtin_amdgcn_wave_barrier();
     sp += k;
     boxes += (unsigned long long)cnt;
-    if (lv == 0) leaf_boxes += (unsigned long long)cnt;
+    if (!KMT && lv == 0) leaf_boxes += (unsigned long long)cnt;
   };
 
   // one leaf: 64 consecutive sorted points, one per lane, data already loaded
   bool stop = false;
   auto leaf_step = [&](int64_t idx, const uint2 (&xr)[3]) {
     const int64_t pos = idx * kAnnLeaf + lane;
-    const bool v = pos < A.N;
     float qs[12], r;
-    leaf_query(A.meta, idx, qf, qs, r);
+    uint32_t count;
+    leaf_query(A.meta, idx, qf, qs, r, count);
+    const bool v = KMT ? lane < (int)count : pos < A.N;
     float s = INFINITY, E = 0.0f;
     if (v) {
       s = leaf_point_dist_r(xr, qs, r);
@@ -402,7 +442,12 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     if (A.budget > 0 && leaves >= (unsigned long long)A.budget) stop = true;
   };
 
-  expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
+  auto expand_node = [&](uint32_t node) {
+    const int2 r = A.kmt_node[node];
+    expand(1, r.x, r.y - r.x);
+  };
+  if (KMT) expand_node(0);
+  else expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
   while (sp > 0 && !ovf && !stop) {
     // stack entries are the same in every lane: keep them in scalar registers
     const uint32_t code = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_code[wv][sp - 1]);
@@ -415,9 +460,13 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     const int lv = (int)(code >> 28);
     if (lv > 0) {
       --sp;
-      const int64_t c0 = (int64_t)(code & 0x0FFFFFFFu) * kAnnFan;
-      const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
-      expand(lv - 1, c0, cnt);
+      if (KMT) {
+        expand_node(code & 0x0FFFFFFFu);
+      } else {
+        const int64_t c0 = (int64_t)(code & 0x0FFFFFFFu) * kAnnFan;
+        const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
+        expand(lv - 1, c0, cnt);
+      }
       continue;
     }
     // a batch of up to kBatch leaves from the top of the stack (nearest first):
@@ -439,7 +488,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
       const int64_t pos = bidx[b < nb ? b : 0] * kAnnLeaf + lane;
-      if (b < nb && pos < A.N) {
+      if (b < nb && (KMT || pos < A.N)) {
         const uint2* p = reinterpret_cast<const uint2*>(A.h16 + 12 * pos);
         xr[b][0] = p[0];
         xr[b][1] = p[1];
@@ -474,7 +523,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   uint32_t o = 0xFFFFFFFFu;
   const bool mine = lane < nc && s_clb[wv][lane] <= U;
   if (mine) {
-    const int64_t j = s_cpos[wv][lane];
+    const int64_t j = KMT ? (int64_t)A.slot_pos[s_cpos[wv][lane]] : (int64_t)s_cpos[wv][lane];
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -514,20 +563,34 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
 
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
                           const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
-                          unsigned long long* counters, double* dist2, hipStream_t st) {
-  if (dist2 && budget != 0) return set_error(DD_ERR_ARG, "second distances need the exact walk");
+                          unsigned long long* counters, double* dist2, hipStream_t st, bool kmt,
+                          double fd) {
+  if (dist2 && (budget != 0 || (kmt && fd != 1.0)))
+    return set_error(DD_ERR_ARG, "second distances need the exact walk");
+  if (!(fd > 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "ann_fd must be in (0, 1]");
   if (len_max <= 0) return DD_OK;
-  if (D.ann_levels < 1 || D.ann_levels > kAnnMaxLevels || D.ann_n[D.ann_levels - 1] > kAnnFan)
-    return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
   AnnArgs A{};
-  for (int l = 0; l < D.ann_levels; ++l) {
-    A.box[l] = D.ann_box[l].as<float>();
-    A.n[l] = D.ann_n[l];
+  if (kmt) {
+    if (D.kmt_nodes < 1) return set_error(DD_ERR_UNSUPPORTED, "dataset has no k-means tree");
+    A.meta = D.kmt_meta.as<float>();
+    A.h16 = D.kmt_h16.as<uint16_t>();
+    A.kmt_node = D.kmt_node.as<int2>();
+    A.kmt_child = D.kmt_child.as<float>();
+    A.slot_pos = D.kmt_pos.as<uint32_t>();
+    A.pos_slot = D.kmt_slot.as<uint32_t>();
+    A.fd = (float)fd;
+  } else {
+    if (D.ann_levels < 1 || D.ann_levels > kAnnMaxLevels || D.ann_n[D.ann_levels - 1] > kAnnFan)
+      return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
+    for (int l = 0; l < D.ann_levels; ++l) {
+      A.box[l] = D.ann_box[l].as<float>();
+      A.n[l] = D.ann_n[l];
+    }
+    A.levels = D.ann_levels;
+    A.meta = D.ann_meta.as<float>();
+    A.q0 = D.ann_q0.as<uint8_t>();
+    A.h16 = D.ann_h16.as<uint16_t>();
   }
-  A.levels = D.ann_levels;
-  A.meta = D.ann_meta.as<float>();
-  A.q0 = D.ann_q0.as<uint8_t>();
-  A.h16 = D.ann_h16.as<uint16_t>();
   A.w64 = D.w64.as<double>();
   A.perm = D.perm.as<uint32_t>();
   A.iperm = D.iperm.as<uint32_t>();
@@ -547,10 +610,18 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
   A.counters = counters;
   const unsigned blocks = (unsigned)((len_max + kWaves - 1) / kWaves);
   A.dist2 = dist2;
-  if (dist2)
-    hipLaunchKernelGGL(ann_walk_kernel<true>, dim3(blocks), dim3(kWaves * 64), 0, st, A);
-  else
-    hipLaunchKernelGGL(ann_walk_kernel<false>, dim3(blocks), dim3(kWaves * 64), 0, st, A);
+  if (kmt) {
+    if (dist2)
+      hipLaunchKernelGGL((ann_walk_kernel<true, true>), dim3(blocks), dim3(kWaves * 64), 0, st, A);
+    else
+      hipLaunchKernelGGL((ann_walk_kernel<false, true>), dim3(blocks), dim3(kWaves * 64), 0, st, A);
+  } else {
+    if (dist2)
+      hipLaunchKernelGGL((ann_walk_kernel<true, false>), dim3(blocks), dim3(kWaves * 64), 0, st, A);
+    else
+      hipLaunchKernelGGL((ann_walk_kernel<false, false>), dim3(blocks), dim3(kWaves * 64), 0, st,
+                         A);
+  }
   DD_HIP(hipGetLastError());
   return DD_OK;
 }

@@ -427,11 +427,12 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
   if (tile != 128 && tile != 256 && tile != 512 && tile != 1024)
     return set_error(DD_ERR_ARG, "tile must be 128, 256, 512 or 1024");
   if (opts && opts->reserved != 0) return set_error(DD_ERR_ARG, "dd_dataset_opts.reserved must be 0");
-  if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN))
+  if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN |
+                DD_PACK_KMEANS))
     return set_error(DD_ERR_ARG, "unknown pack bits");
   // the ANN tree and its compact leaves are built from the sorted FP64 pack,
   // which also serves its rerank; so are the 16-bit packs
-  if (packs & DD_PACK_ANN) packs |= DD_PACK_FP64;
+  if (packs & (DD_PACK_ANN | DD_PACK_KMEANS)) packs |= DD_PACK_FP64;
   if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) packs |= DD_PACK_FP64;
   if (!(packs & (DD_PACK_FP64 | DD_PACK_FP32))) packs |= DD_PACK_FP64;
   D.N = N;
@@ -649,6 +650,9 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
       D.ann_box[0].release();
     }
   }
+
+  // 7. k-means tree over the sorted order
+  if (packs & DD_PACK_KMEANS) DD_TRY(build_kmeans_tree(D, st));
   DD_HIP(hipStreamSynchronize(st));
   return DD_OK;
 }
@@ -701,5 +705,17 @@ extern "C" dd_status dd_dataset_info(const dd_dataset* ds, int64_t* n_points, in
   if (!ds) return dd::set_error(DD_ERR_ARG, "dataset is NULL");
   if (n_points) *n_points = ds->d.N;
   if (device_bytes) *device_bytes = ds->d.device_bytes();
+  return DD_OK;
+}
+
+extern "C" dd_status dd_dataset_index_info(const dd_dataset* ds, dd_index_info* info) {
+  if (!ds || !info) return dd::set_error(DD_ERR_ARG, "dataset or info is NULL");
+  const dd::Dataset& D = ds->d;
+  info->ann_levels = D.ann_levels;
+  info->kmeans_levels = D.kmt_rounds;
+  info->ann_leaves = D.ann_levels > 0 ? D.ann_n[0] : 0;
+  info->kmeans_nodes = D.kmt_nodes;
+  info->kmeans_leaves = D.kmt_leaves;
+  info->kmeans_records = D.kmt_records;
   return DD_OK;
 }

@@ -128,6 +128,8 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
   const int budget = opts ? opts->ann_budget : 0;
   if (budget < 0) return set_error(DD_ERR_ARG, "ann_budget must be >= 0");
+  const double fd = (opts && opts->ann_fd != 0.0) ? opts->ann_fd : 1.0;
+  if (!(fd > 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "ann_fd must be in (0, 1]");
   switch (mode) {
     case DD_EXACT_FP64:
     case DD_DIRECT_FP64:
@@ -143,6 +145,10 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
       break;
     case DD_ANN:
       if (!(D.packs & DD_PACK_ANN)) return set_error(DD_ERR_UNSUPPORTED, "dataset has no ANN tree");
+      break;
+    case DD_KMEANS:
+      if (!(D.packs & DD_PACK_KMEANS))
+        return set_error(DD_ERR_UNSUPPORTED, "dataset has no k-means tree");
       break;
     default:
       return set_error(DD_ERR_UNSUPPORTED, "projection mode not available");
@@ -179,7 +185,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(timing.mark(2, st));
   } else if (mode == DD_EXACT_FP64) {
     DD_TRY(exact64(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));
-  } else if (mode == DD_ANN) {
+  } else if (walk_mode(mode)) {
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
     ann = reinterpret_cast<unsigned long long*>(counters + 16);
@@ -187,7 +193,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     if (dist2_out_dev && budget != 0)
       return set_error(DD_ERR_ARG, "second distances need the exact walk");
     DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann,
-                           dist2_out_dev, st));
+                           dist2_out_dev, st, mode == DD_KMEANS, fd));
     DD_TRY(timing.mark(2, st));
     int h = 0;
     DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -82,15 +82,18 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
 
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
 
-// DD_ANN walk over the dataset's box tree for the queries of L (one wavefront
+// DD_ANN walk over the dataset's box tree (kmt: DD_KMEANS walk over its
+// k-means tree with radius factor fd) for the queries of L (one wavefront
 // each): writes outputs, appends overflowed queries to fb_list / fb_count, adds
-// (points visited, boxes tested, leaves visited, candidates reranked) to
-// counters[0..3].  budget = max leaves per query, 0 = exact.
+// (points visited, boxes tested, leaves visited, candidates reranked, leaf
+// boxes tested) to slot blockIdx % kCounterSlots of counters (8 u64 per slot).
+// budget = max leaves per query, 0 = exact.
 // With dist2 (exact walk only) the walk certifies the two nearest points and
 // writes the second distance (1/2 d^2; -1 when the query went to the fallback).
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
                           const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
-                          unsigned long long* counters, double* dist2, hipStream_t st);
+                          unsigned long long* counters, double* dist2, hipStream_t st,
+                          bool kmt = false, double fd = 1.0);
 
 // u32[q] = min(u32[q], min over the S split bounds U[p][S]).
 dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U, int S, float* u32,

@@ -236,7 +236,7 @@ bool Server::step(Job* j) {
       j->d_half.push_back(sc[0]);
       j->d_full.push_back(sc[1]);
       j->changed.push_back((int64_t)sc[2]);
-      const bool approximate = (mode == DD_ANN && ann_budget > 0);
+      const bool approximate = (walk_mode(mode) && ann_budget > 0);
       if (sc[2] == 0.0) {
         j->stop_reason = 1;
       } else if (approximate && j->it > 1 && !(sc[1] < j->prev_full)) {
@@ -539,7 +539,8 @@ extern "C" dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_by
                   (mode == DD_DIRECT_FP64 && (D.packs & DD_PACK_FP64)) ||
                   (mode == DD_MIXED_BF16 && (D.packs & DD_PACK_BF16)) ||
                   (mode == DD_MIXED_FP16 && (D.packs & DD_PACK_FP16)) ||
-                  (mode == DD_ANN && (D.packs & DD_PACK_ANN));
+                  (mode == DD_ANN && (D.packs & DD_PACK_ANN)) ||
+                  (mode == DD_KMEANS && (D.packs & DD_PACK_KMEANS));
   if (!ok) return set_error(DD_ERR_UNSUPPORTED, "dataset lacks the pack of the server's mode");
   std::unique_ptr<dd_server> h(new (std::nothrow) dd_server());
   if (!h) return set_error(DD_ERR_OOM, "host allocation failed");

@@ -18,7 +18,7 @@ struct FEMesh {
 };
 
 // P_D of whitened states (already in the dataset's coordinates).
-// dist2_out (exact DD_ANN only): distance to the second nearest point, -1
+// dist2_out (exact walks only): distance to the second nearest point, -1
 // where not certified.
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
@@ -75,7 +75,7 @@ class DDSolver {
   int ann_ramp = 0;
   // leaves per projection at DD iteration it (1-based); 0 = exact
   int budget_at(int it) const {
-    if (mode != DD_ANN || ann_budget <= 0) return 0;
+    if (!walk_mode(mode) || ann_budget <= 0) return 0;
     if (ann_ramp <= 0) return ann_budget;
     return it <= ann_ramp ? ann_budget * it : 0;
   }
@@ -88,7 +88,7 @@ class DDSolver {
   DevBuf d_part, d_cgstate;
   DevBuf d_uD, d_lift;   // prescribed displacements and K_fd u_D (empty: homogeneous)
   DevBuf arena;   // one allocation holding every buffer above
-  // skipping of unmoved material points (exact DD_ANN): reference state, half
+  // skipping of unmoved material points (exact walks): reference state, half
   // gap, compacted list and its projection buffers
   bool skip_on = false;
   DevBuf d_qref, d_gap, d_list, d_cnt, d_qc, d_wc, d_ic, d_dc, d_d2c;

@@ -749,7 +749,7 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   if (want_dense && !dense)
     DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
                              d_val.as<double>(), dense, st));
-  skip_on = (mode == DD_ANN && ann_budget == 0 && opts && (opts->flags & DD_SOLVE_SKIP));
+  skip_on = (walk_mode(mode) && ann_budget == 0 && opts && (opts->flags & DD_SOLVE_SKIP));
   if (skip_on) {
     DD_TRY(d_qref.alloc(sizeof(double) * 12 * nm));
     DD_TRY(d_gap.alloc(sizeof(double) * nm));
@@ -1074,7 +1074,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   bool converged = false;
   int stop_reason = 0;
   double prev_full = INFINITY;
-  const bool approximate = (mode == DD_ANN && ann_budget > 0);
+  const bool approximate = (walk_mode(mode) && ann_budget > 0);
   int64_t cg_total = 0;
   double cg_res_max = 0.0;
   if (res && res->history) {

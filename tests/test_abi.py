@@ -58,7 +58,8 @@ def test_struct_layouts_match_header():
     import tempfile
     from paper_2012_00357_amd import _lib
     names = ["dd_dataset_opts", "dd_project_stats", "dd_project_opts", "dd_mesh", "dd_solve_opts",
-             "dd_solve_result", "dd_server_opts", "dd_solve_request", "dd_server_stats"]
+             "dd_solve_result", "dd_server_opts", "dd_solve_request", "dd_server_stats",
+             "dd_index_info"]
     src = "#include <stdio.h>\n#include \"dd.h\"\nint main(void){\n" + "".join(
         f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n"
     with tempfile.TemporaryDirectory() as d:
