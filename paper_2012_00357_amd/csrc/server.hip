@@ -57,7 +57,8 @@ struct Job {
   int64_t n_mp = 0, n_dof = 0;
 
   enum Phase { kQueued, kCg, kReady, kInBatch, kScalars, kDone };
-  Phase phase = kQueued;
+  Phase phase = kQueued;       // scheduler thread only
+  bool done = false;           // results published (guarded by mu): the waiter may free the job
   bool cancel = false;
   dd_status status = DD_OK;
   std::string error;
@@ -177,7 +178,7 @@ void Server::finish(Job* j, dd_status st, const std::string& msg) {
   j->status = st;
   j->error = err;
   j->t_done = Clock::now();
-  j->phase = Job::kDone;
+  j->phase = Job::kDone;   // published (done) once the scheduler has let go of the job
   if (st == DD_OK || st == DD_ERR_NOT_CONVERGED) {
     ++n_completed;
     lat_solve.push_back(ms_since(j->t_submit, j->t_done));
@@ -186,7 +187,6 @@ void Server::finish(Job* j, dd_status st, const std::string& msg) {
   } else {
     ++n_failed;
   }
-  cv_done.notify_all();
 }
 
 // Advances one admitted job as far as it can go without waiting.  Returns true
@@ -352,6 +352,7 @@ void Server::scheduler() {
           j->status = DD_ERR_CANCELLED;
           j->error = "solve cancelled";
           j->phase = Job::kDone;
+          j->done = true;
           j->t_done = Clock::now();
           ++n_cancelled;
           it = queue.erase(it);
@@ -385,12 +386,19 @@ void Server::scheduler() {
       progress = true;
     }
     if (!batch_posted) launch_batch();
-    // drop finished jobs from the active set
-    const size_t before = active.size();
-    active.erase(std::remove_if(active.begin(), active.end(),
-                                [](Job* j) { return j->phase == Job::kDone; }),
-                 active.end());
-    progress |= active.size() != before;
+    // drop finished jobs from the active set, then publish them: a waiter may
+    // free a published job at once, so the scheduler must not touch it again
+    {
+      std::vector<Job*> keep, gone;
+      for (Job* j : active) (j->phase == Job::kDone ? gone : keep).push_back(j);
+      if (!gone.empty()) {
+        active.swap(keep);
+        std::lock_guard<std::mutex> lk(mu);
+        for (Job* j : gone) j->done = true;
+        cv_done.notify_all();
+        progress = true;
+      }
+    }
     n_active = (int64_t)active.size();
     if (!progress) {
       std::unique_lock<std::mutex> lk(mu);
@@ -412,12 +420,14 @@ void Server::scheduler() {
   }
   for (Job* j : active)
     if (j->phase != Job::kDone) finish(j, DD_ERR_CANCELLED, "server destroyed");
-  active.clear();
   std::lock_guard<std::mutex> lk(mu);
+  for (Job* j : active) j->done = true;
+  active.clear();
   for (Job* j : queue) {
     j->status = DD_ERR_CANCELLED;
     j->error = "server destroyed";
     j->phase = Job::kDone;
+    j->done = true;
     ++n_cancelled;
   }
   queue.clear();
@@ -641,7 +651,7 @@ extern "C" dd_status dd_server_wait(dd_server* h, uint64_t ticket, dd_solve_resu
   auto it = s.jobs.find(ticket);
   if (it == s.jobs.end()) return set_error(DD_ERR_ARG, "unknown ticket");
   Job* j = it->second.get();
-  auto done = [&] { return j->phase == Job::kDone; };
+  auto done = [&] { return j->done; };
   if (timeout_s < 0) {
     s.cv_done.wait(lk, done);
   } else if (!s.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
@@ -670,7 +680,7 @@ extern "C" dd_status dd_server_wait(dd_server* h, uint64_t ticket, dd_solve_resu
     res->skipped = 0;
     res->cg_iterations = j->cg_total;
     res->cg_max_residual = j->cg_res_max;
-    res->elapsed_ms = j->phase == Job::kDone ? ms_since(j->t_submit, j->t_done) : 0.0;
+    res->elapsed_ms = ms_since(j->t_submit, j->t_done);
   }
   if (j->status != DD_OK) return set_error(j->status, j->error);
   return DD_OK;
