@@ -109,37 +109,43 @@ ANN_BYTES_PER_POINT = 24.0    # FP16 scaled offsets (12) read per visited point
 ANN_BYTES_PER_LEAF = 64.0     # leaf centre, radius (FP32) read per visited leaf
 ANN_BYTES_PER_LEAF_BOX = 24.0  # quantised leaf box (lo[12], hi[12] as bytes) per test
 ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per test of a higher box
+KMT_BYTES_PER_RECORD = 64.0   # k-means tree child record (centre, radius, code) per test
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 
 
-def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
-    """ANN at scale: N = 10^9 points generated on the device (streamed into the
-    dataset), m = 32768 queries around generated points; exact walks cold and
-    warm-started from the exact answer (the steady state of the DD loop), a few
-    budgets with the generating point as warm start, and the 16^3 DD solve."""
+def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
+    """Tree walks at scale: N = 10^9 points generated on the device (streamed
+    into the dataset), m = 32768 queries around generated points; index "ann"
+    (box tree) or "kmeans" (k-means tree).  Exact walks cold and warm-started
+    from the exact answer (the steady state of the DD loop), a few budgets (and
+    for the k-means tree radius factors f_d < 1) with the generating point as
+    warm start, and the 16^3 DD solve."""
     import numpy as np
     import torch
 
     import ddsynth
     N, m = 1_000_000_000, 32768
+    kmt = index == "kmeans"
     gen = ddsynth.DevicePoints(1003)
     torch.cuda.synchronize()
     t = time.time()
-    ds = L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user, packs=0x1 | 0x10)
+    ds = L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user,
+                                      packs=0x1 | (0x20 if kmt else 0x10))
     torch.cuda.synchronize()
     create_s = time.time() - t
     qe, qs, base = ddsynth.queries_generated(N, 1003, m, 2003)
     states = torch.from_numpy(ddsynth.states(qe, qs)).cuda()
-    out = {"workload": "ANN walk, N=1e9 (generated on device, streamed), m=32768 queries",
+    name = "k-means tree" if kmt else "box tree"
+    out = {"workload": f"{name} walk, N=1e9 (generated on device, streamed), m=32768 queries",
            "N": N, "m": m, "dataset_create_s": round(create_s, 3),
-           "dataset_gb": round(ds.info()[1] / 1e9, 2)}
+           "dataset_gb": round(ds.info()[1] / 1e9, 2), "index": L.dd_dataset_index_info(ds)}
 
-    def run(warm, budget):
+    def run(warm, budget, fd=0.0):
         walk, tot, vis, box, lvs, lbox = [], [], 0, 0, 0, 0
-        L.dd_project(ds, states, warm_start_idx=warm, mode="ann", ann_budget=budget)
+        L.dd_project(ds, states, warm_start_idx=warm, mode=index, ann_budget=budget, ann_fd=fd)
         for _ in range(steps):
-            i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode="ann",
-                                    ann_budget=budget, stats=True)
+            i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode=index,
+                                    ann_budget=budget, ann_fd=fd, stats=True)
             walk.append(st["scan_ms"])
             tot.append(st["total_ms"])
             vis += st["visited"]
@@ -147,8 +153,12 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
             lvs += st["leaves"]
             lbox += st["leaf_boxes"]
         w, tt = sum(walk) / steps, sum(tot) / steps
-        byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
-                + ANN_BYTES_PER_LEAF_BOX * lbox + ANN_BYTES_PER_BOX * (box - lbox)) / steps
+        if kmt:
+            byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
+                    + KMT_BYTES_PER_RECORD * box) / steps
+        else:
+            byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
+                    + ANN_BYTES_PER_LEAF_BOX * lbox + ANN_BYTES_PER_BOX * (box - lbox)) / steps
         return i, d, {"walk_ms": round(w, 3), "total_ms": round(tt, 3),
                       "proj_per_s": round(m / (tt / 1e3), 1),
                       "points_per_query": round(vis / steps / m, 1),
@@ -162,14 +172,18 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
     out["exact_cold"], out["exact_warm"] = cold, warm
     out["roofline"] = {"bound": "hbm", "achieved": warm["achieved_gbs"], "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(warm["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                       "traffic": profile_traffic("ann_walk_N1e9_m32768.md",
+                       "traffic": profile_traffic(f"{index}_walk_N1e9_m32768.md",
                                                   f"N={N} m={m} exact warm"),
-                       "kernel": "ann_walk_kernel (exact, warm-started)",
-                       "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_leaf": ANN_BYTES_PER_LEAF,
-                       "bytes_per_leaf_box": ANN_BYTES_PER_LEAF_BOX,
-                       "bytes_per_box": ANN_BYTES_PER_BOX}
-    log(f"ann 1e9: create {create_s:.2f}s, exact cold {cold['walk_ms']} ms, warm {warm['walk_ms']} ms "
-        f"({warm['achieved_gbs']} GB/s)")
+                       "kernel": f"ann_walk_kernel<false, {'true' if kmt else 'false'}> "
+                                 "(exact, warm-started)",
+                       "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_leaf": ANN_BYTES_PER_LEAF}
+    if kmt:
+        out["roofline"]["bytes_per_record"] = KMT_BYTES_PER_RECORD
+    else:
+        out["roofline"]["bytes_per_leaf_box"] = ANN_BYTES_PER_LEAF_BOX
+        out["roofline"]["bytes_per_box"] = ANN_BYTES_PER_BOX
+    log(f"{index} 1e9: create {create_s:.2f}s, exact cold {cold['walk_ms']} ms, "
+        f"warm {warm['walk_ms']} ms ({warm['achieved_gbs']} GB/s)")
     wb = torch.from_numpy(base).cuda()
     out["budgeted"] = {}
     for b in budgets:
@@ -177,42 +191,50 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True):
         r["recall"] = round(float((ib == ie).double().mean()), 4)
         r["mean_rel_dist_excess"] = float(((db - de) / de).mean())
         out["budgeted"][str(b)] = r
-        log(f"ann 1e9 budget {b}: recall {r['recall']}, walk {r['walk_ms']} ms")
+        log(f"{index} 1e9 budget {b}: recall {r['recall']}, walk {r['walk_ms']} ms")
+    if fds:
+        out["radius_factor"] = {}
+        for fd in fds:
+            ib, db, r = run(wb, 0, fd)
+            r["recall"] = round(float((ib == ie).double().mean()), 4)
+            r["mean_rel_dist_excess"] = float(((db - de) / de).mean())
+            out["radius_factor"][str(fd)] = r
+            log(f"{index} 1e9 f_d {fd}: recall {r['recall']}, walk {r['walk_ms']} ms")
     if not solve:
         ds.close()
         return out
     n = 16
     mask, force = ddsynth.box_bc(n, 100.0)
     init = ddsynth.indices(8 * n ** 3, N, 7)
-    L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann")
+    L.dd_solve(ds, (n, n, n), mask, force, init, mode=index)
     t = time.time()
-    r = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann")
+    r = L.dd_solve(ds, (n, n, n), mask, force, init, mode=index)
     solve_ms = (time.time() - t) * 1e3
     out["dd_solve_16cube"] = {"workload": "16^3 hex (32768 material points), clamp + 100 MPa, "
-                                          "exact ANN projections",
+                                          f"exact {name} walks",
                               "ms": round(solve_ms, 1), "iterations": r["iterations"],
                               "converged": bool(r["converged"])}
-    log(f"ann 1e9 dd_solve 16^3: {solve_ms:.0f} ms, {r['iterations']} iterations")
+    log(f"{index} 1e9 dd_solve 16^3: {solve_ms:.0f} ms, {r['iterations']} iterations")
     t = time.time()
-    rs = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", skip=True)
+    rs = L.dd_solve(ds, (n, n, n), mask, force, init, mode=index, skip=True)
     skip_ms = (time.time() - t) * 1e3
     out["dd_solve_16cube_skip"] = {
         "ms": round(skip_ms, 1), "iterations": rs["iterations"],
         "projections_skipped": rs["skipped"], "projections": rs["iterations"] * 8 * n ** 3,
         "same_u_as_without": bool(np.array_equal(rs["u"], r["u"]))}
-    log(f"ann 1e9 dd_solve 16^3 with skipping: {skip_ms:.0f} ms, skipped {rs['skipped']} of "
+    log(f"{index} 1e9 dd_solve 16^3 with skipping: {skip_ms:.0f} ms, skipped {rs['skipped']} of "
         f"{rs['iterations'] * 8 * n ** 3} projections")
     sched = []
     for budget, ramp in ((4, 0), (4, 10), (16, 10)):
         t = time.time()
-        rb = L.dd_solve(ds, (n, n, n), mask, force, init, mode="ann", ann_budget=budget,
+        rb = L.dd_solve(ds, (n, n, n), mask, force, init, mode=index, ann_budget=budget,
                         ann_ramp=ramp)
         ms_b = (time.time() - t) * 1e3
         err = float(np.linalg.norm(rb["u"] - r["u"]) / np.linalg.norm(r["u"]))
         sched.append({"budget": budget, "ramp": ramp, "ms": round(ms_b, 1),
                       "iterations": rb["iterations"], "stop_reason": rb["stop_reason"],
                       "u_rel_err_vs_exact": err})
-        log(f"ann 1e9 dd_solve 16^3 budget {budget} ramp {ramp}: {ms_b:.0f} ms, "
+        log(f"{index} 1e9 dd_solve 16^3 budget {budget} ramp {ramp}: {ms_b:.0f} ms, "
             f"{rb['iterations']} iterations, u rel err {err:.3e}")
     out["dd_solve_16cube_budgeted"] = sched
     ds.close()
@@ -396,6 +418,10 @@ def main():
                     help="run only the serving leg and print its JSON object")
     ap.add_argument("--ann-only", action="store_true",
                     help="run only the N=1e9 ANN leg and print its JSON object")
+    ap.add_argument("--kmeans-only", action="store_true",
+                    help="run only the N=1e9 k-means tree leg and print its JSON object")
+    ap.add_argument("--skip-kmeans", action="store_true",
+                    help="leave out the N=1e9 k-means tree leg")
     ap.add_argument("--ann-no-solve", action="store_true",
                     help="with --ann-only: leave out the 16^3 DD solve (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -423,8 +449,15 @@ def main():
         print(json.dumps({"serving": serve_leg(L, C, args.serve_solves)}), flush=True)
         return
     if args.ann_only:
-        print(json.dumps({"ann": ann_leg(L, C, args.steps, solve=not args.ann_no_solve)}),
-              flush=True)
+        res = {"ann": ann_leg(L, C, args.steps, solve=not args.ann_no_solve)}
+        if not args.skip_kmeans:
+            res["kmeans"] = ann_leg(L, C, args.steps, solve=not args.ann_no_solve, index="kmeans",
+                                    fds=(0.5, 0.8))
+        print(json.dumps(res), flush=True)
+        return
+    if args.kmeans_only:
+        print(json.dumps({"kmeans": ann_leg(L, C, args.steps, solve=not args.ann_no_solve,
+                                            index="kmeans", fds=(0.5, 0.8))}), flush=True)
         return
     t = time.time()
     e, s = ddsynth.data_points(N, 1002)
@@ -541,6 +574,9 @@ def main():
     ann = None
     if not args.skip_ann:
         ann = ann_leg(L, C, args.steps)
+    kmeans = None
+    if not args.skip_ann and not args.skip_kmeans:
+        kmeans = ann_leg(L, C, args.steps, index="kmeans", fds=(0.5, 0.8))
     serving = None
     if args.serve_solves > 0:
         serving = serve_leg(L, C, args.serve_solves)
@@ -580,6 +616,7 @@ def main():
         "exact_tree_walk": walk,
         "dd_solve": dd,
         "ann": ann,
+        "kmeans_tree": kmeans,
         "serving": serving,
         "paper_example": paper,
         "cpu_baseline": cpu,
