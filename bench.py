@@ -141,7 +141,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
            "dataset_gb": round(ds.info()[1] / 1e9, 2), "index": L.dd_dataset_index_info(ds)}
 
     def run(warm, budget, fd=0.0):
-        walk, tot, vis, box, lvs, lbox = [], [], 0, 0, 0, 0
+        walk, tot, vis, box, lvs, lbox, ovf = [], [], 0, 0, 0, 0, 0
         L.dd_project(ds, states, warm_start_idx=warm, mode=index, ann_budget=budget, ann_fd=fd)
         for _ in range(steps):
             i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode=index,
@@ -152,6 +152,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
             box += st["boxes"]
             lvs += st["leaves"]
             lbox += st["leaf_boxes"]
+            ovf += st["overflowed"]
         w, tt = sum(walk) / steps, sum(tot) / steps
         if kmt:
             byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
@@ -165,6 +166,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
                       "boxes_per_query": round(box / steps / m, 1),
                       "leaves_per_query": round(lvs / steps / m, 1),
                       "leaf_boxes_per_query": round(lbox / steps / m, 1),
+                      "fallback_queries": ovf // steps,
                       "algorithmic_bytes_per_launch": round(byts), "achieved_gbs": round(byts / w / 1e6, 1)}
 
     ie, de, cold = run(None, 0)

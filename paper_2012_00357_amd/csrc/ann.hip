@@ -37,7 +37,9 @@ namespace dd {
 namespace {
 
 constexpr int kWaves = 4;                          // queries (wavefronts) per block
-constexpr int kStack = kAnnFan * kAnnMaxLevels;    // depth-first stack entries per wave
+// depth-first stack entries per wave: at most 63 pending siblings per level,
+// for the box tree's kAnnMaxLevels and the k-means tree's deeper cut
+constexpr int kStack = kAnnFan * 10;
 constexpr int kCand = 64;                          // candidate list entries per wave
 constexpr int kBatch = 2;                          // leaves whose loads are issued together
 constexpr int kRankSort = 16;                      // children ordered by rank up to this many
