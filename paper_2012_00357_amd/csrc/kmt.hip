@@ -374,15 +374,17 @@ __global__ void seed_kernel(const uint32_t* __restrict__ ids, const double* __re
   for (int c = 0; c < 12; ++c) cent[i * 12 + c] = (float)w64[12 * id + c];
 }
 
-// Covering radius of every node about its FP32 centroid (FP64 distances; the
-// float bits of non-negative doubles order as integers).
+// Covering radius of every stored node about its FP32 centroid (FP64
+// distances; the bits of non-negative doubles order as integers).
 __global__ __launch_bounds__(kThreads) void radius_kernel(const uint32_t* __restrict__ ids,
                                                           const double* __restrict__ w64, Segs G,
                                                           int64_t S,
                                                           const uint32_t* __restrict__ cbase,
+                                                          const uint32_t* __restrict__ store_f,
                                                           unsigned long long* __restrict__ rad) {
   const int t = threadIdx.x;
   const int64_t s = chunk_segment(cbase, S, blockIdx.x);
+  if (!store_f[s]) return;   // only the nodes stored this round need their radius
   const uint32_t kc = blockIdx.x - cbase[s];
   const int64_t first = (int64_t)G.start[s] + (int64_t)kc * kChunk;
   const int64_t end = min((int64_t)G.start[s] + (int64_t)G.cnt[s], first + kChunk);
@@ -691,7 +693,7 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
       DD_TRY(rad_b.alloc(8 * (size_t)S));
       DD_HIP(hipMemsetAsync(rad_b.p, 0, rad_b.bytes, st));
       hipLaunchKernelGGL(radius_kernel, dim3(n_chunks), dim3(kThreads), 0, st, ids_in, w64, G, S,
-                         cbase, rad_b.as<unsigned long long>());
+                         cbase, store_f.as<uint32_t>(), rad_b.as<unsigned long long>());
       DD_TRY(grow(recs, 64 * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(rec_owner, 4 * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(frontier, 4 * (size_t)(n_nodes + n_store), st));
