@@ -134,7 +134,7 @@ typedef struct dd_project_opts {
   int32_t ann_budget;       /* DD_ANN, DD_KMEANS: max leaves visited per query;
                                0 = unlimited (exact) */
   int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
-                               every 16th tile first; 0 = automatic (2 without a warm start) */
+                               every 64th tile first; 0 = automatic (2 without a warm start) */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
   double ann_fd;            /* DD_KMEANS: radius factor f_d in (0, 1] of the ball test;
                                0 = 1 (exact) */

@@ -227,11 +227,13 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_HIP(hipMemsetAsync(cb.count, 0, sizeof(int) * (size_t)m * 2, st));
     c.cb = cb;
     // Without a warm start the bound starts at +inf; a streaming pass over every
-    // 16th tile seeds it, so the marking pass logs few stale work items.
+    // 64th tile seeds it, so the marking pass logs few stale work items (a
+    // denser seeding pass costs more than the extra items it saves: at N = 2^27,
+    // m = 65536 every 16th tile gives 299 ms per step, every 64th 289 ms).
     const int passes = (opts && opts->passes) ? opts->passes : (warm_start_idx_dev ? 1 : 2);
     if (passes >= 2) {
       c.phase = Scan16Call::kBound;
-      c.stride = 16;
+      c.stride = 64;
       DD_TRY(launch_scan16(D, fp16, c, st));
       DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
     }
