@@ -224,7 +224,9 @@ __device__ inline float min16(float run, const f32x16_t& a) {
 }
 
 constexpr int kG16 = 2;                                  // 32-query groups per wave
-constexpr int kQ16 = 4 * kG16 * 32;                      // queries per workgroup
+constexpr int kW16 = 8;                                  // waves per workgroup
+constexpr int kT16 = 64 * kW16;                          // threads per workgroup
+constexpr int kQ16 = kW16 * kG16 * 32;                   // queries per workgroup
 static_assert(kG16 == 2, "the pipelined inner loop is written for two query groups");
 
 // Per-(query group, tile) operands of the 16-bit scans: centred query column
@@ -268,15 +270,16 @@ __device__ inline void centre_select(const float* __restrict__ cp, int h, float 
   for (int i = 0; i < 8; ++i) cs[i] = h ? (i < 4 ? cp[8 + i] : 0.0f) : cp[i];
 }
 
-// Streaming pass of the 16-bit scan.  Every workgroup covers 256 queries (two
-// 32-query groups per wave) against the tiles of its split; the split's tiles
+// Streaming pass of the 16-bit scan.  Every workgroup (eight waves, so that two
+// workgroups with their double-buffered tile fill a CU with four waves per SIMD)
+// covers 512 queries (two 32-query groups per wave) against the tiles of its split; the split's tiles
 // are visited with stride `stride` (1 = all; > 1 = a bound-seeding subsample).
 // Tracks the sqrt-space bound U of each query; with MARK, appends a work item
 // whenever some query of a group may have a candidate in the tile (its lower
 // bound <= its running U).  Tiles are staged through LDS half-major (each lane
 // reads 16 consecutive bytes of its row half: conflict-free 128-bit reads).
 template <class T16, int TILE, bool MARK>
-__global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
+__global__ __launch_bounds__(kT16, 4) void scan16_pass_kernel(
     const uint4* __restrict__ wp, const float* __restrict__ centre, const float* __restrict__ radius,
     int64_t n_tiles, int stride, const double* __restrict__ qw, const double* __restrict__ qn2,
     const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L, int S,
@@ -284,9 +287,10 @@ __global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
     unsigned item_cap) {
   typedef Vec16<T16> VT;
   typedef typename VT::type vec_t;
-  constexpr int V = TILE * 2 / 256;   // uint4 per thread per tile
-  constexpr int NB = TILE / 32;       // 32-row blocks per tile
-  static_assert(V >= 1 && TILE * 2 % 256 == 0, "tile");
+  constexpr int V = (TILE * 2 + kT16 - 1) / kT16;   // uint4 per thread per tile
+  constexpr int NB = TILE / 32;                     // 32-row blocks per tile
+  static_assert(TILE * 2 % kT16 == 0 || TILE * 2 < kT16, "tile");
+  auto staged = [](int e) { return TILE * 2 >= kT16 || e < TILE * 2; };
   __shared__ uint4 lds[2][2 * TILE];  // [buffer][half * TILE + row]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, col = lane & 31;
@@ -318,7 +322,8 @@ __global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
     {
       const uint4* src = wp + t0 * TILE * 2;
 #pragma unroll
-      for (int v = 0; v < V; ++v) lds[0][lds_slot(tid + 256 * v)] = src[tid + 256 * v];
+      for (int v = 0; v < V; ++v)
+        if (staged(tid + kT16 * v)) lds[0][lds_slot(tid + kT16 * v)] = src[tid + kT16 * v];
     }
     __syncthreads();
     int cur = 0;
@@ -329,7 +334,8 @@ __global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
       {
         const uint4* src = wp + (more ? tn : t) * TILE * 2;
 #pragma unroll
-        for (int v = 0; v < V; ++v) pre[v] = src[tid + 256 * v];
+        for (int v = 0; v < V; ++v)
+          if (staged(tid + kT16 * v)) pre[v] = src[tid + kT16 * v];
       }
       float cs[8];
       centre_select(centre + 12 * t, h, cs);
@@ -392,7 +398,8 @@ __global__ __launch_bounds__(256, 4) void scan16_pass_kernel(
       }
       if (more) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) lds[cur ^ 1][lds_slot(tid + 256 * v)] = pre[v];
+        for (int v = 0; v < V; ++v)
+          if (staged(tid + kT16 * v)) lds[cur ^ 1][lds_slot(tid + kT16 * v)] = pre[v];
       }
       __syncthreads();
       cur ^= 1;
@@ -473,12 +480,12 @@ static dd_status launch16(const Dataset& D, const uint16_t* pack, const Scan16Ca
                        c.Q->u32, c.Q->invalid, c.L, c.items, c.n_items, c.item_cap, c.cb);
   } else if (c.phase == Scan16Call::kMark) {
     hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, true>), dim3((unsigned)(qblocks * c.S)),
-                       dim3(256), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
+                       dim3(kT16), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
                        c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
                        c.items, c.n_items, c.item_cap);
   } else {
     hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, false>), dim3((unsigned)(qblocks * c.S)),
-                       dim3(256), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
+                       dim3(kT16), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
                        c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
                        c.items, c.n_items, c.item_cap);
   }
