@@ -768,7 +768,10 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
     ++round;
   }
 
-  // leaves: compact blocks, slot maps, child records
+  // leaves: compact blocks, slot maps, child records.  Slots are u32 and the
+  // walk's codes hold 28-bit leaf and node numbers.
+  if (n_leaf * kAnnLeaf > 0xFFFFFFFFll || n_leaf >= (1ll << 28) || n_nodes >= (1ll << 28))
+    return set_error(DD_ERR_TOO_LARGE, "k-means tree: too many leaves or nodes");
   D.kmt_leaves = n_leaf;
   DD_TRY(D.kmt_meta.alloc(64 * (size_t)n_leaf));
   DD_TRY(D.kmt_h16.alloc(2 * 12 * kAnnLeaf * (size_t)n_leaf));
