@@ -123,6 +123,26 @@ def test_kmeans_budget_and_fd_are_approximate_within_bounds(L, config0, C0):
         L.dd_project(ds, states, mode="kmeans", ann_fd=1.5)
 
 
+def test_kmeans_mode_needs_its_pack(L, C0):
+    """The k-means mode on a dataset without the tree is refused (status 8);
+    a dataset without trees reports an empty index."""
+    e, s = ddsynth.data_points(1000, 61)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN)
+    info = L.dd_dataset_index_info(ds)
+    assert info["kmeans_nodes"] == 0 and info["kmeans_leaves"] == 0 and info["ann_levels"] >= 1
+    qe, qs, _ = ddsynth.queries(e, s, 10, 62)
+    with pytest.raises(L.DDError) as ex:
+        L.dd_project(ds, to_dev(ddsynth.states(qe, qs)), mode="kmeans")
+    assert ex.value.status == 8
+    ds2 = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64)
+    assert all(v == 0 for v in L.dd_dataset_index_info(ds2).values())
+    ds3 = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | KMEANS)
+    for fd in (-0.5, 1.0000001):
+        with pytest.raises(L.DDError) as ex:
+            L.dd_project(ds3, to_dev(ddsynth.states(qe, qs)), mode="kmeans", ann_fd=fd)
+        assert ex.value.status == 1
+
+
 def test_kmeans_repeated_points(L, C0):
     """Data with three distinct points repeated (every split degenerate: the
     build falls back to equal runs): exact answers, ties to the lowest index."""
