@@ -109,7 +109,7 @@ ANN_BYTES_PER_POINT = 24.0    # FP16 scaled offsets (12) read per visited point
 ANN_BYTES_PER_LEAF = 64.0     # leaf centre, radius (FP32) read per visited leaf
 ANN_BYTES_PER_LEAF_BOX = 24.0  # quantised leaf box (lo[12], hi[12] as bytes) per test
 ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per test of a higher box
-KMT_BYTES_PER_RECORD = 64.0   # k-means tree child record (centre, radius, code) per test
+KMT_BYTES_PER_RECORD = 160.0  # k-means tree child record (centre, radius, code, box) per test
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 
 

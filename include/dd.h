@@ -86,12 +86,13 @@ typedef enum dd_mode {
   /* As DD_MIXED_BF16 with IEEE half precision instead of bfloat16. */
   DD_MIXED_FP16 = 5,
   /* Warm-started walk over the k-means tree of Section 4 (recursive 4-means,
-   * pack DD_PACK_KMEANS): every stored node holds up to 64 children (three
-   * 4-means levels), each with the ball (centroid, radius) of its points; a
-   * child is pruned when |q - c| - f_d r exceeds the best certified distance
-   * so far.  Same certified FP32 arithmetic, FP64 rerank, budget and
-   * warm-start rules as DD_ANN; exact with ann_budget = 0 and f_d = 1
-   * (dd_project_opts.ann_fd = 0 or 1), approximate otherwise. */
+   * pack DD_PACK_KMEANS): every stored node holds up to 64 children (up to
+   * three 4-means levels), each with the ball (centroid, radius) of its points
+   * and their box in principal-axis coordinates; a child is pruned when
+   * |q - c| - f_d r (with f_d = 1 also its box distance) exceeds the best
+   * certified distance so far.  Same certified FP32 arithmetic, FP64 rerank,
+   * budget and warm-start rules as DD_ANN; exact with ann_budget = 0 and
+   * f_d = 1 (dd_project_opts.ann_fd = 0 or 1), approximate otherwise. */
   DD_KMEANS = 6
 } dd_mode;
 

@@ -198,12 +198,14 @@ __device__ inline float box_lb(const float* __restrict__ b, const float yq[12], 
   return __builtin_sqrtf(s) * kLbShrink - slack;
 }
 
-// Lower bound of the whitened distance from the query to the points of a ball
-// (centre c, radius r >= max |x - c|): |q - c| - f_d r, with |q - c| shrunk by
-// the slack that covers the rounding of the query and of this sum.  Exact
-// bound for f_d = 1; f_d < 1 is the approximate test of Section 4.
-__device__ inline float ball_lb(const float* __restrict__ rec, const float qf[12], float slack,
-                                float fd, uint32_t& code) {
+// Lower bound of the whitened distance from the query to the points of a
+// k-means tree child record: the ball (centre c, radius r >= max |x - c|)
+// gives |q - c| - f_d r (|q - c| shrunk by the slack that covers the rounding
+// of the query and of this sum), exact for f_d = 1 and the approximate test of
+// Section 4 for f_d < 1; with f_d = 1 the bound is also at least the distance
+// to the record's box in principal-axis coordinates.
+__device__ inline float record_lb(const float* __restrict__ rec, const float qf[12],
+                                  const float yq[12], float slack, float fd, uint32_t& code) {
   const float4* m = reinterpret_cast<const float4*>(rec);
   const float4 a = m[0], b = m[1], c = m[2], e = m[3];
   const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
@@ -214,7 +216,9 @@ __device__ inline float ball_lb(const float* __restrict__ rec, const float qf[12
     s = fmaf(t, t, s);
   }
   code = __builtin_bit_cast(uint32_t, e.y);
-  return __builtin_sqrtf(s) * kLbShrink - slack - fd * e.x;
+  const float ball = __builtin_sqrtf(s) * kLbShrink - slack - fd * e.x;
+  if (fd != 1.0f) return ball;
+  return fmaxf(ball, box_lb(rec + 16, yq, slack));
 }
 
 // Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront.
@@ -272,10 +276,8 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
 #pragma unroll
     for (int a = 0; a < 12; ++a) {
       double y = 0.0;
-      if (!KMT) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
-      }
+      for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
       yq[a] = (float)y;
     }
   }
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     if (KMT) {
       // child records [c0, c0 + cnt) of a k-means tree node; val is the code
       if (lane < cnt) {
-        const float lb = ball_lb(A.kmt_child + 16 * (c0 + lane), qf, slack, A.fd, val);
+        const float lb = record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd, val);
         if (lb <= U) key = fmaxf(lb, 0.0f);
       }
       leaf_boxes += (unsigned long long)__popcll(__ballot(lane < cnt && (val >> 28) == 0));

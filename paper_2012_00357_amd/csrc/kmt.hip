@@ -15,7 +15,8 @@
 //   * a stable partition of the node's points by label.
 // Nodes of at most 64 points become leaves.  The walk reads a 64-ary cut of
 // the 4-ary tree: a stored node lists a frontier of its descendants (at most 64
-// children, each with the ball (FP32 centre, radius rounded up) of its points).
+// children, each with the ball (FP32 centre, radius rounded up) of its points
+// and their box in the dataset's principal-axis coordinates, rounded outward).
 // Nodes are stored three 4-means levels apart counted from the leaves; every
 // other node is absorbed into the frontier of the stored node above it while
 // that frontier stays within 64 entries, and stored when it would not.  Leaves
@@ -23,6 +24,7 @@
 // (FP32 centre and radius, FP16 scaled offsets), empty slots +inf.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "dd_internal.h"
@@ -41,6 +43,32 @@ constexpr int kWavesPerBlock = kThreads / 64;
 constexpr int kFan = 64;              // children per stored node
 constexpr int kMaxRounds = 200;
 constexpr int kAcc = kK * 13;         // fixed-point sums (12) and count per child
+
+struct Axes {                         // principal axes: V[12 k + a] = component k of axis a
+  double V[144];
+};
+
+// Order-preserving map of floats to unsigned integers (atomic min / max).
+__device__ inline uint32_t fkey(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float fkey_inv(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// y = V^T x rounded outward to FP32 (lo rounded down, hi up).
+__device__ inline void rotate_out(const Axes& R, const double (&x)[12], float (&lo)[12],
+                                  float (&hi)[12]) {
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    double y = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) y = fma(R.V[12 * k + a], x[k], y);
+    lo[a] = __double2float_rd(y);
+    hi[a] = __double2float_ru(y);
+  }
+}
 
 unsigned grid_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -375,40 +403,71 @@ __global__ void seed_kernel(const uint32_t* __restrict__ ids, const double* __re
 }
 
 // Covering radius of every stored node about its FP32 centroid (FP64
-// distances; the bits of non-negative doubles order as integers).
-__global__ __launch_bounds__(kThreads) void radius_kernel(const uint32_t* __restrict__ ids,
-                                                          const double* __restrict__ w64, Segs G,
-                                                          int64_t S,
-                                                          const uint32_t* __restrict__ cbase,
-                                                          const uint32_t* __restrict__ store_f,
-                                                          unsigned long long* __restrict__ rad) {
+// distances; the bits of non-negative doubles order as integers) and its box
+// in principal-axis coordinates (rounded outward; order-preserving keys).
+// rad[s]: radius bits; blo[s][12], bhi[s][12]: box keys (start at all ones / zero).
+__global__ __launch_bounds__(kThreads) void node_stats_kernel(const uint32_t* __restrict__ ids,
+                                                              const double* __restrict__ w64,
+                                                              Segs G, int64_t S,
+                                                              const uint32_t* __restrict__ cbase,
+                                                              const uint32_t* __restrict__ store_f,
+                                                              Axes R,
+                                                              unsigned long long* __restrict__ rad,
+                                                              uint32_t* __restrict__ kblo,
+                                                              uint32_t* __restrict__ kbhi) {
   const int t = threadIdx.x;
   const int64_t s = chunk_segment(cbase, S, blockIdx.x);
-  if (!store_f[s]) return;   // only the nodes stored this round need their radius
+  if (!store_f[s]) return;   // only the nodes stored this round need their ball and box
   const uint32_t kc = blockIdx.x - cbase[s];
   const int64_t first = (int64_t)G.start[s] + (int64_t)kc * kChunk;
   const int64_t end = min((int64_t)G.start[s] + (int64_t)G.cnt[s], first + kChunk);
   double c[12];
   for (int a = 0; a < 12; ++a) c[a] = (double)G.mean[s * 12 + a];
   double r = 0.0;
+  float blo[12], bhi[12];
+  for (int a = 0; a < 12; ++a) {
+    blo[a] = INFINITY;
+    bhi[a] = -INFINITY;
+  }
   for (int it = 0; it < kItems; ++it) {
     const int64_t p = first + (int64_t)it * kThreads + t;
     if (p >= end) break;
     const int64_t id = ids[p];
-    double d = 0.0;
+    double x[12], d = 0.0;
     for (int a = 0; a < 12; ++a) {
-      const double u = w64[12 * id + a] - c[a];
+      x[a] = w64[12 * id + a];
+      const double u = x[a] - c[a];
       d = fma(u, u, d);
     }
     r = fmax(r, sqrt(d));
+    float lo[12], hi[12];
+    rotate_out(R, x, lo, hi);
+    for (int a = 0; a < 12; ++a) {
+      blo[a] = fminf(blo[a], lo[a]);
+      bhi[a] = fmaxf(bhi[a], hi[a]);
+    }
   }
-  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off));
-  if ((t & 63) == 0) atomicMax(&rad[s], (unsigned long long)__double_as_longlong(r));
+  for (int off = 32; off > 0; off >>= 1) {
+    r = fmax(r, __shfl_xor(r, off));
+    for (int a = 0; a < 12; ++a) {
+      blo[a] = fminf(blo[a], __shfl_xor(blo[a], off));
+      bhi[a] = fmaxf(bhi[a], __shfl_xor(bhi[a], off));
+    }
+  }
+  if ((t & 63) == 0) {
+    atomicMax(&rad[s], (unsigned long long)__double_as_longlong(r));
+    for (int a = 0; a < 12; ++a) {
+      if (blo[a] != INFINITY) atomicMin(&kblo[12 * s + a], fkey(blo[a]));
+      if (bhi[a] != -INFINITY) atomicMax(&kbhi[12 * s + a], fkey(bhi[a]));
+    }
+  }
 }
 
-// Child records of the nodes stored this round: ball of the node's points,
-// code 1 << 28 | node, listed under the node's owner.
+// Child records of the nodes stored this round: ball and box of the node's
+// points, code 1 << 28 | node, listed under the node's owner.
 __global__ void node_record_kernel(Segs G, int64_t S, const unsigned long long* __restrict__ rad,
+                                   const uint32_t* __restrict__ kblo,
+                                   const uint32_t* __restrict__ kbhi,
                                    const uint32_t* __restrict__ store_f,
                                    const uint32_t* __restrict__ store_at, uint32_t node_base,
                                    float* __restrict__ rec, uint32_t* __restrict__ rec_owner,
@@ -416,7 +475,11 @@ __global__ void node_record_kernel(Segs G, int64_t S, const unsigned long long* 
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S || !store_f[s]) return;
   const int64_t at = rec_base + store_at[s];
-  float* r = rec + 16 * at;
+  float* r = rec + kKmtRecord * at;
+  for (int a = 0; a < 12; ++a) {
+    r[16 + a] = fkey_inv(kblo[12 * s + a]);
+    r[28 + a] = fkey_inv(kbhi[12 * s + a]);
+  }
   for (int c = 0; c < 12; ++c) r[c] = G.mean[s * 12 + c];
   const double rd = __longlong_as_double((long long)rad[s]);
   r[12] = __double2float_ru(rd * (1.0 + 1e-12));
@@ -435,7 +498,7 @@ __device__ inline double wave_sum_d(double v) {
 // offsets in slots leaf * 64 + lane, empty slots +inf), slot maps, and the
 // leaf's child record.
 __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ ids,
-                                                   const double* __restrict__ w64,
+                                                   const double* __restrict__ w64, Axes R,
                                                    const LeafRec* __restrict__ leaves,
                                                    int64_t n_leaf, float* __restrict__ meta,
                                                    _Float16* __restrict__ h16,
@@ -467,11 +530,23 @@ __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ 
   const double inv = 1.0 / (double)rf;
   for (int a = 0; a < 12; ++a)
     h16[12 * slot + a] = v ? (_Float16)((x[a] - (double)c[a]) * inv) : (_Float16)INFINITY;
+  float blo[12], bhi[12];
+  rotate_out(R, x, blo, bhi);
+  for (int a = 0; a < 12; ++a) {
+    if (!v) {
+      blo[a] = INFINITY;
+      bhi[a] = -INFINITY;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      blo[a] = fminf(blo[a], __shfl_xor(blo[a], off));
+      bhi[a] = fmaxf(bhi[a], __shfl_xor(bhi[a], off));
+    }
+  }
   slot_pos[slot] = v ? (uint32_t)id : 0xFFFFFFFFu;
   if (v) pos_slot[id] = (uint32_t)slot;
   if (lane == 0) {
     float* m = meta + 16 * leaf;
-    float* q = rec + 16 * (rec_base + leaf);
+    float* q = rec + kKmtRecord * (rec_base + leaf);
     for (int a = 0; a < 12; ++a) {
       m[a] = c[a];
       q[a] = c[a];
@@ -484,6 +559,10 @@ __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ 
     q[13] = __uint_as_float((uint32_t)leaf);
     q[14] = 0.0f;
     q[15] = 0.0f;
+    for (int a = 0; a < 12; ++a) {
+      q[16 + a] = blo[a];
+      q[28 + a] = bhi[a];
+    }
     rec_owner[rec_base + leaf] = L.owner;
   }
 }
@@ -491,8 +570,8 @@ __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ 
 __global__ void gather_records_kernel(const float* __restrict__ rec, const uint32_t* __restrict__ order,
                                       int64_t n, float* __restrict__ child) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 16 * n) return;
-  child[i] = rec[16 * (int64_t)order[i / 16] + (i % 16)];
+  if (i >= kKmtRecord * n) return;
+  child[i] = rec[kKmtRecord * (int64_t)order[i / kKmtRecord] + (i % kKmtRecord)];
 }
 
 // node[o] = (first record, end) of owner o's run in the owner-sorted records.
@@ -555,6 +634,8 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
     e = std::min(e, ex - 1);
   }
   const double fix = std::ldexp(1.0, e);
+  Axes R;
+  std::memcpy(R.V, D.V, sizeof(R.V));
 
   DevBuf ids[2], labels, leaves_b, recs, rec_owner, frontier;
   DD_TRY(ids[0].alloc(4 * (size_t)N));
@@ -689,16 +770,23 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
                             (int64_t)read_u32(store_f.as<uint32_t>() + S - 1, st);
     const uint32_t node_base = (uint32_t)n_nodes;
     if (n_store > 0) {
-      // their balls become child records of their owners
+      // their balls and boxes become child records of their owners
+      DevBuf kblo, kbhi;
       DD_TRY(rad_b.alloc(8 * (size_t)S));
+      DD_TRY(kblo.alloc(4 * 12 * (size_t)S));
+      DD_TRY(kbhi.alloc(4 * 12 * (size_t)S));
       DD_HIP(hipMemsetAsync(rad_b.p, 0, rad_b.bytes, st));
-      hipLaunchKernelGGL(radius_kernel, dim3(n_chunks), dim3(kThreads), 0, st, ids_in, w64, G, S,
-                         cbase, store_f.as<uint32_t>(), rad_b.as<unsigned long long>());
-      DD_TRY(grow(recs, 64 * (size_t)(n_rec + n_store), st));
+      DD_HIP(hipMemsetAsync(kblo.p, 0xFF, kblo.bytes, st));
+      DD_HIP(hipMemsetAsync(kbhi.p, 0, kbhi.bytes, st));
+      hipLaunchKernelGGL(node_stats_kernel, dim3(n_chunks), dim3(kThreads), 0, st, ids_in, w64, G,
+                         S, cbase, store_f.as<uint32_t>(), R, rad_b.as<unsigned long long>(),
+                         kblo.as<uint32_t>(), kbhi.as<uint32_t>());
+      DD_TRY(grow(recs, 4 * kKmtRecord * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(rec_owner, 4 * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(frontier, 4 * (size_t)(n_nodes + n_store), st));
       hipLaunchKernelGGL(node_record_kernel, dim3(grid_of(S, 256)), dim3(256), 0, st, G, S,
-                         rad_b.as<unsigned long long>(), store_f.as<uint32_t>(),
+                         rad_b.as<unsigned long long>(), kblo.as<uint32_t>(), kbhi.as<uint32_t>(),
+                         store_f.as<uint32_t>(),
                          store_at.as<uint32_t>(), node_base, recs.as<float>(),
                          rec_owner.as<uint32_t>(), n_rec);
       hipLaunchKernelGGL(new_frontier_kernel, dim3(grid_of(S, 256)), dim3(256), 0, st, S,
@@ -777,10 +865,10 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
   DD_TRY(D.kmt_h16.alloc(2 * 12 * kAnnLeaf * (size_t)n_leaf));
   DD_TRY(D.kmt_pos.alloc(4 * kAnnLeaf * (size_t)n_leaf));
   DD_TRY(D.kmt_slot.alloc(4 * (size_t)N));
-  DD_TRY(grow(recs, 64 * (size_t)(n_rec + n_leaf), st));
+  DD_TRY(grow(recs, 4 * kKmtRecord * (size_t)(n_rec + n_leaf), st));
   DD_TRY(grow(rec_owner, 4 * (size_t)(n_rec + n_leaf), st));
   hipLaunchKernelGGL(leaf_kernel, dim3(grid_of(n_leaf, 4)), dim3(256), 0, st,
-                     ids[cur].as<uint32_t>(), D.w64.as<double>(), leaves_b.as<LeafRec>(), n_leaf,
+                     ids[cur].as<uint32_t>(), D.w64.as<double>(), R, leaves_b.as<LeafRec>(), n_leaf,
                      D.kmt_meta.as<float>(), D.kmt_h16.as<_Float16>(), D.kmt_pos.as<uint32_t>(),
                      D.kmt_slot.as<uint32_t>(), recs.as<float>(), rec_owner.as<uint32_t>(), n_rec);
   DD_HIP(hipGetLastError());
@@ -793,8 +881,8 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
   int bits = 1;
   while (bits < 32 && (1ll << bits) < n_nodes) ++bits;
   DD_TRY(radix_sort_pairs(rec_owner.as<uint32_t>(), order.as<uint32_t>(), n_rec, bits, st));
-  DD_TRY(D.kmt_child.alloc(64 * (size_t)n_rec));
-  hipLaunchKernelGGL(gather_records_kernel, dim3(grid_of(16 * n_rec, 256)), dim3(256), 0, st,
+  DD_TRY(D.kmt_child.alloc(4 * kKmtRecord * (size_t)n_rec));
+  hipLaunchKernelGGL(gather_records_kernel, dim3(grid_of(kKmtRecord * n_rec, 256)), dim3(256), 0, st,
                      recs.as<float>(), order.as<uint32_t>(), n_rec, D.kmt_child.as<float>());
   DD_TRY(D.kmt_node.alloc(8 * (size_t)n_nodes));
   DD_HIP(hipMemsetAsync(D.kmt_node.p, 0, D.kmt_node.bytes, st));
