@@ -140,7 +140,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
            "N": N, "m": m, "dataset_create_s": round(create_s, 3),
            "dataset_gb": round(ds.info()[1] / 1e9, 2), "index": L.dd_dataset_index_info(ds)}
 
-    def run(warm, budget, fd=0.0):
+    def run(warm, budget, fd=None):
         walk, tot, vis, box, lvs, lbox, ovf = [], [], 0, 0, 0, 0, 0
         L.dd_project(ds, states, warm_start_idx=warm, mode=index, ann_budget=budget, ann_fd=fd)
         for _ in range(steps):
@@ -335,12 +335,16 @@ def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8, modes=("bf16", "ann")):
 
 
 def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_000_000_000),
-              seeds=5, mode="ann"):
+              seeds=5, mode="ann", kmeans_Ns=(100_000_000, 1_000_000_000), kmeans_fds=(0.0, 0.4),
+              kmeans_ramp=20):
     """The paper's own example (Section 3): cube of edge 10 mm, 20^3 hexahedra
     (64000 material points), bottom fixed, top rotated by 2 degrees; data from
     the nonlinear law with strains in +-0.025; metric from the PCA of the data;
-    exact projections.  Per data-set size: iterations, final global distance
-    and solve time over `seeds` random initial associations."""
+    exact projections.  Per data-set size: iterations, final global distance,
+    solve time and the GPU time of the projections over `seeds` random initial
+    associations.  For the sizes in kmeans_Ns also the approximate k-means tree
+    of Sections 4.2 and 4.5: f_d ramped linearly from 0 to f_d^f over the
+    first kmeans_ramp iterations, for each f_d^f in kmeans_fds."""
     import numpy as np
     import torch
 
@@ -350,44 +354,69 @@ def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_0
     out = {"workload": "paper example: 20^3 hex cube (edge 10 mm, 64000 material points), bottom "
                        "fixed, top rotated 2 deg; nonlinear law E=1000 MPa, alpha=500, strains "
                        "+-0.025; PCA metric; exact " + mode + " projections",
-           "runs": []}
-    for N in Ns:
-        seed = 3000 + N % 997
-        t = time.time()
+           "runs": [], "kmeans_runs": []}
+
+    def dataset(N, seed, packs):
         if N <= 1_000_000:
             e, s = ddsynth.data_points_nonlinear(N, seed)
             de, dsg = torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda()
             C = L.dd_metric_pca(de, dsg)
-            ds = L.dd_dataset_create(de, dsg, C, packs=0x1 | 0x4 | 0x10)
+            ds = L.dd_dataset_create(de, dsg, C, packs=packs)
             del de, dsg
-        else:
-            # generated on the device and streamed into the dataset; the metric
-            # from the PCA of the first 2^24 points (a uniform sample of the set)
-            gen = ddsynth.DevicePoints(seed, law="nonlinear")
-            se, ss = gen.generate(0, 1 << 24)
-            C = L.dd_metric_pca(se, ss)
-            del se, ss
-            torch.cuda.empty_cache()
-            ds = L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user, packs=0x1 | 0x10)
-        torch.cuda.synchronize()
-        build_s = time.time() - t
-        its, dist, ms = [], [], []
+            return ds
+        # generated on the device and streamed into the dataset; the metric
+        # from the PCA of the first 2^24 points (a uniform sample of the set)
+        gen = ddsynth.DevicePoints(seed, law="nonlinear")
+        se, ss = gen.generate(0, 1 << 24)
+        C = L.dd_metric_pca(se, ss)
+        del se, ss
+        torch.cuda.empty_cache()
+        return L.dd_dataset_create_streamed(N, C, gen.fill_fn, gen.user, packs=packs)
+
+    def solves(ds, N, **kw):
+        its, dist, ms, pms = [], [], [], []
         for seed in range(seeds):
             init = ddsynth.indices(8 * n ** 3, N, 5000 + seed)
             t = time.time()
-            r = L.dd_solve(ds, (n, n, n, size, size, size), mask, force, init, mode=mode,
-                           dirichlet_values=val)
+            r = L.dd_solve(ds, (n, n, n, size, size, size), mask, force, init,
+                           dirichlet_values=val, **kw)
             ms.append((time.time() - t) * 1e3)
             its.append(r["iterations"])
             dist.append(float(r["d_full"][-1]))
-        run = {"N": N, "dataset_build_s": round(build_s, 2),
-               "mean_iterations": round(float(np.mean(its)), 2),
-               "mean_final_global_distance": float(np.mean(dist)),
-               "mean_solve_ms": round(float(np.mean(ms)), 1),
-               "p50_solve_ms": round(float(np.percentile(ms, 50)), 1)}
+            pms.append(r["project_ms"])
+        return {"mean_iterations": round(float(np.mean(its)), 2),
+                "mean_final_global_distance": float(np.mean(dist)),
+                "mean_solve_ms": round(float(np.mean(ms)), 1),
+                "p50_solve_ms": round(float(np.percentile(ms, 50)), 1),
+                "mean_search_ms": round(float(np.mean(pms)), 1)}
+
+    for N in Ns:
+        seed = 3000 + N % 997
+        t = time.time()
+        ds = dataset(N, seed, 0x1 | 0x10 | (0x4 if N <= 1_000_000 else 0))
+        torch.cuda.synchronize()
+        run = {"N": N, "dataset_build_s": round(time.time() - t, 2)}
+        run.update(solves(ds, N, mode=mode))
         out["runs"].append(run)
         log(f"paper example N={N}: {run['mean_iterations']} iterations, final distance "
-            f"{run['mean_final_global_distance']:.4g}, {run['mean_solve_ms']} ms")
+            f"{run['mean_final_global_distance']:.4g}, {run['mean_solve_ms']} ms "
+            f"(search {run['mean_search_ms']} ms)")
+        ds.close()
+        torch.cuda.empty_cache()
+        if N not in kmeans_Ns or not kmeans_fds:
+            continue
+        t = time.time()
+        ds = dataset(N, seed, 0x1 | 0x20)
+        torch.cuda.synchronize()
+        build_s = round(time.time() - t, 2)
+        for fd in kmeans_fds:
+            run = {"N": N, "f_d_final": fd, "ramp_iterations": kmeans_ramp,
+                   "dataset_build_s": build_s}
+            run.update(solves(ds, N, mode="kmeans", ann_fd=fd, ann_ramp=kmeans_ramp))
+            out["kmeans_runs"].append(run)
+            log(f"paper example N={N}, k-means tree f_d^f {fd}: {run['mean_iterations']} "
+                f"iterations, final distance {run['mean_final_global_distance']:.4g}, "
+                f"{run['mean_solve_ms']} ms (search {run['mean_search_ms']} ms)")
         ds.close()
         torch.cuda.empty_cache()
     return out

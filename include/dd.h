@@ -92,7 +92,12 @@ typedef enum dd_mode {
    * |q - c| - f_d r (with f_d = 1 also its box distance) exceeds the best
    * certified distance so far.  Same certified FP32 arithmetic, FP64 rerank,
    * budget and warm-start rules as DD_ANN; exact with ann_budget = 0 and
-   * f_d = 1 (dd_project_opts.ann_fd = 0 or 1), approximate otherwise. */
+   * f_d = 1 (ann_radius_discount = 0), approximate otherwise.  With f_d < 1
+   * the walk is the search of Section 4.2: siblings nearest centre first, a
+   * child entered while |q - c| - f_d r is below the best distance the walk
+   * has found itself (the first descent reaches a leaf whatever the warm
+   * start); the warm-start point stays a candidate, so the answer is never
+   * farther than it. */
   DD_KMEANS = 6
 } dd_mode;
 
@@ -137,8 +142,10 @@ typedef struct dd_project_opts {
   int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
                                every 64th tile first; 0 = automatic (2 without a warm start) */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
-  double ann_fd;            /* DD_KMEANS: radius factor f_d in (0, 1] of the ball test;
-                               0 = 1 (exact) */
+  double ann_radius_discount;  /* DD_KMEANS: 1 - f_d in [0, 1], the part of a child's radius
+                                  the ball test |q - c| - f_d r leaves out (Section 4.2):
+                                  0 = exact (f_d = 1), 1 = centres only (f_d = 0);
+                                  > 0 with another mode is DD_ERR_ARG */
 } dd_project_opts;
 
 /*
@@ -250,12 +257,20 @@ typedef struct dd_solve_opts {
   int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
   int32_t ann_budget;    /* DD_ANN, DD_KMEANS: leaves per projection (0 = exact walk) */
-  int32_t ann_ramp;      /* DD_ANN, DD_KMEANS with a budget: > 0 = accuracy schedule, iteration i <= ann_ramp
-                            uses ann_budget * i leaves, later iterations walk exactly (the paper's
-                            search accuracy growing over the iterations, Section 4.5) */
+  int32_t ann_ramp;      /* DD_ANN, DD_KMEANS: > 0 = accuracy schedule.  With a budget,
+                            iteration i <= ann_ramp uses ann_budget * i leaves and later
+                            iterations walk exactly; with ann_radius_discount > 0 see there
+                            (the paper's search accuracy growing over the iterations,
+                            Section 4.5) */
   const double* dirichlet_values;  /* host [ndof] or NULL: prescribed displacements at the
                                       Dirichlet DOFs (e.g. the rotated face of Section 3's
                                       example); eta stays homogeneous there */
+  double ann_radius_discount;      /* DD_KMEANS: 1 - f_d^f in [0, 1], the final radius factor of
+                                      the ball test (0 = exact); with ann_ramp > 1, iteration
+                                      i <= ann_ramp uses f_d = f_d^f (i - 1) / (ann_ramp - 1),
+                                      from 0 up to f_d^f (the paper's linear ramp of Section
+                                      4.5), later ones f_d^f; > 0 with another mode is
+                                      DD_ERR_ARG */
 } dd_solve_opts;
 #define DD_SOLVE_NO_GRAPH 0x1
 /* P_C by CG even for meshes of at most 16384 DOFs, where dd_solve otherwise
@@ -291,6 +306,9 @@ typedef struct dd_solve_result {
   double cg_max_residual;   /* out: largest final relative CG residual */
   double elapsed_ms;        /* out: host wall time of the loop */
   int64_t skipped;          /* out: projections skipped as unmoved (exact DD_ANN, DD_KMEANS) */
+  double project_ms;        /* out: GPU time of the P_D steps (HIP events around each), the
+                               paper's search time; dd_server_wait writes 0 (its projections
+                               serve many solves at once) */
 } dd_solve_result;
 
 /*
@@ -299,11 +317,11 @@ typedef struct dd_solve_result {
  * K = A_e{w B^T C B} assembled once, E = A_e{w B^T C eps*},
  * S = f - A_e{w B^T sig*}, eps = B u, sig = sig* + C B eta), then
  * z_{i+1} = P_D(y_i), until no association changes (the stopping rule for
- * exact projections).  With an approximate projection (a walk with a budget,
- * no ramp) the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer
+ * exact projections).  With an approximate projection (a walk with a budget
+ * or f_d < 1) the loop also stops when sum_e w_e dist(y_i, z_{i+1}) no longer
  * decreases, since the alternating-minimisation descent no longer holds
- * (Section 4.1); with an accuracy schedule (ann_ramp) the stopping rules apply
- * once the walk has become exact.  Each projection is warm-started from the
+ * (Section 4.1); with an accuracy schedule (ann_ramp) both stopping rules wait
+ * until the schedule has ended.  Each projection is warm-started from the
  * current association.
  *   mesh            structured box mesh (see dd_mesh)
  *   dirichlet_mask  host uint8 [ndof]: 1 = homogeneous Dirichlet DOF (u = eta = 0)

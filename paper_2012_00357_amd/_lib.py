@@ -55,7 +55,7 @@ class dd_index_info(ctypes.Structure):
 class dd_project_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("splits", ctypes.c_int32), ("ann_budget", ctypes.c_int32),
                 ("passes", ctypes.c_int32), ("stats", ctypes.POINTER(dd_project_stats)),
-                ("ann_fd", ctypes.c_double)]
+                ("ann_radius_discount", ctypes.c_double)]
 
 
 def _load():
@@ -191,7 +191,7 @@ def dd_dataset_destroy(ds: Dataset):
 
 def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: int = 0,
                ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False,
-               passes: int = 0, ann_fd: float = 0.0):
+               passes: int = 0, ann_fd: float | None = None):
     """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats])."""
     import torch
     m = int(states.shape[0])
@@ -207,7 +207,8 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
         pw = _dev_ptr(warm_start_idx, torch.int64, None, "warm_start_idx")
     st = dd_project_stats()
     opts = dd_project_opts(MODES[mode] if isinstance(mode, str) else int(mode), splits, ann_budget,
-                           passes, ctypes.pointer(st) if stats else None, float(ann_fd))
+                           passes, ctypes.pointer(st) if stats else None,
+                           0.0 if ann_fd is None else 1.0 - float(ann_fd))
     _check(_lib.dd_project(ds.handle, ps, m, pw, ctypes.byref(opts), pi, pd, _stream(stream)),
            "dd_project")
     if stats:
@@ -261,7 +262,8 @@ class dd_solve_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("cg_max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("ann_budget", ctypes.c_int32),
-                ("ann_ramp", ctypes.c_int32), ("dirichlet_values", ctypes.c_void_p)]
+                ("ann_ramp", ctypes.c_int32), ("dirichlet_values", ctypes.c_void_p),
+                ("ann_radius_discount", ctypes.c_double)]
 
 
 class dd_solve_result(ctypes.Structure):
@@ -271,7 +273,8 @@ class dd_solve_result(ctypes.Structure):
                 ("history_capacity", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
                 ("cg_iterations", ctypes.c_int64), ("cg_max_residual", ctypes.c_double),
-                ("elapsed_ms", ctypes.c_double), ("skipped", ctypes.c_int64)]
+                ("elapsed_ms", ctypes.c_double), ("skipped", ctypes.c_int64),
+                ("project_ms", ctypes.c_double)]
 
 
 _lib.dd_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_mesh), ctypes.c_void_p, ctypes.c_void_p,
@@ -283,12 +286,13 @@ _lib.dd_solve.restype = ctypes.c_int
 def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp64",
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
              cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, cg: bool = False,
-             ann_ramp: int = 0, skip: bool = False, dirichlet_values=None, stream=None):
+             ann_ramp: int = 0, skip: bool = False, dirichlet_values=None, stream=None,
+             ann_fd: float | None = None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
     (when requested), iterations, converged, cg_iterations, cg_max_residual,
-    elapsed_ms.  Not converging within max_iter is reported, not raised."""
+    elapsed_ms, project_ms.  Not converging within max_iter is reported, not raised."""
     nx, ny, nz = mesh[:3]
     lx, ly, lz = (mesh[3:] if len(mesh) > 3 else (1.0, 1.0, 1.0))
     m = dd_mesh(nx, ny, nz, lx, ly, lz)
@@ -305,13 +309,15 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
     res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
                           out["sig"].ctypes.data, out["d_half"].ctypes.data,
                           out["d_full"].ctypes.data, out["changed"].ctypes.data,
-                          hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0, 0)
+                          hist.ctypes.data if history else None, cap, 0, 0, 0, 0, 0.0, 0.0, 0,
+                          0.0)
     dv = None
     if dirichlet_values is not None:
         dv = np.ascontiguousarray(np.asarray(dirichlet_values, dtype=np.float64).reshape(n_dof))
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
                          cg_max_iter, (0 if graph else 1) | (2 if cg else 0) | (4 if skip else 0),
-                         cg_tol, ann_budget, ann_ramp, dv.ctypes.data if dv is not None else None)
+                         cg_tol, ann_budget, ann_ramp, dv.ctypes.data if dv is not None else None,
+                         0.0 if ann_fd is None else 1.0 - float(ann_fd))
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
                        init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), _stream(stream))
     if st not in (DD_OK, 5):
@@ -323,7 +329,8 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
         out["history"] = hist[:it + 1]
     out.update(iterations=it, converged=bool(res.converged), stop_reason=res.stop_reason,
                skipped=res.skipped, cg_iterations=res.cg_iterations,
-               cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms)
+               cg_max_residual=res.cg_max_residual, elapsed_ms=res.elapsed_ms,
+               project_ms=res.project_ms)
     return out
 
 
@@ -407,7 +414,7 @@ class DDServer:
         res = dd_solve_result(out["u"].ctypes.data, out["idx"].ctypes.data, out["eps"].ctypes.data,
                               out["sig"].ctypes.data, out["d_half"].ctypes.data,
                               out["d_full"].ctypes.data, out["changed"].ctypes.data, None, cap,
-                              0, 0, 0, 0, 0.0, 0.0, 0)
+                              0, 0, 0, 0, 0.0, 0.0, 0, 0.0)
         st = _lib.dd_server_wait(self._h, ticket, ctypes.byref(res), float(timeout_s))
         if st == 9:   # DD_ERR_TIMEOUT: the ticket stays valid
             raise DDError(st, "dd_server_wait", dd_last_error())

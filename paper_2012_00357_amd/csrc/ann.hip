@@ -202,10 +202,13 @@ __device__ inline float box_lb(const float* __restrict__ b, const float yq[12], 
 // k-means tree child record: the ball (centre c, radius r >= max |x - c|)
 // gives |q - c| - f_d r (|q - c| shrunk by the slack that covers the rounding
 // of the query and of this sum), exact for f_d = 1 and the approximate test of
-// Section 4 for f_d < 1; with f_d = 1 the bound is also at least the distance
-// to the record's box in principal-axis coordinates.
+// Section 4.2 for f_d < 1; with f_d = 1 the bound is also at least the
+// distance to the record's box in principal-axis coordinates.  dc receives
+// the shrunk |q - c| (the order in which the approximate search visits
+// siblings).
 __device__ inline float record_lb(const float* __restrict__ rec, const float qf[12],
-                                  const float yq[12], float slack, float fd, uint32_t& code) {
+                                  const float yq[12], float slack, float fd, uint32_t& code,
+                                  float& dc) {
   const float4* m = reinterpret_cast<const float4*>(rec);
   const float4 a = m[0], b = m[1], c = m[2], e = m[3];
   const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
@@ -216,25 +219,30 @@ __device__ inline float record_lb(const float* __restrict__ rec, const float qf[
     s = fmaf(t, t, s);
   }
   code = __builtin_bit_cast(uint32_t, e.y);
-  const float ball = __builtin_sqrtf(s) * kLbShrink - slack - fd * e.x;
+  dc = __builtin_sqrtf(s) * kLbShrink - slack;
+  const float ball = dc - fd * e.x;
   if (fd != 1.0f) return ball;
   return fmaxf(ball, box_lb(rec + 16, yq, slack));
 }
 
-// Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront.
-__device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
+// Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront;
+// AUX: aux travels with its key.
+template <bool AUX>
+__device__ inline void wave_sort64(float& key, uint32_t& val, float& aux, int lane) {
 #pragma unroll
   for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
       const float ok = __shfl_xor(key, j);
       const uint32_t ov = __shfl_xor(val, j);
+      const float oa = AUX ? __shfl_xor(aux, j) : 0.0f;
       const bool up = (lane & k) == 0;
       const bool lower = (lane & j) == 0;
       const bool take = (lower == up) ? (ok < key) : (ok > key);
       if (take) {
         key = ok;
         val = ov;
+        if (AUX) aux = oa;
       }
     }
   }
@@ -245,7 +253,12 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, int lane) {
 // candidates hold every point within the second-smallest distance.
 //
 // KMT: walk the k-means tree instead of the box tree (ball bounds, padded
-// leaf blocks addressed by slot).
+// leaf blocks addressed by slot).  With f_d < 1 the walk is the approximate
+// search of Section 4.2: siblings are visited nearest centre first, a child is
+// entered while |q - c| - f_d r stays below the best distance the walk itself
+// has found (none at the start, so the first descent always reaches a leaf:
+// the warm-start point bounds no branch), and the warm-start point remains a
+// candidate, so the answer is never farther than the previous association.
 template <bool TOP2, bool KMT>
 __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
@@ -288,6 +301,10 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   // smallest over distinct points, U1 tracking the smallest)
   float U = TOP2 ? INFINITY : A.u32[q];
   float U1 = INFINITY;
+  // approximate k-means search: Ua, the best upper bound over the points the
+  // walk has evaluated, decides which branches are entered
+  const bool approx = KMT && A.fd != 1.0f;
+  float Ua = INFINITY;
   int nc = 0;
   bool ovf = false;
 
@@ -316,13 +333,19 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   int sp = 0;
   unsigned long long boxes = 0, leaves = 0, visited = 0, leaf_boxes = 0;
   auto expand = [&](int lv, int64_t c0, int cnt) {
-    float key = INFINITY;
+    float key = INFINITY;     // visiting order
+    float bnd = INFINITY;     // entry test, kept on the stack (the bound itself unless approx)
     uint32_t val = 0;
     if (KMT) {
       // child records [c0, c0 + cnt) of a k-means tree node; val is the code
       if (lane < cnt) {
-        const float lb = record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd, val);
-        if (lb <= U) key = fmaxf(lb, 0.0f);
+        float dc;
+        const float lb =
+            record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd, val, dc);
+        if (lb <= (approx ? Ua : U)) {
+          bnd = fmaxf(lb, 0.0f);
+          key = approx ? fmaxf(dc, 0.0f) : bnd;
+        }
       }
       leaf_boxes += (unsigned long long)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
     } else if (lv == 0 && A.levels >= 2) {
@@ -347,6 +370,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       if (lb <= U) key = fmaxf(lb, 0.0f);
       val = ((uint32_t)lv << 28) | (uint32_t)(c0 + lane);
     }
+    if (!KMT) bnd = key;
     const uint64_t pass = __ballot(key != INFINITY);
     int k = __popcll(pass);
     // depth-first order keeps at most kAnnFan entries per level on the stack;
@@ -365,13 +389,14 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       }
       if (k > 0 && key != INFINITY) {
         s_code[wv][sp + k - 1 - rank] = val;
-        s_lb[wv][sp + k - 1 - rank] = key;
+        s_lb[wv][sp + k - 1 - rank] = bnd;
       }
     } else {
-      wave_sort64(key, val, lane);
+      if (approx) wave_sort64<true>(key, val, bnd, lane);
+      else wave_sort64<false>(key, val, bnd, lane);
       if (lane < k) {
         s_code[wv][sp + k - 1 - lane] = val;
-        s_lb[wv][sp + k - 1 - lane] = key;
+        s_lb[wv][sp + k - 1 - lane] = approx ? bnd : key;
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -405,7 +430,9 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       U1 = lo;
       U = hi;
     } else {
-      U = fminf(U, wave_min_f(v ? s + E : INFINITY));
+      const float mn = wave_min_f(v ? s + E : INFINITY);
+      U = fminf(U, mn);
+      Ua = fminf(Ua, mn);
     }
     const bool keep = v && (s - E <= U);
     const uint64_t km = __ballot(keep);
@@ -457,7 +484,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     const uint32_t code = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_code[wv][sp - 1]);
     const float lb = __builtin_bit_cast(
         float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, s_lb[wv][sp - 1])));
-    if (lb > U) {
+    if (lb > (approx ? Ua : U)) {
       --sp;
       continue;
     }
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
-      if (b < nb && !stop && blb[b] <= U) leaf_step(bidx[b], xr[b]);
+      if (b < nb && !stop && blb[b] <= (approx ? Ua : U)) leaf_step(bidx[b], xr[b]);
     }
   }
 
@@ -571,7 +598,7 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
                           double fd) {
   if (dist2 && (budget != 0 || (kmt && fd != 1.0)))
     return set_error(DD_ERR_ARG, "second distances need the exact walk");
-  if (!(fd > 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "ann_fd must be in (0, 1]");
+  if (!(fd >= 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "f_d must be in [0, 1]");
   if (len_max <= 0) return DD_OK;
   AnnArgs A{};
   if (kmt) {

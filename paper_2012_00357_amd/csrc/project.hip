@@ -128,8 +128,12 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
   const int budget = opts ? opts->ann_budget : 0;
   if (budget < 0) return set_error(DD_ERR_ARG, "ann_budget must be >= 0");
-  const double fd = (opts && opts->ann_fd != 0.0) ? opts->ann_fd : 1.0;
-  if (!(fd > 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "ann_fd must be in (0, 1]");
+  const double discount = opts ? opts->ann_radius_discount : 0.0;
+  if (!(discount >= 0.0 && discount <= 1.0))
+    return set_error(DD_ERR_ARG, "ann_radius_discount must be in [0, 1]");
+  const double fd = 1.0 - discount;
+  if (discount > 0.0 && mode != DD_KMEANS)
+    return set_error(DD_ERR_ARG, "ann_radius_discount applies to the k-means walk only");
   switch (mode) {
     case DD_EXACT_FP64:
     case DD_DIRECT_FP64:
@@ -190,7 +194,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(sc.get(fb, (size_t)m));
     ann = reinterpret_cast<unsigned long long*>(counters + 16);
     DD_TRY(timing.mark(1, st));
-    if (dist2_out_dev && budget != 0)
+    if (dist2_out_dev && (budget != 0 || fd < 1.0))
       return set_error(DD_ERR_ARG, "second distances need the exact walk");
     DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann,
                            dist2_out_dev, st, mode == DD_KMEANS, fd));
@@ -301,10 +305,11 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
 
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
-                           double* dist_out, hipStream_t st, double* dist2_out) {
+                           double* dist_out, hipStream_t st, double* dist2_out, double fd) {
   dd_project_opts o{};
   o.mode = mode;
   o.ann_budget = ann_budget;
+  o.ann_radius_discount = 1.0 - fd;
   return project_impl_ex(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, dist2_out, st);
 }
 

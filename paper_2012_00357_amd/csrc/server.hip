@@ -681,6 +681,7 @@ extern "C" dd_status dd_server_wait(dd_server* h, uint64_t ticket, dd_solve_resu
     res->cg_iterations = j->cg_total;
     res->cg_max_residual = j->cg_res_max;
     res->elapsed_ms = ms_since(j->t_submit, j->t_done);
+    res->project_ms = 0.0;
   }
   if (j->status != DD_OK) return set_error(j->status, j->error);
   return DD_OK;

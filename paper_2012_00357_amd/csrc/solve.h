@@ -20,9 +20,11 @@ struct FEMesh {
 // P_D of whitened states (already in the dataset's coordinates).
 // dist2_out (exact walks only): distance to the second nearest point, -1
 // where not certified.
+// fd: radius factor of the k-means walk's ball test (1 = exact).
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
-                           double* dist_out, hipStream_t st, double* dist2_out = nullptr);
+                           double* dist_out, hipStream_t st, double* dist2_out = nullptr,
+                           double fd = 1.0);
 
 // K^-1 for the mesh and Dirichlet pattern, formed on st from the CSR matrix on
 // first use and cached on the dataset.
@@ -73,12 +75,23 @@ class DDSolver {
   int mode = DD_EXACT_FP64;
   int ann_budget = 0;
   int ann_ramp = 0;
+  double ann_fd = 1.0;   // final radius factor of the k-means walk (1 = exact)
   // leaves per projection at DD iteration it (1-based); 0 = exact
   int budget_at(int it) const {
     if (!walk_mode(mode) || ann_budget <= 0) return 0;
     if (ann_ramp <= 0) return ann_budget;
     return it <= ann_ramp ? ann_budget * it : 0;
   }
+  // radius factor of the k-means walk at DD iteration it: the linear ramp to
+  // the final factor over the first ann_ramp iterations, then the final one
+  // (iteration 1 uses f_d = 0, iteration ann_ramp the final factor)
+  double fd_at(int it) const {
+    if (mode != DD_KMEANS || ann_fd >= 1.0) return 1.0;
+    if (ann_ramp <= 1 || it >= ann_ramp) return ann_fd;
+    return ann_fd * (double)(it - 1) / (double)(ann_ramp - 1);
+  }
+  // iteration it projects approximately
+  bool approximate_at(int it) const { return budget_at(it) > 0 || fd_at(it) < 1.0; }
   double cg_tol = 1e-13;
   int cg_max_iter = 20000;
   int64_t nnz = 0;

@@ -627,6 +627,14 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   ann_ramp = opts ? opts->ann_ramp : 0;
   if (ann_budget < 0 || ann_ramp < 0)
     return set_error(DD_ERR_ARG, "dd_solve_opts: ann_budget and ann_ramp must be >= 0");
+  {
+    const double discount = opts ? opts->ann_radius_discount : 0.0;
+    if (!(discount >= 0.0 && discount <= 1.0))
+      return set_error(DD_ERR_ARG, "dd_solve_opts: ann_radius_discount must be in [0, 1]");
+    if (discount > 0.0 && mode != DD_KMEANS)
+      return set_error(DD_ERR_ARG, "dd_solve_opts: ann_radius_discount applies to DD_KMEANS only");
+    ann_fd = 1.0 - discount;
+  }
   use_graph = !(opts && (opts->flags & DD_SOLVE_NO_GRAPH));
   cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
   cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
@@ -749,7 +757,8 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   if (want_dense && !dense)
     DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
                              d_val.as<double>(), dense, st));
-  skip_on = (walk_mode(mode) && ann_budget == 0 && opts && (opts->flags & DD_SOLVE_SKIP));
+  skip_on = (walk_mode(mode) && ann_budget == 0 && fd_at(1) >= 1.0 && opts &&
+             (opts->flags & DD_SOLVE_SKIP));
   if (skip_on) {
     DD_TRY(d_qref.alloc(sizeof(double) * 12 * nm));
     DD_TRY(d_gap.alloc(sizeof(double) * nm));
@@ -771,7 +780,7 @@ dd_status DDSolver::project_step(int it) {
   const int64_t nm = M.n_mp;
   if (!skip_on)
     return project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, budget_at(it),
-                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st);
+                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st, nullptr, fd_at(it));
   DD_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int), st));
   hipLaunchKernelGGL(skip_kernel, dim3(g256(nm)), dim3(256), 0, st, nm, d_yw.as<double>(),
                      d_qref.as<double>(), d_gap.as<double>(), d_idx.as<int64_t>(),
@@ -1067,6 +1076,21 @@ dd_status DDSolver::fetch_results(double* u, int64_t* idx, double* eps, double* 
   return DD_OK;
 }
 
+namespace {
+// two timing events, destroyed with the scope
+struct StepEvents {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  dd_status init() {
+    for (auto& x : e) DD_HIP(hipEventCreate(&x));
+    return DD_OK;
+  }
+  ~StepEvents() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+}  // namespace
+
 dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   const int64_t nm = M.n_mp, nd = M.n_dof;
   auto t0 = std::chrono::steady_clock::now();
@@ -1074,15 +1098,19 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   bool converged = false;
   int stop_reason = 0;
   double prev_full = INFINITY;
-  const bool approximate = (walk_mode(mode) && ann_budget > 0);
   int64_t cg_total = 0;
   double cg_res_max = 0.0;
+  double project_ms = 0.0;
+  StepEvents ev;
+  DD_TRY(ev.init());
   if (res && res->history) {
     DD_HIP(hipMemcpyAsync(res->history, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
   }
   for (it = 1; it <= max_iter; ++it) {
     DD_TRY(constraint_projection());
+    DD_HIP(hipEventRecord(ev.e[0], st));
     DD_TRY(project_step(it));
+    DD_HIP(hipEventRecord(ev.e[1], st));
     hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
                        d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
                        d_idx.as<int64_t>(), d_scal.as<double>());
@@ -1095,6 +1123,9 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
       DD_HIP(hipMemcpyAsync(res->history + (int64_t)it * nm, d_idx_new.p, sizeof(int64_t) * nm,
                             hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
+    float pms = 0.f;
+    DD_HIP(hipEventElapsedTime(&pms, ev.e[0], ev.e[1]));
+    project_ms += pms;
     int cg_it[2] = {cg_last_iters[0], cg_last_iters[1]};
     double cg_res[2] = {cg_last_res[0], cg_last_res[1]};
     int bad = 0;
@@ -1109,8 +1140,9 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     }
     // the new association becomes the current one
     std::swap(d_idx.p, d_idx_new.p);
-    // under an accuracy schedule the stopping rules wait for the exact walk
-    const bool scheduled = approximate && ann_ramp > 0 && it <= ann_ramp;
+    // under an accuracy schedule the stopping rules wait for its end
+    const bool approximate = approximate_at(it);
+    const bool scheduled = ann_ramp > 0 && it <= ann_ramp && approximate_at(1);
     if (sc[2] == 0.0 && !scheduled) {
       converged = true;
       stop_reason = 1;
@@ -1118,7 +1150,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     }
     // an approximate projection gives no descent guarantee: stop once the
     // distance to the data stops decreasing
-    if (approximate && ann_ramp == 0 && it > 1 && !(sc[1] < prev_full)) {
+    if (approximate && !scheduled && it > 1 && !(sc[1] < prev_full)) {
       stop_reason = 2;
       break;
     }
@@ -1132,6 +1164,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     res->skipped = skipped_total;
     res->cg_iterations = cg_total;
     res->cg_max_residual = cg_res_max;
+    res->project_ms = project_ms;
     DD_TRY(fetch_results(res->u, res->idx, res->eps, res->sig));
     res->elapsed_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -105,7 +105,8 @@ def test_kmeans_budget_and_fd_are_approximate_within_bounds(L, config0, C0):
     rng = np.random.default_rng(15)
     warm = rng.integers(0, 65536, 4096).astype(np.int64)
     wd = oracle.pair_dist_raw(st_np[:, :6], st_np[:, 6:], config0["e"][warm], config0["s"][warm], C0)
-    for budget, fd in ((1, 1.0), (4, 1.0), (64, 1.0), (0, 0.25), (0, 0.5), (0, 0.8), (4, 0.5)):
+    for budget, fd in ((1, 1.0), (4, 1.0), (64, 1.0), (0, 0.0), (0, 0.25), (0, 0.5), (0, 0.8),
+                       (4, 0.5)):
         idx, dist, st = L.dd_project(ds, states, warm_start_idx=to_dev(warm), mode="kmeans",
                                      ann_budget=budget, ann_fd=fd, stats=True)
         idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
@@ -175,6 +176,43 @@ def test_dd_solve_kmeans_equals_fp64_trajectory(L, C0, n):
         assert np.array_equal(a["history"], r["history"])
         assert np.array_equal(a["u"], r["u"])
         assert np.array_equal(a["d_full"], r["d_full"])
+
+
+def test_dd_solve_kmeans_fd_schedule(L, C0):
+    """The f_d schedule of Section 4.5 in dd_solve: with f_d^f = 1 the ramp
+    changes nothing (the exact trajectory); with f_d^f < 1 no stopping rule
+    fires before the ramp ends, and every point of the last projection lies
+    between its exact nearest neighbour and its previous association.  f_d
+    with another projection mode is refused."""
+    n = 4
+    e, s = ddsynth.data_points(200000, 1011)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | KMEANS)
+    mask, force = ddsynth.box_bc(n, 100.0)
+    init = ddsynth.indices(8 * n ** 3, 200000, 12)
+    exact = L.dd_solve(ds, (n, n, n), mask, force, init, mode="kmeans", history=True)
+    same = L.dd_solve(ds, (n, n, n), mask, force, init, mode="kmeans", history=True,
+                      ann_fd=1.0, ann_ramp=6)
+    assert np.array_equal(exact["history"], same["history"])
+    assert same["project_ms"] > 0
+    for fd, ramp in ((0.0, 0), (0.0, 6), (0.4, 6), (0.8, 3)):
+        r = L.dd_solve(ds, (n, n, n), mask, force, init, mode="kmeans", history=True,
+                       ann_fd=fd, ann_ramp=ramp)
+        k = r["iterations"]
+        _say(f"f_d^f {fd}, ramp {ramp}: {k} iterations (stop {r['stop_reason']}), final "
+             f"distance {r['d_full'][-1]:.6g} (exact walk {exact['d_full'][-1]:.6g}), "
+             f"search {r['project_ms']:.2f} ms")
+        assert r["stop_reason"] in (1, 2)
+        assert k >= ramp
+        hist = r["history"]
+        assert hist.min() >= 0 and hist.max() < 200000
+        got = oracle.pair_dist_raw(r["eps"], r["sig"], e[hist[k]], s[hist[k]], C0)
+        prev = oracle.pair_dist_raw(r["eps"], r["sig"], e[hist[k - 1]], s[hist[k - 1]], C0)
+        _, od, _ = oracle.pd_raw(e, s, C0, r["eps"], r["sig"])
+        assert np.all(got >= od * (1 - 1e-12))
+        assert np.all(got <= prev * (1 + 1e-12))
+    with pytest.raises(L.DDError) as ex:
+        L.dd_solve(ds, (n, n, n), mask, force, init, mode="fp64", ann_fd=0.5)
+    assert ex.value.status == 1
 
 
 def test_server_kmeans_mode(L, C0):
