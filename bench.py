@@ -109,7 +109,8 @@ ANN_BYTES_PER_POINT = 24.0    # FP16 scaled offsets (12) read per visited point
 ANN_BYTES_PER_LEAF = 64.0     # leaf centre, radius (FP32) read per visited leaf
 ANN_BYTES_PER_LEAF_BOX = 24.0  # quantised leaf box (lo[12], hi[12] as bytes) per test
 ANN_BYTES_PER_BOX = 96.0      # FP32 box (lo[12], hi[12]) read per test of a higher box
-KMT_BYTES_PER_RECORD = 160.0  # k-means tree child record (centre, radius, code, box) per test
+KMT_BYTES_PER_RECORD = 80.0   # k-means tree child record (centre, radius, code, byte box) per test
+KMT_BYTES_PER_NODE = 96.0     # FP32 box of an expanded k-means tree node (decodes its children)
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 
 
@@ -141,7 +142,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
            "dataset_gb": round(ds.info()[1] / 1e9, 2), "index": L.dd_dataset_index_info(ds)}
 
     def run(warm, budget, fd=None):
-        walk, tot, vis, box, lvs, lbox, ovf = [], [], 0, 0, 0, 0, 0
+        walk, tot, vis, box, lvs, lbox, nds, ovf = [], [], 0, 0, 0, 0, 0, 0
         L.dd_project(ds, states, warm_start_idx=warm, mode=index, ann_budget=budget, ann_fd=fd)
         for _ in range(steps):
             i, d, st = L.dd_project(ds, states, warm_start_idx=warm, mode=index,
@@ -152,11 +153,12 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
             box += st["boxes"]
             lvs += st["leaves"]
             lbox += st["leaf_boxes"]
+            nds += st["nodes"]
             ovf += st["overflowed"]
         w, tt = sum(walk) / steps, sum(tot) / steps
         if kmt:
             byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
-                    + KMT_BYTES_PER_RECORD * box) / steps
+                    + KMT_BYTES_PER_RECORD * box + KMT_BYTES_PER_NODE * nds) / steps
         else:
             byts = (ANN_BYTES_PER_POINT * vis + ANN_BYTES_PER_LEAF * lvs
                     + ANN_BYTES_PER_LEAF_BOX * lbox + ANN_BYTES_PER_BOX * (box - lbox)) / steps
@@ -166,6 +168,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
                       "boxes_per_query": round(box / steps / m, 1),
                       "leaves_per_query": round(lvs / steps / m, 1),
                       "leaf_boxes_per_query": round(lbox / steps / m, 1),
+                      "nodes_per_query": round(nds / steps / m, 1),
                       "fallback_queries": ovf // steps,
                       "algorithmic_bytes_per_launch": round(byts), "achieved_gbs": round(byts / w / 1e6, 1)}
 
@@ -181,6 +184,7 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
                        "bytes_per_point": ANN_BYTES_PER_POINT, "bytes_per_leaf": ANN_BYTES_PER_LEAF}
     if kmt:
         out["roofline"]["bytes_per_record"] = KMT_BYTES_PER_RECORD
+        out["roofline"]["bytes_per_node"] = KMT_BYTES_PER_NODE
     else:
         out["roofline"]["bytes_per_leaf_box"] = ANN_BYTES_PER_LEAF_BOX
         out["roofline"]["bytes_per_box"] = ANN_BYTES_PER_BOX

@@ -132,6 +132,8 @@ typedef struct dd_project_stats {
   int64_t leaf_boxes;       /* DD_ANN: of the boxes tested, leaf boxes (read quantised, 24 bytes;
                                the others are 96-byte FP32 boxes); DD_KMEANS: of the balls
                                tested, leaf balls */
+  int64_t nodes;            /* DD_KMEANS: stored nodes expanded (each reads its 96-byte box, in
+                               which its children's boxes are quantised); DD_ANN: 0 */
 } dd_project_stats;
 
 typedef struct dd_project_opts {

@@ -43,7 +43,7 @@ class dd_project_stats(ctypes.Structure):
                 ("visited", ctypes.c_int64), ("scan_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("slow_tiles", ctypes.c_int64),
                 ("boxes", ctypes.c_int64), ("leaves", ctypes.c_int64),
-                ("leaf_boxes", ctypes.c_int64)]
+                ("leaf_boxes", ctypes.c_int64), ("nodes", ctypes.c_int64)]
 
 
 class dd_index_info(ctypes.Structure):
@@ -216,7 +216,7 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
                                    "visited": st.visited, "scan_ms": st.scan_ms,
                                    "total_ms": st.total_ms, "slow_tiles": st.slow_tiles,
                                    "boxes": st.boxes, "leaves": st.leaves,
-                                   "leaf_boxes": st.leaf_boxes}
+                                   "leaf_boxes": st.leaf_boxes, "nodes": st.nodes}
     return idx_out, dist_out
 
 

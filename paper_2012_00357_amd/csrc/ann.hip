@@ -71,6 +71,7 @@ struct AnnArgs {
   Outputs out;
   // k-means tree (KMT): nodes, child records, slot <-> sorted position, f_d
   const int2* kmt_node;
+  const float* kmt_nbox;
   const float* kmt_child;
   const uint32_t* slot_pos;
   const uint32_t* pos_slot;
@@ -78,8 +79,9 @@ struct AnnArgs {
   double* dist2;                  // TOP2: distance to the second nearest point (1/2 d^2)
   int* fb_list;
   int* fb_count;
-  // kCounterSlots slots of 8: [0] points visited, [1] boxes tested, [2] leaves,
-  // [3] candidates, [4] leaf boxes tested; block b adds into slot b % kCounterSlots
+  // kCounterSlots slots, kCounterStride u64 apart: [0] points visited, [1] boxes
+  // tested, [2] leaves, [3] candidates, [4] leaf boxes tested, [5] nodes
+  // expanded (k-means tree); block b adds into slot b % kCounterSlots
   // (one cache line each, so the per-wave atomics do not all meet on one line)
   unsigned long long* counters;
 };
@@ -160,15 +162,12 @@ __device__ inline float leaf_point_dist_r(const uint2 (&xr)[3], const float qs[1
   return r * __builtin_sqrtf(d);
 }
 
-// Lower bound from a leaf box quantised inside its parent box (plo, step),
-// decoded outward by delta, which exceeds the FP32 rounding of the decoding.
-__device__ inline float qbox_lb(const uint8_t* __restrict__ q, const float plo[12],
-                                const float step[12], float delta, const float yq[12],
-                                float slack) {
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(q);
-  uint32_t v[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) v[i] = w[i];
+// Lower bound from a box quantised inside its parent box (plo, step), given as
+// its 24 bytes (lo[12], hi[12]) in six words, decoded outward by delta, which
+// exceeds the FP32 rounding of the decoding.
+__device__ __attribute__((always_inline)) inline float qbox_lb_words(const uint32_t (&v)[6], const float plo[12],
+                                      const float step[12], float delta, const float yq[12],
+                                      float slack) {
   float s = 0.0f;
 #pragma unroll
   for (int a = 0; a < 12; ++a) {
@@ -180,6 +179,35 @@ __device__ inline float qbox_lb(const uint8_t* __restrict__ q, const float plo[1
     s = fmaf(g, g, s);
   }
   return __builtin_sqrtf(s) * kLbShrink - slack;
+}
+
+// The same with the parent box given by its corners (the step formed at use,
+// so that only the corners stay live; uniform, they can sit in scalar registers).
+__device__ __attribute__((always_inline)) inline float qbox_lb_corners(
+    const uint32_t (&v)[6], const float plo[12], const float phi[12], float delta,
+    const float yq[12], float slack) {
+  float s = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 12; ++a) {
+    const float step = (phi[a] - plo[a]) * (1.0f / 255.0f);
+    const float ql = (float)((v[a >> 2] >> (8 * (a & 3))) & 0xFFu);
+    const float qh = (float)((v[3 + (a >> 2)] >> (8 * (a & 3))) & 0xFFu);
+    const float lo = fmaf(ql, step, plo[a]) - delta;
+    const float hi = fmaf(qh, step, plo[a]) + delta;
+    const float g = fmaxf(fmaxf(lo - yq[a], yq[a] - hi), 0.0f);
+    s = fmaf(g, g, s);
+  }
+  return __builtin_sqrtf(s) * kLbShrink - slack;
+}
+
+__device__ inline float qbox_lb(const uint8_t* __restrict__ q, const float plo[12],
+                                const float step[12], float delta, const float yq[12],
+                                float slack) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(q);
+  uint32_t v[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = w[i];
+  return qbox_lb_words(v, plo, step, delta, yq, slack);
 }
 
 // Lower bound of the whitened distance from the query to box b, minus the slack
@@ -203,12 +231,12 @@ __device__ inline float box_lb(const float* __restrict__ b, const float yq[12], 
 // gives |q - c| - f_d r (|q - c| shrunk by the slack that covers the rounding
 // of the query and of this sum), exact for f_d = 1 and the approximate test of
 // Section 4.2 for f_d < 1; with f_d = 1 the bound is also at least the
-// distance to the record's box in principal-axis coordinates.  dc receives
-// the shrunk |q - c| (the order in which the approximate search visits
-// siblings).
-__device__ inline float record_lb(const float* __restrict__ rec, const float qf[12],
-                                  const float yq[12], float slack, float fd, uint32_t& code,
-                                  float& dc) {
+// distance to the record's box in principal-axis coordinates (quantised inside
+// the owner node's box plo, phi; decoding margin delta).  dc receives the
+// shrunk |q - c| (the order in which the approximate search visits siblings).
+__device__ __attribute__((always_inline)) inline float record_lb(
+    const float* __restrict__ rec, const float qf[12], const float yq[12], float slack, float fd,
+    const float plo[12], const float phi[12], float delta, uint32_t& code, float& dc) {
   const float4* m = reinterpret_cast<const float4*>(rec);
   const float4 a = m[0], b = m[1], c = m[2], e = m[3];
   const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
@@ -222,7 +250,11 @@ __device__ inline float record_lb(const float* __restrict__ rec, const float qf[
   dc = __builtin_sqrtf(s) * kLbShrink - slack;
   const float ball = dc - fd * e.x;
   if (fd != 1.0f) return ball;
-  return fmaxf(ball, box_lb(rec + 16, yq, slack));
+  const float4 f = m[4];
+  const uint32_t v[6] = {__builtin_bit_cast(uint32_t, e.z), __builtin_bit_cast(uint32_t, e.w),
+                         __builtin_bit_cast(uint32_t, f.x), __builtin_bit_cast(uint32_t, f.y),
+                         __builtin_bit_cast(uint32_t, f.z), __builtin_bit_cast(uint32_t, f.w)};
+  return fmaxf(ball, qbox_lb_corners(v, plo, phi, delta, yq, slack));
 }
 
 // Ascending bitonic sort of (key, val) across the 64 lanes of a wavefront;
@@ -332,16 +364,27 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   // farthest first (so the nearest is on top of the stack)
   int sp = 0;
   unsigned long long boxes = 0, leaves = 0, visited = 0, leaf_boxes = 0;
-  auto expand = [&](int lv, int64_t c0, int cnt) {
+  uint32_t nodes = 0;
+  auto expand = [&](int lv, int64_t c0, int cnt, uint32_t node) {
     float key = INFINITY;     // visiting order
     float bnd = INFINITY;     // entry test, kept on the stack (the bound itself unless approx)
     uint32_t val = 0;
     if (KMT) {
-      // child records [c0, c0 + cnt) of a k-means tree node; val is the code
+      // child records [c0, c0 + cnt) of k-means tree node `node`; their boxes
+      // are quantised inside the node's box; val is the code
+      float plo[12], phi[12], amax = 0.0f;
+      const float* pb = A.kmt_nbox + 24 * (int64_t)node;
+#pragma unroll
+      for (int a = 0; a < 12; ++a) {
+        plo[a] = approx ? 0.0f : pb[a];
+        phi[a] = approx ? 0.0f : pb[12 + a];
+        amax = fmaxf(amax, fabsf(plo[a]) + fabsf(phi[a]));
+      }
+      const float delta = kEps20 * amax + 1e-30f;
       if (lane < cnt) {
         float dc;
-        const float lb =
-            record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd, val, dc);
+        const float lb = record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd,
+                                   plo, phi, delta, val, dc);
         if (lb <= (approx ? Ua : U)) {
           bnd = fmaxf(lb, 0.0f);
           key = approx ? fmaxf(dc, 0.0f) : bnd;
@@ -473,12 +516,13 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     if (A.budget > 0 && leaves >= (unsigned long long)A.budget) stop = true;
   };
 
-  auto expand_node = [&](uint32_t node) {
+  auto expand_node = [&](uint32_t node) __attribute__((always_inline)) {
+    ++nodes;
     const int2 r = A.kmt_node[node];
-    expand(1, r.x, r.y - r.x);
+    expand(1, r.x, r.y - r.x, node);
   };
   if (KMT) expand_node(0);
-  else expand(A.levels - 1, 0, (int)A.n[A.levels - 1]);
+  else expand(A.levels - 1, 0, (int)A.n[A.levels - 1], 0);
   while (sp > 0 && !ovf && !stop) {
     // stack entries are the same in every lane: keep them in scalar registers
     const uint32_t code = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_code[wv][sp - 1]);
@@ -496,7 +540,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       } else {
         const int64_t c0 = (int64_t)(code & 0x0FFFFFFFu) * kAnnFan;
         const int cnt = (int)min((int64_t)kAnnFan, A.n[lv - 1] - c0);
-        expand(lv - 1, c0, cnt);
+        expand(lv - 1, c0, cnt, 0);
       }
       continue;
     }
@@ -535,11 +579,12 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   }
 
   if (lane == 0) {
-    unsigned long long* c = A.counters + 8 * (blockIdx.x % kCounterSlots);
+    unsigned long long* c = A.counters + kCounterStride * (blockIdx.x % kCounterSlots);
     atomicAdd(c + 0, visited);
     atomicAdd(c + 1, boxes);
     atomicAdd(c + 2, leaves);
     atomicAdd(c + 4, leaf_boxes);
+    if (KMT) atomicAdd(c + 5, (unsigned long long)nodes);
   }
   if (ovf) {
     if (lane == 0) {
@@ -566,7 +611,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   }
   const uint64_t mine_mask = __ballot(mine);
   if (lane == 0)
-    atomicAdd(A.counters + 8 * (blockIdx.x % kCounterSlots) + 3,
+    atomicAdd(A.counters + kCounterStride * (blockIdx.x % kCounterSlots) + 3,
               (unsigned long long)__popcll(mine_mask));
   const double dm = d;
   const uint32_t om = o;
@@ -606,6 +651,7 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
     A.meta = D.kmt_meta.as<float>();
     A.h16 = D.kmt_h16.as<uint16_t>();
     A.kmt_node = D.kmt_node.as<int2>();
+    A.kmt_nbox = D.kmt_nbox.as<float>();
     A.kmt_child = D.kmt_child.as<float>();
     A.slot_pos = D.kmt_pos.as<uint32_t>();
     A.pos_slot = D.kmt_slot.as<uint32_t>();

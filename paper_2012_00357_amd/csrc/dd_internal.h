@@ -71,8 +71,9 @@ constexpr int kDim = 12;           // phase-space dimension 2M (M = 6 Voigt comp
 constexpr int kKeyAxes = 6;        // principal axes used for the spatial order
 constexpr int kAnnLeaf = 64;       // points per ANN leaf (one wavefront)
 constexpr int kAnnFan = 64;        // children per ANN tree node (one wavefront)
-constexpr int kCounterSlots = 8;   // ANN walk statistics: slots of 8 u64, one per cache line
-constexpr int kKmtRecord = 40;     // floats per k-means tree child record (160 B)
+constexpr int kCounterSlots = 32;  // ANN walk statistics: slots, each on its own 128-byte line
+constexpr int kCounterStride = 16; // u64 per slot (8 used)
+constexpr int kKmtRecord = 20;     // floats per k-means tree child record (80 B)
 
 // projection modes that walk a tree (warm starts, budgets, skipping)
 inline bool walk_mode(int mode) { return mode == DD_ANN || mode == DD_KMEANS; }
@@ -139,12 +140,15 @@ struct Dataset {
   // k-means tree (DD_PACK_KMEANS): recursive 4-means, stored as a 64-ary cut,
   // each stored node with up to 64 child records (ball of the child's points:
   // FP32 centre c, radius >= max |x - c|; their box in principal-axis
-  // coordinates; code (1 << 28 | node) or leaf); leaves of at most 64 points in
-  // padded 64-slot blocks, compact as above
+  // coordinates, quantised to bytes inside the node's own box; code
+  // (1 << 28 | node) or leaf); leaves of at most 64 points in padded 64-slot
+  // blocks, compact as above
   int64_t kmt_nodes = 0, kmt_leaves = 0, kmt_records = 0;
   int kmt_rounds = 0;
-  DevBuf kmt_node;   // int2 [nodes]: first child record, child count (node 0: root)
-  DevBuf kmt_child;  // float [records][kKmtRecord]: c[12], r, code (bits), 0, 0, box lo[12], hi[12]
+  DevBuf kmt_node;   // int2 [nodes]: first child record, end of its records (node 0: root)
+  DevBuf kmt_nbox;   // float [nodes][24]: box lo[12], hi[12] of the node's points (rounded outward)
+  DevBuf kmt_child;  // float [records][kKmtRecord]: c[12], r, code (bits), box lo[12], hi[12] as
+                     // bytes inside the owner node's box (lo rounded down, hi up)
   DevBuf kmt_meta;   // float [leaves][16]: c[12], r, 1/r, count (bits), 0
   DevBuf kmt_h16;    // uint16 [leaves*64][12]; empty slots +inf
   DevBuf kmt_pos;    // uint32 [leaves*64]: sorted position of each slot (empty: 0xFFFFFFFF)

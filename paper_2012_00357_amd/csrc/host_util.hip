@@ -124,7 +124,7 @@ int64_t Dataset::device_bytes() const {
                         centre.bytes + radius.bytes + wbf16.bytes + wfp16.bytes);
   for (int l = 0; l < kAnnMaxLevels; ++l) b += (int64_t)ann_box[l].bytes;
   b += (int64_t)(ann_meta.bytes + ann_q0.bytes + ann_h16.bytes);
-  b += (int64_t)(kmt_node.bytes + kmt_child.bytes + kmt_meta.bytes + kmt_h16.bytes +
+  b += (int64_t)(kmt_node.bytes + kmt_nbox.bytes + kmt_child.bytes + kmt_meta.bytes + kmt_h16.bytes +
                  kmt_pos.bytes + kmt_slot.bytes);
   return b;
 }

@@ -43,6 +43,9 @@ constexpr int kWavesPerBlock = kThreads / 64;
 constexpr int kFan = 64;              // children per stored node
 constexpr int kMaxRounds = 200;
 constexpr int kAcc = kK * 13;         // fixed-point sums (12) and count per child
+// build-time child record (floats): c[12], r, code (bits), 0, 0, box lo[12],
+// hi[12] in FP32; the walk's records (kKmtRecord) carry the box as bytes
+constexpr int kKmtBuild = 40;
 
 struct Axes {                         // principal axes: V[12 k + a] = component k of axis a
   double V[144];
@@ -475,7 +478,7 @@ __global__ void node_record_kernel(Segs G, int64_t S, const unsigned long long* 
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S || !store_f[s]) return;
   const int64_t at = rec_base + store_at[s];
-  float* r = rec + kKmtRecord * at;
+  float* r = rec + kKmtBuild * at;
   for (int a = 0; a < 12; ++a) {
     r[16 + a] = fkey_inv(kblo[12 * s + a]);
     r[28 + a] = fkey_inv(kbhi[12 * s + a]);
@@ -546,7 +549,7 @@ __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ 
   if (v) pos_slot[id] = (uint32_t)slot;
   if (lane == 0) {
     float* m = meta + 16 * leaf;
-    float* q = rec + kKmtRecord * (rec_base + leaf);
+    float* q = rec + kKmtBuild * (rec_base + leaf);
     for (int a = 0; a < 12; ++a) {
       m[a] = c[a];
       q[a] = c[a];
@@ -570,8 +573,63 @@ __global__ __launch_bounds__(256) void leaf_kernel(const uint32_t* __restrict__ 
 __global__ void gather_records_kernel(const float* __restrict__ rec, const uint32_t* __restrict__ order,
                                       int64_t n, float* __restrict__ child) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kKmtRecord * n) return;
-  child[i] = rec[kKmtRecord * (int64_t)order[i / kKmtRecord] + (i % kKmtRecord)];
+  if (i >= kKmtBuild * n) return;
+  child[i] = rec[kKmtBuild * (int64_t)order[i / kKmtBuild] + (i % kKmtBuild)];
+}
+
+// Box of each stored node: the union of its child records' boxes (exact in
+// FP32: the children's bounds are already rounded outward).
+__global__ void node_box_kernel(const float* __restrict__ child, const int2* __restrict__ node,
+                                int64_t n_nodes, float* __restrict__ nbox) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_nodes) return;
+  float lo[12], hi[12];
+  for (int a = 0; a < 12; ++a) {
+    lo[a] = INFINITY;
+    hi[a] = -INFINITY;
+  }
+  const int2 r = node[o];
+  for (int64_t i = r.x; i < r.y; ++i) {
+    const float* c = child + kKmtBuild * i;
+    for (int a = 0; a < 12; ++a) {
+      lo[a] = fminf(lo[a], c[16 + a]);
+      hi[a] = fmaxf(hi[a], c[28 + a]);
+    }
+  }
+  for (int a = 0; a < 12; ++a) {
+    nbox[24 * o + a] = lo[a];
+    nbox[24 * o + 12 + a] = hi[a];
+  }
+}
+
+// Walk records: centre, radius and code as built; the box quantised to bytes
+// inside the owner node's box (lo rounded down, hi up, in FP64 from the FP32
+// bounds), read back with the owner's box and an outward decoding margin.
+__global__ void compress_records_kernel(const float* __restrict__ child,
+                                        const uint32_t* __restrict__ owner, int64_t n,
+                                        const float* __restrict__ nbox, float* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* c = child + kKmtBuild * i;
+  float* q = rec + kKmtRecord * i;
+  for (int a = 0; a < 14; ++a) q[a] = c[a];
+  const float* p = nbox + 24 * (int64_t)owner[i];
+  uint8_t b[24];
+  for (int a = 0; a < 12; ++a) {
+    const double plo = p[a], ext = (double)p[12 + a] - plo;
+    int ql = 0, qh = 255;
+    if (ext > 0.0) {
+      ql = (int)floor(((double)c[16 + a] - plo) / ext * 255.0);
+      qh = (int)ceil(((double)c[28 + a] - plo) / ext * 255.0);
+      ql = ql < 0 ? 0 : (ql > 255 ? 255 : ql);
+      qh = qh < 0 ? 0 : (qh > 255 ? 255 : qh);
+    }
+    b[a] = (uint8_t)ql;
+    b[12 + a] = (uint8_t)qh;
+  }
+  for (int w = 0; w < 6; ++w)
+    q[14 + w] = __uint_as_float((uint32_t)b[4 * w] | ((uint32_t)b[4 * w + 1] << 8) |
+                                ((uint32_t)b[4 * w + 2] << 16) | ((uint32_t)b[4 * w + 3] << 24));
 }
 
 // node[o] = (first record, end) of owner o's run in the owner-sorted records.
@@ -781,7 +839,7 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
       hipLaunchKernelGGL(node_stats_kernel, dim3(n_chunks), dim3(kThreads), 0, st, ids_in, w64, G,
                          S, cbase, store_f.as<uint32_t>(), R, rad_b.as<unsigned long long>(),
                          kblo.as<uint32_t>(), kbhi.as<uint32_t>());
-      DD_TRY(grow(recs, 4 * kKmtRecord * (size_t)(n_rec + n_store), st));
+      DD_TRY(grow(recs, 4 * kKmtBuild * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(rec_owner, 4 * (size_t)(n_rec + n_store), st));
       DD_TRY(grow(frontier, 4 * (size_t)(n_nodes + n_store), st));
       hipLaunchKernelGGL(node_record_kernel, dim3(grid_of(S, 256)), dim3(256), 0, st, G, S,
@@ -865,7 +923,7 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
   DD_TRY(D.kmt_h16.alloc(2 * 12 * kAnnLeaf * (size_t)n_leaf));
   DD_TRY(D.kmt_pos.alloc(4 * kAnnLeaf * (size_t)n_leaf));
   DD_TRY(D.kmt_slot.alloc(4 * (size_t)N));
-  DD_TRY(grow(recs, 4 * kKmtRecord * (size_t)(n_rec + n_leaf), st));
+  DD_TRY(grow(recs, 4 * kKmtBuild * (size_t)(n_rec + n_leaf), st));
   DD_TRY(grow(rec_owner, 4 * (size_t)(n_rec + n_leaf), st));
   hipLaunchKernelGGL(leaf_kernel, dim3(grid_of(n_leaf, 4)), dim3(256), 0, st,
                      ids[cur].as<uint32_t>(), D.w64.as<double>(), R, leaves_b.as<LeafRec>(), n_leaf,
@@ -881,13 +939,21 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
   int bits = 1;
   while (bits < 32 && (1ll << bits) < n_nodes) ++bits;
   DD_TRY(radix_sort_pairs(rec_owner.as<uint32_t>(), order.as<uint32_t>(), n_rec, bits, st));
-  DD_TRY(D.kmt_child.alloc(4 * kKmtRecord * (size_t)n_rec));
-  hipLaunchKernelGGL(gather_records_kernel, dim3(grid_of(kKmtRecord * n_rec, 256)), dim3(256), 0, st,
-                     recs.as<float>(), order.as<uint32_t>(), n_rec, D.kmt_child.as<float>());
+  DevBuf full;
+  DD_TRY(full.alloc(4 * kKmtBuild * (size_t)n_rec));
+  hipLaunchKernelGGL(gather_records_kernel, dim3(grid_of(kKmtBuild * n_rec, 256)), dim3(256), 0, st,
+                     recs.as<float>(), order.as<uint32_t>(), n_rec, full.as<float>());
   DD_TRY(D.kmt_node.alloc(8 * (size_t)n_nodes));
   DD_HIP(hipMemsetAsync(D.kmt_node.p, 0, D.kmt_node.bytes, st));
   hipLaunchKernelGGL(node_range_kernel, dim3(grid_of(n_rec, 256)), dim3(256), 0, st,
                      rec_owner.as<uint32_t>(), n_rec, D.kmt_node.as<int2>());
+  DD_TRY(D.kmt_nbox.alloc(4 * 24 * (size_t)n_nodes));
+  hipLaunchKernelGGL(node_box_kernel, dim3(grid_of(n_nodes, 256)), dim3(256), 0, st,
+                     full.as<float>(), D.kmt_node.as<int2>(), n_nodes, D.kmt_nbox.as<float>());
+  DD_TRY(D.kmt_child.alloc(4 * kKmtRecord * (size_t)n_rec));
+  hipLaunchKernelGGL(compress_records_kernel, dim3(grid_of(n_rec, 256)), dim3(256), 0, st,
+                     full.as<float>(), rec_owner.as<uint32_t>(), n_rec, D.kmt_nbox.as<float>(),
+                     D.kmt_child.as<float>());
   DD_HIP(hipGetLastError());
   DD_HIP(hipStreamSynchronize(st));
   D.kmt_nodes = n_nodes;

@@ -171,8 +171,9 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   DD_TRY(sc.get(Q.u32, (size_t)m));
   DD_TRY(sc.get(Q.invalid, (size_t)m));
   // [0] fb1, [1] fb2, [2..3] candidates (u64), [4..5] slow tiles (u64),
-  // [16..16 + 16 kCounterSlots) ANN walk statistics (kCounterSlots slots of 8 u64)
-  constexpr int kNumCounters = 16 + 16 * kCounterSlots;
+  // [32..) ANN walk statistics (kCounterSlots slots of kCounterStride u64, each
+  // slot on its own 128-byte line)
+  constexpr int kNumCounters = 32 + 2 * kCounterStride * kCounterSlots;
   int* counters = nullptr;
   DD_TRY(sc.get(counters, kNumCounters));
   DD_HIP(hipMemsetAsync(counters, 0, kNumCounters * sizeof(int), st));
@@ -192,7 +193,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   } else if (walk_mode(mode)) {
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
-    ann = reinterpret_cast<unsigned long long*>(counters + 16);
+    ann = reinterpret_cast<unsigned long long*>(counters + 32);
     DD_TRY(timing.mark(1, st));
     if (dist2_out_dev && (budget != 0 || fd < 1.0))
       return set_error(DD_ERR_ARG, "second distances need the exact walk");
@@ -278,14 +279,14 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   }
   if (opts && opts->stats) {
     unsigned long long nc = 0;
-    unsigned long long slots[8 * kCounterSlots] = {};
-    unsigned long long a[5] = {0, 0, 0, 0, 0};
+    unsigned long long slots[kCounterStride * kCounterSlots] = {};
+    unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
     DD_HIP(hipMemcpyAsync(&nc, counters + 2, sizeof(nc), hipMemcpyDeviceToHost, st));
     if (ann) DD_HIP(hipMemcpyAsync(slots, ann, sizeof(slots), hipMemcpyDeviceToHost, st));
     DD_TRY(timing.mark(3, st));
     DD_HIP(hipStreamSynchronize(st));
     for (int s = 0; s < kCounterSlots; ++s)
-      for (int i = 0; i < 5; ++i) a[i] += slots[8 * s + i];
+      for (int i = 0; i < 6; ++i) a[i] += slots[kCounterStride * s + i];
     nc += a[3];
     float scan_ms = 0.0f, total_ms = 0.0f;
     DD_HIP(hipEventElapsedTime(&scan_ms, timing.ev[1], timing.ev[2]));
@@ -296,6 +297,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     opts->stats->boxes = (int64_t)a[1];
     opts->stats->leaves = (int64_t)a[2];
     opts->stats->leaf_boxes = (int64_t)a[4];
+    opts->stats->nodes = (int64_t)a[5];
     opts->stats->scan_ms = scan_ms;
     opts->stats->total_ms = total_ms;
     opts->stats->slow_tiles = n_items_host;

@@ -86,7 +86,8 @@ int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
 // k-means tree with radius factor fd) for the queries of L (one wavefront
 // each): writes outputs, appends overflowed queries to fb_list / fb_count, adds
 // (points visited, boxes tested, leaves visited, candidates reranked, leaf
-// boxes tested) to slot blockIdx % kCounterSlots of counters (8 u64 per slot).
+// boxes tested, nodes expanded) to slot blockIdx % kCounterSlots of counters
+// (kCounterStride u64 per slot).
 // budget = max leaves per query, 0 = exact.
 // With dist2 (exact walk only) the walk certifies the two nearest points and
 // writes the second distance (1/2 d^2; -1 when the query went to the fallback).

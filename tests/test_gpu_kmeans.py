@@ -124,6 +124,35 @@ def test_kmeans_budget_and_fd_are_approximate_within_bounds(L, config0, C0):
         L.dd_project(ds, states, mode="kmeans", ann_fd=1.5)
 
 
+def test_kmeans_fd_search_descends_past_a_good_warm_start(L, C0, config0):
+    """With f_d < 1 the warm start bounds no branch (Section 4.2: the search
+    descends to the nearest centre's leaf first, then backtracks by the ball
+    test against its own best).  Warm-started from each query's second
+    nearest point, f_d = 0 must still find the nearest point for many
+    queries, and never return a point farther than the warm start."""
+    ds, states = config0["ds"], config0["states"]
+    e, s = config0["e"], config0["s"]
+    qs_np = states.cpu().numpy()
+    wq = oracle.whiten(qs_np[:, :6], qs_np[:, 6:], C0)
+    wd = oracle.whiten(e, s, C0)
+    # the nearest point after the oracle's nearest (brute force)
+    second = np.empty(len(wq), np.int64)
+    n2 = np.einsum("ij,ij->i", wd, wd)
+    for a in range(0, len(wq), 512):
+        d = n2[None, :] - 2.0 * wq[a:a + 512] @ wd.T
+        d[np.arange(len(d)), config0["oi"][a:a + 512]] = np.inf
+        second[a:a + 512] = np.argmin(d, axis=1)
+    warm_d = oracle.pair_dist_raw(qs_np[:, :6], qs_np[:, 6:], e[second], s[second], C0)
+    for fd in (0.0, 0.5):
+        idx, dist = L.dd_project(ds, states, warm_start_idx=to_dev(second), mode="kmeans",
+                                 ann_fd=fd)
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        recall = float(np.mean(idx == config0["oi"]))
+        _say(f"f_d {fd}, warm = second nearest: recall {recall:.4f}")
+        assert np.all(dist <= warm_d * (1 + 1e-12))
+        assert recall >= 0.25
+
+
 def test_kmeans_mode_needs_its_pack(L, C0):
     """The k-means mode on a dataset without the tree is refused (status 8);
     a dataset without trees reports an empty index."""
