@@ -192,7 +192,10 @@ def dd_dataset_destroy(ds: Dataset):
 def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: int = 0,
                ann_budget: int = 0, idx_out=None, dist_out=None, stream=None, stats: bool = False,
                passes: int = 0, ann_fd: float | None = None):
-    """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats])."""
+    """dd_project: states device float64 [m][12] -> (idx int64 [m], dist float64 [m][, stats]).
+
+    ann_fd is the k-means walk's f_d (None = 1, exact); it is passed as
+    ann_radius_discount = 1 - f_d."""
     import torch
     m = int(states.shape[0])
     ps = _dev_ptr(states, torch.float64, (12,), "states")
@@ -289,6 +292,9 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
              ann_ramp: int = 0, skip: bool = False, dirichlet_values=None, stream=None,
              ann_fd: float | None = None):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
+
+    ann_fd is the final f_d of the k-means walk (None = 1, exact), passed as
+    ann_radius_discount = 1 - f_d; with ann_ramp it is reached linearly from 0.
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
     (when requested), iterations, converged, cg_iterations, cg_max_residual,
