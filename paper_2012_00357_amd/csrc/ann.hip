@@ -12,7 +12,9 @@
 // skipped when its lower bound exceeds the current bound U.
 //
 // Leaves are stored compactly: per leaf its centre c and radius r (FP32), per
-// point the FP16 offset (x - c) / r; a leaf's box is read quantised to 8 bits
+// point the FP16 offset (x - c) / r, both in the boxes' principal-axis
+// coordinates (a rotation: distances are those of the whitened space, and
+// the walk needs only the rotated query); a leaf's box is read quantised to 8 bits
 // inside its parent's box, decoded outward.
 //
 // Certification.  s~ = r sqrt(sum (q'' - x'')^2) in FP32 with q'' = (q - c)/r
@@ -118,7 +120,8 @@ __device__ inline float half_hi(uint32_t w) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
-// Centred, scaled query of a leaf: qs = (q - c) / r.
+// Centred, scaled query of a leaf: qs = (q - c) / r (q in the leaves' frame:
+// principal-axis coordinates for the box tree, whitened for the k-means tree).
 __device__ inline void leaf_query(const float* __restrict__ meta, int64_t leaf, const float qf[12],
                                   float qs[12], float& r, uint32_t& count) {
   const float4* m = reinterpret_cast<const float4*>(meta + 16 * leaf);
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       const int64_t pos = KMT ? (int64_t)A.pos_slot[A.iperm[wi]] : (int64_t)A.iperm[wi];
       float qs[12], r;
       uint32_t count;
-      leaf_query(A.meta, pos / kAnnLeaf, qf, qs, r, count);
+      leaf_query(A.meta, pos / kAnnLeaf, KMT ? qf : yq, qs, r, count);
       const float s = leaf_point_dist(A.h16, pos, qs, r);
       const float E = ebase + kEps20 * (2.0f * s + 2.0f * r) + kLeafRel * r;
       U = fminf(U, s + E);
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     const int64_t pos = idx * kAnnLeaf + lane;
     float qs[12], r;
     uint32_t count;
-    leaf_query(A.meta, idx, qf, qs, r, count);
+    leaf_query(A.meta, idx, KMT ? qf : yq, qs, r, count);
     const bool v = KMT ? lane < (int)count : pos < A.N;
     float s = INFINITY, E = 0.0f;
     if (v) {

@@ -308,9 +308,9 @@ __global__ __launch_bounds__(256) void ann_node_box_kernel(const float* __restri
 }
 
 // Compact leaf of the walk (one wavefront per leaf): centre, radius and the
-// scaled FP16 offsets of its points.
+// scaled FP16 offsets of its points, in principal-axis coordinates.
 __global__ __launch_bounds__(256) void ann_leaf_pack_kernel(const double* __restrict__ w64,
-                                                            int64_t N, int64_t n_leaf,
+                                                            int64_t N, Rot12 R, int64_t n_leaf,
                                                             float* __restrict__ meta,
                                                             _Float16* __restrict__ h16) {
   const int lane = threadIdx.x & 63;
@@ -319,8 +319,17 @@ __global__ __launch_bounds__(256) void ann_leaf_pack_kernel(const double* __rest
   const int64_t i = leaf * kAnnLeaf + lane;
   const bool v = i < N;
   int cnt = __popcll(__ballot(v));
+  // the point in principal-axis coordinates y = V^T x (the boxes' frame)
   double x[12];
-  for (int k = 0; k < 12; ++k) x[k] = v ? w64[12 * i + k] : 0.0;
+  {
+    double w[12];
+    for (int k = 0; k < 12; ++k) w[k] = v ? w64[12 * i + k] : 0.0;
+    for (int a = 0; a < 12; ++a) {
+      double y = 0.0;
+      for (int k = 0; k < 12; ++k) y = fma(R.V[12 * k + a], w[k], y);
+      x[a] = y;
+    }
+  }
   float c[12];
   for (int k = 0; k < 12; ++k) {
     double sum = x[k];
@@ -636,7 +645,7 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
     DD_TRY(D.ann_meta.alloc(sizeof(float) * 16 * (size_t)nl));
     DD_TRY(D.ann_h16.alloc(sizeof(uint16_t) * 12 * (size_t)(nl * kAnnLeaf)));
     hipLaunchKernelGGL(ann_leaf_pack_kernel, dim3(grid_for(nl, 4)), dim3(256), 0, st,
-                       D.w64.as<double>(), N, nl, D.ann_meta.as<float>(),
+                       D.w64.as<double>(), N, R, nl, D.ann_meta.as<float>(),
                        D.ann_h16.as<_Float16>());
     DD_HIP(hipGetLastError());
     if (D.ann_levels >= 2) {

@@ -130,10 +130,11 @@ struct Dataset {
   DevBuf ann_box[kAnnMaxLevels];
   int64_t ann_n[kAnnMaxLevels] = {0};
   int ann_levels = 0;
-  // compact leaves read by the walk: per leaf the FP32 centre c (mean of its
-  // points), radius r (max |x - c|, rounded up, at least 2^-20) and its box
-  // quantised to 8 bits inside its parent's box (rounded outward); per point the
-  // FP16 scaled offset (x - c) / r (round to nearest)
+  // compact leaves read by the walk, in principal-axis coordinates y = V^T x:
+  // per leaf the FP32 centre c (mean of its points), radius r (max |y - c|,
+  // rounded up, at least 2^-20) and its box quantised to 8 bits inside its
+  // parent's box (rounded outward); per point the FP16 scaled offset (y - c) / r
+  // (round to nearest)
   DevBuf ann_meta;   // float [n_leaf][16]: c[12], r, 1/r, 0, 0
   DevBuf ann_q0;     // uint8 [n_leaf][24]: lo[12], hi[12] in 1/255 of the parent box
   DevBuf ann_h16;    // uint16 [n_leaf*64][12]
