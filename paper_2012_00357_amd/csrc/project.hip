@@ -210,8 +210,8 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     }
   } else {
     const bool fp16 = (mode == DD_MIXED_FP16);
-    int64_t qblocks = (m + 255) / 256;
-    const int S = choose_splits(qblocks, D.n_tiles, splits);
+    const int64_t qblocks = (m + kScan16Queries - 1) / kScan16Queries;
+    const int S = choose_splits16(qblocks, D.n_tiles, splits);
     Scan16Call c;
     c.Q = &Q;
     c.L = all;
