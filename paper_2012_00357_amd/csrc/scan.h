@@ -80,6 +80,9 @@ dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
 dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len, int S,
                      Outputs out, hipStream_t st);
 
+// Splits of a scan over the data (FP64 and direct scans): `requested` if > 0;
+// with fewer than 64 query blocks one round of workgroups (512), otherwise
+// about 2048; multiples of 8 keep a split's workgroups on one XCD.
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
 
 // Queries per workgroup of the 16-bit pass (eight waves of two 32-query groups).

@@ -29,7 +29,9 @@ int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested) {
   if (requested > 0) {
     S = requested;
   } else {
-    S = (2048 + n_query_blocks - 1) / std::max<int64_t>(n_query_blocks, 1);
+    // few query blocks: one round of workgroups; many: about 2048 workgroups
+    const int64_t qb = std::max<int64_t>(n_query_blocks, 1);
+    S = ((qb < 64 ? 512 : 2048) + qb - 1) / qb;
     if (S >= 8) S = (S + 7) / 8 * 8;   // all blocks of one split on one XCD
   }
   S = std::min<int64_t>(S, std::max<int64_t>(n_tiles, 1));
