@@ -148,38 +148,40 @@ dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U
 
 // ---------------------------------------------------------------------------
 // Merge and FP64 rerank (direct form 1/2 |q - x|^2), lexicographic minimum of
-// (distance, original index) over every certified candidate.
+// (distance, original index) over every certified candidate.  With few
+// candidate slots per query (the 16-bit scans: one list per half-wave), one
+// thread per query; with many (the FP64 scan: one list per split and part),
+// one wavefront per query, its lanes taking the slots in turn before the wave
+// reduces (the minimum is order-independent: the same result as a serial
+// merge).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void merge_rerank_kernel(
+__global__ __launch_bounds__(256) void merge_rerank_thread_kernel(
     QueryList L, CandBuf cb, const float* __restrict__ Uq, const double* __restrict__ qw,
     const int* __restrict__ invalid,
     const double* __restrict__ w64, const float* __restrict__ w32, const uint32_t* __restrict__ perm,
     Outputs out, int* __restrict__ fb_list, int* __restrict__ fb_count,
     unsigned long long* __restrict__ n_cand) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= list_len(L)) return;
-  const int64_t q = list_query(L, p);
-  if (invalid[q]) {
+  const int64_t q = p < list_len(L) ? list_query(L, p) : -1;
+  unsigned long long nc = 0;
+  if (q >= 0 && invalid[q]) {
     out.idx[q] = -1;
     if (out.dist) out.dist[q] = NAN;
-    return;
-  }
-  const int S = cb.S, P = cb.P, K = cb.K;
-  float Uf = INFINITY;
-  if (Uq) {
-    Uf = Uq[q];
-  } else {
-    for (int s = 0; s < S; ++s) Uf = fminf(Uf, cb.U[p * S + s]);
-  }
-  double qv[12];
-  for (int k = 0; k < 12; ++k) qv[k] = qw[12 * q + k];
-  double best = INFINITY;
-  uint32_t bo = 0xFFFFFFFFu;
-  bool ovf = false;
-  unsigned long long nc = 0;
-  for (int s = 0; s < S; ++s) {
-    for (int part = 0; part < P; ++part) {
-      const int64_t slot = (p * S + s) * P + part;
+  } else if (q >= 0) {
+    const int S = cb.S, P = cb.P, K = cb.K;
+    float Uf = INFINITY;
+    if (Uq) {
+      Uf = Uq[q];
+    } else {
+      for (int s = 0; s < S; ++s) Uf = fminf(Uf, cb.U[p * S + s]);
+    }
+    double qv[12];
+    for (int k = 0; k < 12; ++k) qv[k] = qw[12 * q + k];
+    double best = INFINITY;
+    uint32_t bo = 0xFFFFFFFFu;
+    bool ovf = false;
+    for (int sl = 0; sl < S * P; ++sl) {
+      const int64_t slot = p * (S * P) + sl;   // (p S + s) P + part with sl = s P + part
       const int c = cb.count[slot];
       const int raw = c & ~kOverflowBit;
       ovf = ovf || (c & kOverflowBit) || raw > K;
@@ -202,15 +204,95 @@ __global__ __launch_bounds__(256) void merge_rerank_kernel(
         }
       }
     }
+    if (ovf || bo == 0xFFFFFFFFu) {
+      int k = atomicAdd(fb_count, 1);
+      fb_list[k] = (int)q;
+    } else {
+      out.idx[q] = (int64_t)bo;
+      if (out.dist) out.dist[q] = 0.5 * best;
+    }
   }
-  if (ovf || bo == 0xFFFFFFFFu) {
-    int k = atomicAdd(fb_count, 1);
-    fb_list[k] = (int)q;
+  // one atomic add per wavefront for the candidate count
+  for (int off = 32; off > 0; off >>= 1) nc += __shfl_xor(nc, off);
+  if (n_cand && (threadIdx.x & 63) == 0 && nc) atomicAdd(n_cand, nc);
+}
+
+__global__ __launch_bounds__(256) void merge_rerank_wave_kernel(
+    QueryList L, CandBuf cb, const float* __restrict__ Uq, const double* __restrict__ qw,
+    const int* __restrict__ invalid,
+    const double* __restrict__ w64, const float* __restrict__ w32, const uint32_t* __restrict__ perm,
+    Outputs out, int* __restrict__ fb_list, int* __restrict__ fb_count,
+    unsigned long long* __restrict__ n_cand) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= list_len(L)) return;   // wave-uniform
+  const int64_t q = list_query(L, p);
+  if (invalid[q]) {
+    if (lane == 0) {
+      out.idx[q] = -1;
+      if (out.dist) out.dist[q] = NAN;
+    }
+    return;
+  }
+  const int S = cb.S, P = cb.P, K = cb.K;
+  float Uf = INFINITY;
+  if (Uq) {
+    Uf = Uq[q];
   } else {
-    out.idx[q] = (int64_t)bo;
-    if (out.dist) out.dist[q] = 0.5 * best;
+    for (int s = lane; s < S; s += 64) Uf = fminf(Uf, cb.U[p * S + s]);
+    for (int off = 32; off > 0; off >>= 1) Uf = fminf(Uf, __shfl_xor(Uf, off));
   }
-  if (n_cand && nc) atomicAdd(n_cand, nc);
+  double qv[12];
+  for (int k = 0; k < 12; ++k) qv[k] = qw[12 * q + k];
+  double best = INFINITY;
+  uint32_t bo = 0xFFFFFFFFu;
+  bool ovf = false;
+  unsigned long long nc = 0;
+  const int slots = S * P;
+  for (int sl = lane; sl < slots; sl += 64) {
+    const int64_t slot = p * slots + sl;   // (p S + s) P + part with sl = s P + part
+    const int c = cb.count[slot];
+    const int raw = c & ~kOverflowBit;
+    ovf = ovf || (c & kOverflowBit) || raw > K;
+    const int n = raw < K ? raw : K;
+    for (int e = 0; e < n; ++e) {
+      if (cb.lb[slot * K + e] <= Uf) {
+        const uint32_t j = cb.j[slot * K + e];
+        double d = 0.0;
+        for (int k = 0; k < 12; ++k) {
+          double x = w64 ? w64[12 * (int64_t)j + k] : (double)w32[12 * (int64_t)j + k];
+          double t = qv[k] - x;
+          d = fma(t, t, d);
+        }
+        const uint32_t o = perm[j];
+        if (d < best || (d == best && o < bo)) {
+          best = d;
+          bo = o;
+        }
+        ++nc;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off);
+    const uint32_t oo = (uint32_t)__shfl_xor((int)bo, off);
+    if (ob < best || (ob == best && oo < bo)) {
+      best = ob;
+      bo = oo;
+    }
+    nc += __shfl_xor(nc, off);
+  }
+  ovf = __any(ovf);
+  if (lane == 0) {
+    if (ovf || bo == 0xFFFFFFFFu) {
+      int k = atomicAdd(fb_count, 1);
+      fb_list[k] = (int)q;
+    } else {
+      out.idx[q] = (int64_t)bo;
+      if (out.dist) out.dist[q] = 0.5 * best;
+    }
+    if (n_cand && nc) atomicAdd(n_cand, nc);
+  }
 }
 
 dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
@@ -218,9 +300,16 @@ dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
                               Outputs out, int* fb_list, int* fb_count, unsigned long long* n_cand,
                               hipStream_t st) {
   if (list_len_max <= 0) return DD_OK;
-  hipLaunchKernelGGL(merge_rerank_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, cb, Uq, Q.qw,
-                     Q.invalid, D.w64.as<double>(), D.w64.p ? nullptr : D.w32.as<float>(),
-                     D.perm.as<uint32_t>(), out, fb_list, fb_count, n_cand);
+  if (cb.S * cb.P <= 8)
+    hipLaunchKernelGGL(merge_rerank_thread_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, cb,
+                       Uq, Q.qw, Q.invalid, D.w64.as<double>(),
+                       D.w64.p ? nullptr : D.w32.as<float>(), D.perm.as<uint32_t>(), out, fb_list,
+                       fb_count, n_cand);
+  else
+    hipLaunchKernelGGL(merge_rerank_wave_kernel, dim3(grid1(list_len_max, 4)), dim3(256), 0, st, L,
+                       cb, Uq, Q.qw, Q.invalid, D.w64.as<double>(),
+                       D.w64.p ? nullptr : D.w32.as<float>(), D.perm.as<uint32_t>(), out, fb_list,
+                       fb_count, n_cand);
   DD_HIP(hipGetLastError());
   return DD_OK;
 }
