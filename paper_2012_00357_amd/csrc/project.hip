@@ -83,8 +83,10 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
   int* fb = nullptr;
   DD_TRY(sc.get(fb, (size_t)len_max));
   int* fb_count = d_counters + 1;
-  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, nullptr, out, fb, fb_count,
-                             reinterpret_cast<unsigned long long*>(d_counters + 2), st));
+  // candidates are counted only for the statistics
+  unsigned long long* n_cand =
+      (tm && tm->on) ? reinterpret_cast<unsigned long long*>(d_counters + 2) : nullptr;
+  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, nullptr, out, fb, fb_count, n_cand, st));
   int h = 0;
   DD_HIP(hipMemcpyAsync(&h, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(hipStreamSynchronize(st));
@@ -266,8 +268,9 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(launch_scan16(D, fp16, c, st));
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
-    DD_TRY(launch_merge_rerank(D, Q, all, m, cb, Q.u32, out, fb, counters,
-                               reinterpret_cast<unsigned long long*>(counters + 2), st));
+    DD_TRY(launch_merge_rerank(
+        D, Q, all, m, cb, Q.u32, out, fb, counters,
+        timing.on ? reinterpret_cast<unsigned long long*>(counters + 2) : nullptr, st));
     int h = 0;
     DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
