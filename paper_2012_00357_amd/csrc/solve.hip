@@ -200,23 +200,25 @@ __global__ void gather_z_kernel(const int64_t* __restrict__ idx, int64_t n_mp, i
 }
 
 // RHS by gathering, per DOF, the contributions of its (<= 8) elements and their
-// Gauss points in a fixed order:  E = A{ w B^T C eps* },  S = f - A{ w B^T sig* }.
-// Dirichlet DOFs get 0.
+// Gauss points: one wavefront per DOF, lane 8 a + g taking Gauss point g of the
+// element whose local node a is the DOF's node, then a fixed-order wave sum.
 // E = A_e{w B^T C eps*} - K_fd u_D on free DOFs and u_D on Dirichlet DOFs (the
 // identity rows of K carry the prescribed displacement), S = f - A_e{w B^T sig*}
 // on free DOFs and 0 on Dirichlet DOFs (eta vanishes there).  uD and lift may be
 // null (homogeneous conditions).
-__global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
-                                    const double* __restrict__ zc, const uint8_t* __restrict__ mask,
-                                    const double* __restrict__ f, const double* __restrict__ uD,
-                                    const double* __restrict__ lift, double* __restrict__ E,
-                                    double* __restrict__ S) {
-  const int64_t dof = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void assemble_rhs_kernel(
+    int nx, int ny, int nz, double w, BOps Bo, const double* __restrict__ zc,
+    const uint8_t* __restrict__ mask, const double* __restrict__ f, const double* __restrict__ uD,
+    const double* __restrict__ lift, double* __restrict__ E, double* __restrict__ S) {
+  const int lane = threadIdx.x & 63;
+  const int64_t dof = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t n_dof = 3 * (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-  if (dof >= n_dof) return;
+  if (dof >= n_dof) return;   // wave-uniform
   if (mask[dof]) {
-    E[dof] = uD ? uD[dof] : 0.0;
-    S[dof] = 0.0;
+    if (lane == 0) {
+      E[dof] = uD ? uD[dof] : 0.0;
+      S[dof] = 0.0;
+    }
     return;
   }
   const int comp = (int)(dof % 3);
@@ -224,24 +226,26 @@ __global__ void assemble_rhs_kernel(int nx, int ny, int nz, double w, BOps Bo,
   const int i = (int)(nd % (nx + 1));
   const int j = (int)((nd / (nx + 1)) % (ny + 1));
   const int k = (int)(nd / ((int64_t)(nx + 1) * (ny + 1)));
+  const int a = lane >> 3, g = lane & 7;
+  const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
   double se = 0.0, ss = 0.0;
-  for (int ez = k - 1; ez <= k; ++ez)
-    for (int ey = j - 1; ey <= j; ++ey)
-      for (int ex = i - 1; ex <= i; ++ex) {
-        if (ex < 0 || ey < 0 || ez < 0 || ex >= nx || ey >= ny || ez >= nz) continue;
-        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
-        const int64_t el = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
-        for (int g = 0; g < 8; ++g) {
-          const double* z = zc + 12 * (8 * el + g);
-          for (int r = 0; r < 6; ++r) {
-            const double bv = Bo.B[g][24 * r + 3 * a + comp];
-            se = fma(bv, z[r], se);
-            ss = fma(bv, z[6 + r], ss);
-          }
-        }
-      }
-  E[dof] = lift ? w * se - lift[dof] : w * se;
-  S[dof] = f[dof] - w * ss;
+  if (ex >= 0 && ey >= 0 && ez >= 0 && ex < nx && ey < ny && ez < nz) {
+    const int64_t el = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+    const double* z = zc + 12 * (8 * el + g);
+    for (int r = 0; r < 6; ++r) {
+      const double bv = Bo.B[g][24 * r + 3 * a + comp];
+      se = fma(bv, z[r], se);
+      ss = fma(bv, z[6 + r], ss);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    se += __shfl_xor(se, off);
+    ss += __shfl_xor(ss, off);
+  }
+  if (lane == 0) {
+    E[dof] = lift ? w * se - lift[dof] : w * se;
+    S[dof] = f[dof] - w * ss;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -839,7 +843,7 @@ dd_status DDSolver::pc_begin() {
   hipLaunchKernelGGL(gather_z_kernel, dim3(g256(nm)), dim3(256), 0, st, d_idx.as<int64_t>(), nm,
                      ds->N, ds->iperm.as<uint32_t>(), ds->w64.as<double>(), Lm, d_zw.as<double>(),
                      d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
-  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
+  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(64 * nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
                      d_uD.as<double>(), d_lift.as<double>(), d_b.as<double>(),
                      d_b.as<double>() + nd);
@@ -1037,7 +1041,7 @@ dd_status DDSolver::constraint_projection() {
   hipLaunchKernelGGL(gather_z_kernel, dim3(g256(nm)), dim3(256), 0, st, d_idx.as<int64_t>(), nm,
                      ds->N, ds->iperm.as<uint32_t>(), ds->w64.as<double>(), Lm, d_zw.as<double>(),
                      d_zc.as<double>(), reinterpret_cast<int*>(d_cgstat.as<char>() + 32));
-  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
+  hipLaunchKernelGGL(assemble_rhs_kernel, dim3(g256(64 * nd)), dim3(256), 0, st, M.nx, M.ny, M.nz, M.w,
                      Bo, d_zc.as<double>(), d_mask.as<uint8_t>(), d_f.as<double>(),
                      d_uD.as<double>(), d_lift.as<double>(), d_b.as<double>(),
                      d_b.as<double>() + nd);
