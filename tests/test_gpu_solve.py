@@ -48,6 +48,27 @@ def test_dd_solve_matches_oracle_trajectory(L, C0, mode):
     np.testing.assert_allclose(got["sig"], ref.sig, rtol=0, atol=1e-9 * np.abs(ref.sig).max())
 
 
+@pytest.mark.parametrize("mode", ["fp64", "ann"])
+def test_dd_solve_resumes_from_a_checkpoint(L, C0, mode):
+    """The association alone fixes the next iterate (Section 2): a solve cut
+    after k iterations and resumed from its association (the checkpoint)
+    follows the uninterrupted trajectory bit for bit."""
+    e, s, m, mask, f, init = _problem(4, 50000, 71)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x10)
+    full = L.dd_solve(ds, (4, 4, 4), mask, f, init, mode=mode, history=True)
+    K = full["iterations"]
+    assert full["converged"] and K >= 3
+    k = K // 2
+    cut = L.dd_solve(ds, (4, 4, 4), mask, f, init, mode=mode, history=True, max_iter=k)
+    assert cut["iterations"] == k and not cut["converged"]
+    assert np.array_equal(cut["history"], full["history"][:k + 1])
+    rest = L.dd_solve(ds, (4, 4, 4), mask, f, cut["idx"], mode=mode, history=True)
+    assert rest["iterations"] == K - k and rest["converged"]
+    assert np.array_equal(rest["history"], full["history"][k:])
+    assert np.array_equal(rest["u"], full["u"]) and np.array_equal(rest["idx"], full["idx"])
+    assert np.array_equal(rest["d_full"], full["d_full"][k:])
+
+
 def test_dd_solve_monotone_and_deterministic(L, C0):
     e, s, m, mask, f, init = _problem(4, 50000, 61)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
