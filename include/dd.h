@@ -193,7 +193,10 @@ dd_status dd_dataset_create_streamed(int64_t N, const double* C, dd_fill_fn fill
 /* Release a dataset's device memory (NULL is a no-op). */
 dd_status dd_dataset_destroy(dd_dataset* ds);
 
-/* Number of points, and bytes of device memory the dataset holds. */
+/* Number of points, and bytes of device memory the dataset holds: its packs and
+   trees plus the projection scratch it keeps between calls (at most 8 idle
+   blocks of at most 1 GiB, released by dd_dataset_destroy).  The K^-1 cache of
+   dd_solve is not counted. */
 dd_status dd_dataset_info(const dd_dataset* ds, int64_t* n_points, int64_t* device_bytes);
 
 /* Shape of a dataset's search trees (zeros for a tree it does not hold). */

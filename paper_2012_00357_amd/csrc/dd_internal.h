@@ -91,6 +91,27 @@ struct DenseInverse {
 constexpr int64_t kDenseMaxDof = 16384;               // meshes up to here use K^-1
 constexpr int64_t kDenseCacheBytes = (int64_t)4 << 30;  // inverses kept per dataset
 
+// Device scratch of the projection, reused from call to call.  A call takes an
+// idle arena (or makes one), carves its buffers out of the arena's block and
+// hands the arena back when it returns, recording `done` on its stream; the
+// next call that takes the arena makes its own stream wait for `done`, so the
+// reuse is stream-ordered on any stream.  Requests beyond the block are
+// allocated stream-ordered and freed on return, and the block then grows (up
+// to kArenaKeepBytes) so that a call of the same size fits next time.
+struct ScratchArena {
+  void* block = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;   // recorded on the last user's stream
+  uint32_t* pinned = nullptr;  // kArenaPinnedWords of pinned host memory (small readbacks)
+  ScratchArena() = default;
+  ScratchArena(const ScratchArena&) = delete;
+  ScratchArena& operator=(const ScratchArena&) = delete;
+  ~ScratchArena();
+};
+constexpr size_t kArenaKeepBytes = (size_t)1 << 30;  // largest block an arena keeps
+constexpr int kArenaKeep = 8;                         // idle arenas kept per dataset
+constexpr int kArenaPinnedWords = 64;
+
 struct Dataset {
   int device = 0;
   int64_t N = 0;
@@ -158,6 +179,11 @@ struct Dataset {
   // inverses of K for dd_solve, most recently used first (see DenseInverse)
   mutable std::mutex cache_mu;
   mutable std::list<std::shared_ptr<DenseInverse>> pc_cache;
+  // idle projection scratch arenas (see ScratchArena); arena_bytes counts the
+  // blocks of idle and busy arenas
+  mutable std::mutex arena_mu;
+  mutable std::vector<std::unique_ptr<ScratchArena>> arenas;
+  mutable int64_t arena_bytes = 0;
 
   int64_t device_bytes() const;
 };

@@ -34,6 +34,14 @@ void DevBuf::release() {
   owned = true;
 }
 
+ScratchArena::~ScratchArena() {
+  // the last user's work on the block must end before the block is freed
+  if (done) (void)hipEventSynchronize(done);
+  if (block) (void)hipFree(block);
+  if (pinned) (void)hipHostFree(pinned);
+  if (done) (void)hipEventDestroy(done);
+}
+
 bool cholesky6(const double* C, double* L) {
   std::memset(L, 0, 36 * sizeof(double));
   for (int j = 0; j < 6; ++j) {
@@ -126,7 +134,8 @@ int64_t Dataset::device_bytes() const {
   b += (int64_t)(ann_meta.bytes + ann_q0.bytes + ann_h16.bytes);
   b += (int64_t)(kmt_node.bytes + kmt_nbox.bytes + kmt_child.bytes + kmt_meta.bytes + kmt_h16.bytes +
                  kmt_pos.bytes + kmt_slot.bytes);
-  return b;
+  std::lock_guard<std::mutex> lk(arena_mu);
+  return b + arena_bytes;
 }
 
 }  // namespace dd

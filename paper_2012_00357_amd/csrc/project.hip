@@ -1,5 +1,7 @@
 // dd_project: dispatch of the projection P_D (Section 2) to the scan kernels.
 #include <algorithm>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "pack16.h"
@@ -10,24 +12,97 @@ namespace dd {
 
 namespace {
 
-// Stream-ordered device scratch released when the call ends.
+// Device scratch of one call, carved from one of the dataset's arenas (see
+// ScratchArena); what does not fit is allocated stream-ordered and freed when
+// the call ends.
 struct Scratch {
+  const Dataset& D;
   hipStream_t st;
-  std::vector<void*> ptrs;
-  explicit Scratch(hipStream_t s) : st(s) {}
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+  std::unique_ptr<ScratchArena> a;
+  size_t off = 0;    // bytes carved from the block
+  size_t need = 0;   // bytes requested by the call
+  std::vector<void*> extra;
+  Scratch(const Dataset& d, hipStream_t s) : D(d), st(s) {}
+  dd_status open() {
+    {
+      std::lock_guard<std::mutex> lk(D.arena_mu);
+      if (!D.arenas.empty()) {
+        a = std::move(D.arenas.back());
+        D.arenas.pop_back();
+      }
+    }
+    if (a) {
+      DD_HIP(hipStreamWaitEvent(st, a->done, 0));
+      return DD_OK;
+    }
+    std::unique_ptr<ScratchArena> n(new ScratchArena);
+    DD_HIP(hipEventCreateWithFlags(&n->done, hipEventDisableTiming));
+    DD_HIP(hipHostMalloc((void**)&n->pinned, sizeof(uint32_t) * kArenaPinnedWords,
+                         hipHostMallocDefault));
+    a = std::move(n);
+    return DD_OK;
   }
+  // word i of the arena's pinned host memory
+  uint32_t* host_word(int i) const { return a->pinned + i; }
   template <class T>
   dd_status get(T*& out, size_t n) {
+    const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
+    need += bytes;
+    if (a->block && off + bytes <= a->bytes) {
+      out = reinterpret_cast<T*>(static_cast<char*>(a->block) + off);
+      off += bytes;
+      return DD_OK;
+    }
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, std::max<size_t>(n, 1) * sizeof(T), st);
+    hipError_t e = hipMallocAsync(&p, bytes, st);
     if (e != hipSuccess)
       return set_error(e == hipErrorOutOfMemory ? DD_ERR_OOM : DD_ERR_DEVICE,
                        std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    ptrs.push_back(p);
+    extra.push_back(p);
     out = static_cast<T*>(p);
     return DD_OK;
+  }
+  ~Scratch() {
+    for (void* p : extra) (void)hipFreeAsync(p, st);
+    if (!a) return;
+    if (need > a->bytes && need <= kArenaKeepBytes) {
+      // grow the block for the next call once the work queued on it is done
+      const size_t grown = std::min(kArenaKeepBytes, ((need + need / 4) + ((1u << 20) - 1)) &
+                                                         ~(size_t)((1u << 20) - 1));
+      void* p = nullptr;
+      const int64_t old = (int64_t)a->bytes;
+      if (hipStreamSynchronize(st) != hipSuccess) {   // the arena is dropped
+        std::lock_guard<std::mutex> lk(D.arena_mu);
+        D.arena_bytes -= old;
+        return;
+      }
+      if (a->block) (void)hipFree(a->block);
+      a->block = nullptr;
+      a->bytes = 0;
+      if (hipMalloc(&p, grown) == hipSuccess) {
+        a->block = p;
+        a->bytes = grown;
+      } else {
+        (void)hipGetLastError();
+      }
+      std::lock_guard<std::mutex> lk(D.arena_mu);
+      D.arena_bytes += (int64_t)a->bytes - old;
+    }
+    if (hipEventRecord(a->done, st) != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      std::lock_guard<std::mutex> lk(D.arena_mu);
+      D.arena_bytes -= (int64_t)a->bytes;
+      a.reset();
+      return;
+    }
+    std::unique_ptr<ScratchArena> drop;   // freed after the lock is released
+    std::lock_guard<std::mutex> lk(D.arena_mu);
+    if ((int)D.arenas.size() < kArenaKeep) {
+      D.arenas.push_back(std::move(a));
+    } else {
+      D.arena_bytes -= (int64_t)a->bytes;
+      drop = std::move(a);   // its destructor waits for `done` before freeing
+    }
   }
 };
 
@@ -87,9 +162,10 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
   unsigned long long* n_cand =
       (tm && tm->on) ? reinterpret_cast<unsigned long long*>(d_counters + 2) : nullptr;
   DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, nullptr, out, fb, fb_count, n_cand, st));
-  int h = 0;
-  DD_HIP(hipMemcpyAsync(&h, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
+  uint32_t* hw = sc.host_word(0);
+  DD_HIP(hipMemcpyAsync(hw, fb_count, sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(hipStreamSynchronize(st));
+  const int h = (int)*hw;
   if (n_fallback) *n_fallback += h;
   if (h > 0) {
     QueryList L2{fb, fb_count, h};
@@ -163,7 +239,8 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   DD_HIP(hipGetDevice(&cur_dev));
   if (cur_dev != D.device) return set_error(DD_ERR_ARG, "dataset lives on another device");
 
-  Scratch sc(st);
+  Scratch sc(D, st);
+  DD_TRY(sc.open());
   Timing timing;
   if (opts && opts->stats) DD_TRY(timing.init(st));
   QueryPrep Q;
@@ -202,9 +279,10 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann,
                            dist2_out_dev, st, mode == DD_KMEANS, fd));
     DD_TRY(timing.mark(2, st));
-    int h = 0;
-    DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    uint32_t* hw = sc.host_word(1);
+    DD_HIP(hipMemcpyAsync(hw, counters, sizeof(int), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
+    const int h = (int)*hw;
     n_fallback += h;
     if (h > 0) {
       QueryList L1{fb, counters, h};
@@ -250,16 +328,18 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(launch_scan16(D, fp16, c, st));
     DD_TRY(timing.mark(2, st));
     DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
-    unsigned ni = 0;
-    DD_HIP(hipMemcpyAsync(&ni, n_items, sizeof(ni), hipMemcpyDeviceToHost, st));
+    uint32_t* nw = sc.host_word(2);
+    DD_HIP(hipMemcpyAsync(nw, n_items, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
+    unsigned ni = *nw;
     if (ni > c.item_cap) {
       // too many items were logged under the running bound: mark again under
       // the final bound, which logs only tiles holding certified candidates
       DD_HIP(hipMemsetAsync(n_items, 0, sizeof(unsigned), st));
       DD_TRY(launch_scan16(D, fp16, c, st));
-      DD_HIP(hipMemcpyAsync(&ni, n_items, sizeof(ni), hipMemcpyDeviceToHost, st));
+      DD_HIP(hipMemcpyAsync(nw, n_items, sizeof(unsigned), hipMemcpyDeviceToHost, st));
       DD_HIP(hipStreamSynchronize(st));
+      ni = *nw;
       if (ni > c.item_cap) return set_error(DD_ERR_TOO_LARGE, "16-bit scan work list overflow");
     }
     n_items_host = ni;
@@ -271,9 +351,10 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(launch_merge_rerank(
         D, Q, all, m, cb, Q.u32, out, fb, counters,
         timing.on ? reinterpret_cast<unsigned long long*>(counters + 2) : nullptr, st));
-    int h = 0;
-    DD_HIP(hipMemcpyAsync(&h, counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    uint32_t* hw = sc.host_word(1);
+    DD_HIP(hipMemcpyAsync(hw, counters, sizeof(int), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
+    const int h = (int)*hw;
     n_fallback += h;
     if (h > 0) {
       QueryList L1{fb, counters, h};

@@ -1107,6 +1107,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   double project_ms = 0.0;
   StepEvents ev;
   DD_TRY(ev.init());
+  DD_TRY(async_init());
   if (res && res->history) {
     DD_HIP(hipMemcpyAsync(res->history, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
   }
@@ -1119,10 +1120,9 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
                        d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
                        d_idx.as<int64_t>(), d_scal.as<double>());
     DD_HIP(hipGetLastError());
-    double sc[3];
-    char cgs[64];
-    DD_HIP(hipMemcpyAsync(sc, d_scal.p, sizeof(sc), hipMemcpyDeviceToHost, st));
-    DD_HIP(hipMemcpyAsync(cgs, d_cgstat.p, 40, hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(h_pin + 128, d_scal.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(h_pin + 160, d_cgstat.as<char>() + 32, sizeof(int), hipMemcpyDeviceToHost,
+                          st));
     if (res && res->history && it <= res->history_capacity)
       DD_HIP(hipMemcpyAsync(res->history + (int64_t)it * nm, d_idx_new.p, sizeof(int64_t) * nm,
                             hipMemcpyDeviceToHost, st));
@@ -1132,8 +1132,10 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     project_ms += pms;
     int cg_it[2] = {cg_last_iters[0], cg_last_iters[1]};
     double cg_res[2] = {cg_last_res[0], cg_last_res[1]};
+    double sc[3];
     int bad = 0;
-    std::memcpy(&bad, cgs + 32, sizeof(bad));
+    std::memcpy(sc, h_pin + 128, sizeof(sc));
+    std::memcpy(&bad, h_pin + 160, sizeof(bad));
     if (bad) return set_error(DD_ERR_DEVICE, "dd_solve: the admissible state became non-finite");
     cg_total += cg_it[0] + cg_it[1];
     cg_res_max = std::max(cg_res_max, std::max(cg_res[0], cg_res[1]));

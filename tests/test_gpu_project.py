@@ -131,6 +131,70 @@ def test_queries_on_data_points_and_duplicates(L, C0, mode):
     assert np.all(dist.cpu().numpy() == 0.0)
 
 
+@pytest.mark.parametrize("mode", ["fp64", "bf16", "ann"])
+def test_scratch_reuse_across_sizes_streams_and_threads(L, C0, mode):
+    """Projections reuse the dataset's scratch arenas: calls that grow the block,
+    calls on another stream and calls from two threads at once give the same
+    indices and distances as the first call; the footprint grows by the kept
+    scratch only."""
+    import threading
+    import torch
+    _say("scratch reuse", mode)
+    e, s = ddsynth.data_points(20000, 5101)
+    qe, qs, _ = ddsynth.queries(e, s, 3000, 5102)
+    oi, od, o2 = oracle.pd_raw(e, s, C0, qe, qs)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4 | 0x10)
+    _, b0 = L.dd_dataset_info(ds)
+    states = to_dev(ddsynth.states(qe, qs))
+    i1, d1 = L.dd_project(ds, states, mode=mode)
+    compare_to_oracle(i1.cpu().numpy(), d1.cpu().numpy(), oi, od, o2)
+    def same(i, d, reps, n=None):
+        # another batch size may merge the split lists with the other merge
+        # kernel: equal indices, distances to rounding
+        ri, rd = i1.cpu()[:n].repeat(reps), d1.cpu()[:n].repeat(reps)
+        assert torch.equal(i.cpu(), ri)
+        np.testing.assert_allclose(d.cpu().numpy(), rd.numpy(), rtol=1e-14, atol=0)
+
+    big = states.repeat(4, 1).contiguous()
+    for q, reps, n in [(states[:37].contiguous(), 1, 37), (big, 4, None)]:
+        same(*L.dd_project(ds, q, mode=mode), reps, n)
+    i, d = L.dd_project(ds, states, mode=mode)
+    assert torch.equal(i, i1) and torch.equal(d, d1)
+    other = torch.cuda.Stream()
+    with torch.cuda.stream(other):
+        i, d = L.dd_project(ds, big, mode=mode, stream=other)
+        other.synchronize()
+    same(i, d, 4)
+    out, errs = {}, []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                for r in range(3):
+                    q = big if (k + r) % 2 else states
+                    i, d = L.dd_project(ds, q, mode=mode, stream=st)
+                    st.synchronize()
+                    out[(k, r)] = (q is big, i.cpu(), d.cpu())
+        except Exception as ex:   # reported below, in the test's thread
+            errs.append(repr(ex))
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=100)
+    assert not errs and len(out) == 6, errs
+    for is_big, i, d in out.values():
+        if is_big:
+            same(i, d, 4)
+        else:
+            assert torch.equal(i, i1.cpu()) and torch.equal(d, d1.cpu())
+    _, b1 = L.dd_dataset_info(ds)
+    _say(f"  device bytes {b0} -> {b1}")
+    assert b0 < b1 <= b0 + 8 * (1 << 30)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_invalid_states_and_empty(L, config0, mode):
     import torch
