@@ -327,7 +327,9 @@ typedef struct dd_solve_result {
  * decreases, since the alternating-minimisation descent no longer holds
  * (Section 4.1); with an accuracy schedule (ann_ramp) both stopping rules wait
  * until the schedule has ended.  Each projection is warm-started from the
- * current association.
+ * current association; the 16-bit scans also run their bound-seeding pass
+ * (passes = 2) at the first iteration and after an iteration that changed
+ * more than 90 % of the associations, where that start is stale.
  *   mesh            structured box mesh (see dd_mesh)
  *   dirichlet_mask  host uint8 [ndof]: 1 = homogeneous Dirichlet DOF (u = eta = 0)
  *   nodal_force     host float64 [ndof]: consistent nodal forces f

@@ -391,9 +391,11 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
 
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
-                           double* dist_out, hipStream_t st, double* dist2_out, double fd) {
+                           double* dist_out, hipStream_t st, double* dist2_out, double fd,
+                           int passes) {
   dd_project_opts o{};
   o.mode = mode;
+  o.passes = passes;
   o.ann_budget = ann_budget;
   o.ann_radius_discount = 1.0 - fd;
   return project_impl_ex(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, dist2_out, st);

@@ -21,10 +21,11 @@ struct FEMesh {
 // dist2_out (exact walks only): distance to the second nearest point, -1
 // where not certified.
 // fd: radius factor of the k-means walk's ball test (1 = exact).
+// passes: as dd_project_opts.passes (0 = the default for the warm start given).
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
                            double* dist_out, hipStream_t st, double* dist2_out = nullptr,
-                           double fd = 1.0);
+                           double fd = 1.0, int passes = 0);
 
 // K^-1 for the mesh and Dirichlet pattern, formed on st from the CSR matrix on
 // first use and cached on the dataset.
@@ -92,6 +93,16 @@ class DDSolver {
   }
   // iteration it projects approximately
   bool approximate_at(int it) const { return budget_at(it) > 0 || fd_at(it) < 1.0; }
+  // associations the previous iteration changed (-1 before the first)
+  int64_t last_changed = -1;
+  // passes of the 16-bit scans at iteration it: the bound-seeding pass runs
+  // beside the warm start while that start is stale (the first iteration, or
+  // after an iteration that changed nearly every association); 0 = warm start
+  // alone
+  int scan_passes(int it) const {
+    if (mode != DD_MIXED_BF16 && mode != DD_MIXED_FP16) return 0;
+    return (it == 1 || last_changed < 0 || 10 * last_changed > 9 * M.n_mp) ? 2 : 0;
+  }
   double cg_tol = 1e-13;
   int cg_max_iter = 20000;
   int64_t nnz = 0;

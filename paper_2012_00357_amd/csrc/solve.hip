@@ -784,7 +784,8 @@ dd_status DDSolver::project_step(int it) {
   const int64_t nm = M.n_mp;
   if (!skip_on)
     return project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, budget_at(it),
-                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st, nullptr, fd_at(it));
+                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st, nullptr, fd_at(it),
+                            scan_passes(it));
   DD_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int), st));
   hipLaunchKernelGGL(skip_kernel, dim3(g256(nm)), dim3(256), 0, st, nm, d_yw.as<double>(),
                      d_qref.as<double>(), d_gap.as<double>(), d_idx.as<int64_t>(),
@@ -1108,6 +1109,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
   StepEvents ev;
   DD_TRY(ev.init());
   DD_TRY(async_init());
+  last_changed = -1;
   if (res && res->history) {
     DD_HIP(hipMemcpyAsync(res->history, d_idx.p, sizeof(int64_t) * nm, hipMemcpyDeviceToHost, st));
   }
@@ -1139,6 +1141,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     if (bad) return set_error(DD_ERR_DEVICE, "dd_solve: the admissible state became non-finite");
     cg_total += cg_it[0] + cg_it[1];
     cg_res_max = std::max(cg_res_max, std::max(cg_res[0], cg_res[1]));
+    last_changed = (int64_t)sc[2];
     if (res) {
       if (res->d_half && it <= res->history_capacity) res->d_half[it - 1] = sc[0];
       if (res->d_full && it <= res->history_capacity) res->d_full[it - 1] = sc[1];
