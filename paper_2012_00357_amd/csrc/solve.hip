@@ -510,43 +510,62 @@ __global__ void recover_kernel(int nx, int ny, int nz, BOps Bo, Mat6 LT, Mat6 L,
   }
 }
 
-// Deterministic per-iteration scalars over the material points (one block):
+// Deterministic per-iteration scalars over the material points:
 //   out[0] = sum_e w 1/2 |y_e - z_e|^2 (D_half), out[1] = sum_e w dist_e (D_full),
 //   out[2] = #{idx_new != idx_old}.
-__global__ __launch_bounds__(1024) void iter_scalars_kernel(
+// out[3] holds a ticket (u32, zero between launches) and out[4 + 3b ..] the
+// partial sums of block b.  Block b sums a fixed range of material points (the
+// squared differences read as one flat, coalesced array), its waves reduce in a
+// fixed shuffle order and the block stores its partials; the block that takes
+// the last ticket adds the partials in block order and resets the ticket, so
+// the result does not depend on which block finishes last.
+constexpr int kScalBlocks = 32;
+__global__ __launch_bounds__(256) void iter_scalars_kernel(
     int64_t n_mp, double w, const double* __restrict__ yw, const double* __restrict__ zw,
     const double* __restrict__ dist, const int64_t* __restrict__ idx_new,
-    const int64_t* __restrict__ idx_old, double* __restrict__ out) {
-  __shared__ double red[3 * 1024];
+    const int64_t* __restrict__ idx_old, double* out) {
   const int t = threadIdx.x;
+  const int64_t chunk = (n_mp + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = min(n_mp, (int64_t)blockIdx.x * chunk);
+  const int64_t e1 = min(n_mp, e0 + chunk);
   double dh = 0.0, df = 0.0, ch = 0.0;
-  for (int64_t e = t; e < n_mp; e += 1024) {
-    double s = 0.0;
-    for (int k = 0; k < 12; ++k) {
-      const double d = yw[12 * e + k] - zw[12 * e + k];
-      s = fma(d, d, s);
-    }
-    dh += 0.5 * s;
+  for (int64_t f = 12 * e0 + t; f < 12 * e1; f += 256) {
+    const double d = yw[f] - zw[f];
+    dh = fma(d, d, dh);
+  }
+  for (int64_t e = e0 + t; e < e1; e += 256) {
     df += dist[e];
     ch += (idx_new[e] != idx_old[e]) ? 1.0 : 0.0;
   }
-  red[t] = dh;
-  red[1024 + t] = df;
-  red[2048 + t] = ch;
+  for (int off = 32; off > 0; off >>= 1) {
+    dh += __shfl_down(dh, off);
+    df += __shfl_down(df, off);
+    ch += __shfl_down(ch, off);
+  }
+  __shared__ double ws[3][4];
+  __shared__ int last;
+  if ((t & 63) == 0) {
+    ws[0][t >> 6] = dh;
+    ws[1][t >> 6] = df;
+    ws[2][t >> 6] = ch;
+  }
   __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) {
-      red[t] += red[t + off];
-      red[1024 + t] += red[1024 + t + off];
-      red[2048 + t] += red[2048 + t + off];
-    }
-    __syncthreads();
-  }
   if (t == 0) {
-    out[0] = w * red[0];
-    out[1] = w * red[1024];
-    out[2] = red[2048];
+    double* part = out + 4 + 3 * blockIdx.x;
+    for (int k = 0; k < 3; ++k) part[k] = ((ws[k][0] + ws[k][1]) + ws[k][2]) + ws[k][3];
+    __threadfence();
+    last = atomicAdd(reinterpret_cast<unsigned*>(out + 3), 1u) == gridDim.x - 1;
   }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (t < 3) {
+    const volatile double* part = out + 4;
+    double sum = 0.0;
+    for (unsigned b = 0; b < gridDim.x; ++b) sum += part[3 * b + t];
+    out[t] = t == 0 ? 0.5 * w * sum : (t == 1 ? w * sum : sum);
+  }
+  if (t == 0) *reinterpret_cast<volatile unsigned*>(out + 3) = 0u;
 }
 
 // Unmoved material points (exact ANN projections).  If the state y moved by
@@ -714,7 +733,8 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
       {&d_x, sizeof(double) * 2 * nd}, {&d_idx, sizeof(int64_t) * nm},
       {&d_idx_new, sizeof(int64_t) * nm}, {&d_dist, sizeof(double) * nm},
       {&d_zw, sizeof(double) * 12 * nm}, {&d_zc, sizeof(double) * 12 * nm},
-      {&d_yw, sizeof(double) * 12 * nm}, {&d_scal, sizeof(double) * 4}, {&d_cgstat, 64}};
+      {&d_yw, sizeof(double) * 12 * nm}, {&d_scal, sizeof(double) * (4 + 3 * kScalBlocks)},
+      {&d_cgstat, 64}};
   if (!uD.empty()) {
     parts.push_back({&d_uD, sizeof(double) * nd});
     parts.push_back({&d_lift, sizeof(double) * nd});
@@ -758,6 +778,7 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
   DD_HIP(hipMemcpyAsync(d_f.p, force, sizeof(double) * nd, hipMemcpyHostToDevice, st));
   DD_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double) * 2 * nd, st));
   DD_HIP(hipMemsetAsync(d_cgstat.p, 0, 64, st));
+  DD_HIP(hipMemsetAsync(d_scal.p, 0, d_scal.bytes, st));   // the scalars kernel's ticket
   if (want_dense && !dense)
     DD_TRY(dense_inverse_for(D, M, mask, d_rowptr.as<int32_t>(), d_col.as<int32_t>(),
                              d_val.as<double>(), dense, st));
@@ -823,7 +844,7 @@ int64_t DDSolver::footprint_bytes(const dd_mesh& m) {
   const int64_t nnz = 81 * nd;
   const int64_t nb = (nd + kCgBlock - 1) / kCgBlock, nbs = (nd + kRowsPerBlock - 1) / kRowsPerBlock;
   return 4 * (nd + 1) + 12 * nnz + (8 + 1 + 8 + 16 + 16 + 64) * nd + (8 + 8 + 8 + 3 * 96) * nm +
-         32 + 64 + 64 * (nb + nbs) + (int64_t)sizeof(CGState);
+         8 * (4 + 3 * kScalBlocks) + 64 + 64 * (nb + nbs) + (int64_t)sizeof(CGState);
 }
 
 // Pinned layout: [0, 128) CG state, [128, 152) iteration scalars, [160, 164) bad flag.
@@ -932,7 +953,7 @@ dd_status DDSolver::pc_end() {
 
 dd_status DDSolver::scalars_begin() {
   const int64_t nm = M.n_mp;
-  hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
+  hipLaunchKernelGGL(iter_scalars_kernel, dim3(kScalBlocks), dim3(256), 0, st, nm, M.w, d_yw.as<double>(),
                      d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
                      d_idx.as<int64_t>(), d_scal.as<double>());
   DD_HIP(hipGetLastError());
@@ -1118,7 +1139,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
     DD_HIP(hipEventRecord(ev.e[0], st));
     DD_TRY(project_step(it));
     DD_HIP(hipEventRecord(ev.e[1], st));
-    hipLaunchKernelGGL(iter_scalars_kernel, dim3(1), dim3(1024), 0, st, nm, M.w, d_yw.as<double>(),
+    hipLaunchKernelGGL(iter_scalars_kernel, dim3(kScalBlocks), dim3(256), 0, st, nm, M.w, d_yw.as<double>(),
                        d_zw.as<double>(), d_dist.as<double>(), d_idx_new.as<int64_t>(),
                        d_idx.as<int64_t>(), d_scal.as<double>());
     DD_HIP(hipGetLastError());
