@@ -463,50 +463,61 @@ __global__ __launch_bounds__(kCgBlock) void cg_pupdate_kernel(
 // Admissible state at every material point from u, eta (whitened):
 //   w_eps = L^T B u,  w_sig = w_sig* + L^T B eta;  optionally raw eps = B u,
 //   sig = sig* + C B eta with C B eta = L (L^T B eta).
-__global__ void recover_kernel(int nx, int ny, int nz, BOps Bo, Mat6 LT, Mat6 L,
-                               const double* __restrict__ x /*[2][n_dof]*/, int64_t n_dof,
-                               const double* __restrict__ zw, const double* __restrict__ zc,
-                               double* __restrict__ yw, double* __restrict__ eps_raw,
-                               double* __restrict__ sig_raw) {
-  const int64_t mp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Eight lanes per material point, lane a taking element node a.  The node
+// sums meet in an xor butterfly, which leaves the same sums in all eight lanes
+// (each step adds the same two values on both partners); lane r < 6 then
+// writes row r.
+__global__ __launch_bounds__(256) void recover_kernel(int nx, int ny, int nz, BOps Bo, Mat6 LT,
+                                                      Mat6 L,
+                                                      const double* __restrict__ x /*[2][n_dof]*/,
+                                                      int64_t n_dof, const double* __restrict__ zw,
+                                                      const double* __restrict__ zc,
+                                                      double* __restrict__ yw,
+                                                      double* __restrict__ eps_raw,
+                                                      double* __restrict__ sig_raw) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mp = gid >> 3;
+  const int a = (int)(gid & 7);
   const int64_t n_mp = 8 * (int64_t)nx * ny * nz;
-  if (mp >= n_mp) return;
+  if (mp >= n_mp) return;   // whole groups of eight leave together
   const int g = (int)(mp % 8);
   const int64_t el = mp / 8;
   const int ex = (int)(el % nx), ey = (int)((el / nx) % ny), ez = (int)(el / ((int64_t)nx * ny));
   double eu[6] = {0, 0, 0, 0, 0, 0}, ee[6] = {0, 0, 0, 0, 0, 0};
-  for (int a = 0; a < 8; ++a) {
-    const int64_t nd = dnode(nx, ny, ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
-    for (int c = 0; c < 3; ++c) {
-      const double uv = x[3 * nd + c], ev = x[n_dof + 3 * nd + c];
-      for (int r = 0; r < 6; ++r) {
-        const double bv = Bo.B[g][24 * r + 3 * a + c];
-        eu[r] = fma(bv, uv, eu[r]);
-        ee[r] = fma(bv, ev, ee[r]);
-      }
-    }
-  }
-  double we[6], ws[6];
-  for (int r = 0; r < 6; ++r) {
-    double a = 0.0, b = 0.0;
-    for (int c = 0; c < 6; ++c) {
-      a = fma(LT.a[6 * r + c], eu[c], a);
-      b = fma(LT.a[6 * r + c], ee[c], b);
-    }
-    we[r] = a;
-    ws[r] = b;
-  }
-  for (int r = 0; r < 6; ++r) {
-    yw[12 * mp + r] = we[r];
-    yw[12 * mp + 6 + r] = zw[12 * mp + 6 + r] + ws[r];
-  }
-  if (eps_raw) {
+  const int64_t nd = dnode(nx, ny, ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
+  for (int c = 0; c < 3; ++c) {
+    const double uv = x[3 * nd + c], ev = x[n_dof + 3 * nd + c];
     for (int r = 0; r < 6; ++r) {
-      double cb = 0.0;
-      for (int c = 0; c < 6; ++c) cb = fma(L.a[6 * r + c], ws[c], cb);
-      eps_raw[6 * mp + r] = eu[r];
-      sig_raw[6 * mp + r] = zc[12 * mp + 6 + r] + cb;
+      const double bv = Bo.B[g][24 * r + 3 * a + c];
+      eu[r] = fma(bv, uv, eu[r]);
+      ee[r] = fma(bv, ev, ee[r]);
     }
+  }
+  for (int m = 1; m < 8; m <<= 1) {
+    for (int r = 0; r < 6; ++r) {
+      eu[r] += __shfl_xor(eu[r], m, 8);
+      ee[r] += __shfl_xor(ee[r], m, 8);
+    }
+  }
+  if (a >= 6) return;
+  const int r = a;
+  double we = 0.0, ws = 0.0, eur = 0.0;
+  for (int c = 0; c < 6; ++c) {
+    we = fma(LT.a[6 * r + c], eu[c], we);
+    ws = fma(LT.a[6 * r + c], ee[c], ws);
+    eur = (c == r) ? eu[c] : eur;
+  }
+  yw[12 * mp + r] = we;
+  yw[12 * mp + 6 + r] = zw[12 * mp + 6 + r] + ws;
+  if (eps_raw) {
+    double cb = 0.0;
+    for (int c = 0; c < 6; ++c) {
+      double wsc = 0.0;
+      for (int k = 0; k < 6; ++k) wsc = fma(LT.a[6 * c + k], ee[k], wsc);
+      cb = fma(L.a[6 * r + c], wsc, cb);
+    }
+    eps_raw[6 * mp + r] = eur;
+    sig_raw[6 * mp + r] = zc[12 * mp + 6 + r] + cb;
   }
 }
 
@@ -943,7 +954,7 @@ dd_status DDSolver::pc_end() {
   std::memcpy(LTm.a, Lt, sizeof(Lt));
   BOps Bo;
   std::memcpy(Bo.B, M.B, sizeof(Bo.B));
-  hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
+  hipLaunchKernelGGL(recover_kernel, dim3(g256(8 * nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
                      d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),
                      (double*)nullptr, (double*)nullptr);
   DD_HIP(hipGetLastError());
@@ -1068,7 +1079,7 @@ dd_status DDSolver::constraint_projection() {
                      d_uD.as<double>(), d_lift.as<double>(), d_b.as<double>(),
                      d_b.as<double>() + nd);
   DD_TRY(cg_solve());
-  hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
+  hipLaunchKernelGGL(recover_kernel, dim3(g256(8 * nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm, Lm,
                      d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(), d_yw.as<double>(),
                      (double*)nullptr, (double*)nullptr);
   DD_HIP(hipGetLastError());
@@ -1090,7 +1101,7 @@ dd_status DDSolver::fetch_results(double* u, int64_t* idx, double* eps, double* 
     std::memcpy(LTm.a, Lt, sizeof(Lt));
     BOps Bo;
     std::memcpy(Bo.B, M.B, sizeof(Bo.B));
-    hipLaunchKernelGGL(recover_kernel, dim3(g256(nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm,
+    hipLaunchKernelGGL(recover_kernel, dim3(g256(8 * nm)), dim3(256), 0, st, M.nx, M.ny, M.nz, Bo, LTm,
                        Lm, d_x.as<double>(), nd, d_zw.as<double>(), d_zc.as<double>(),
                        d_yw.as<double>(), er.as<double>(), sr.as<double>());
     DD_HIP(hipGetLastError());
