@@ -171,6 +171,9 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(const double* __restri
   if (r >= n) return;
   const double* row = inv + r * n_pad;
   double a0 = 0.0, a1 = 0.0;
+  // unrolled so that several iterations' loads are in flight; the FMA chain
+  // keeps its order
+#pragma unroll 8
   for (int64_t j = lane; j < n; j += 64) {
     const double k = row[j];
     a0 = fma(k, b[j], a0);
