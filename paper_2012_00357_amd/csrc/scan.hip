@@ -150,10 +150,11 @@ dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U
 // Merge and FP64 rerank (direct form 1/2 |q - x|^2), lexicographic minimum of
 // (distance, original index) over every certified candidate.  With few
 // candidate slots per query (the 16-bit scans: one list per half-wave), one
-// thread per query; with many (the FP64 scan: one list per split and part),
-// one wavefront per query, its lanes taking the slots in turn before the wave
-// reduces (the minimum is order-independent: the same result as a serial
-// merge).
+// thread per query in large batches and, in small ones, one wavefront per query
+// whose lanes take the (slot, entry) pairs; with many slots (the FP64 scan: one
+// list per split and part), one wavefront per query, its lanes taking the
+// slots in turn.  The wave then reduces; the minimum is order-independent, so
+// every variant gives the result of a serial merge.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void merge_rerank_thread_kernel(
     QueryList L, CandBuf cb, const float* __restrict__ Uq, const double* __restrict__ qw,
@@ -217,6 +218,9 @@ __global__ __launch_bounds__(256) void merge_rerank_thread_kernel(
   if (n_cand && (threadIdx.x & 63) == 0 && nc) atomicAdd(n_cand, nc);
 }
 
+// FLAT: the lanes take (slot, entry) pairs instead of whole slots, for lists
+// with few slots of many entries (the 16-bit scans' two half-wave lists).
+template <bool FLAT>
 __global__ __launch_bounds__(256) void merge_rerank_wave_kernel(
     QueryList L, CandBuf cb, const float* __restrict__ Uq, const double* __restrict__ qw,
     const int* __restrict__ invalid,
@@ -249,28 +253,40 @@ __global__ __launch_bounds__(256) void merge_rerank_wave_kernel(
   bool ovf = false;
   unsigned long long nc = 0;
   const int slots = S * P;
-  for (int sl = lane; sl < slots; sl += 64) {
-    const int64_t slot = p * slots + sl;   // (p S + s) P + part with sl = s P + part
-    const int c = cb.count[slot];
-    const int raw = c & ~kOverflowBit;
-    ovf = ovf || (c & kOverflowBit) || raw > K;
-    const int n = raw < K ? raw : K;
-    for (int e = 0; e < n; ++e) {
-      if (cb.lb[slot * K + e] <= Uf) {
-        const uint32_t j = cb.j[slot * K + e];
-        double d = 0.0;
-        for (int k = 0; k < 12; ++k) {
-          double x = w64 ? w64[12 * (int64_t)j + k] : (double)w32[12 * (int64_t)j + k];
-          double t = qv[k] - x;
-          d = fma(t, t, d);
-        }
-        const uint32_t o = perm[j];
-        if (d < best || (d == best && o < bo)) {
-          best = d;
-          bo = o;
-        }
-        ++nc;
+  auto rerank = [&](int64_t slot, int e) __attribute__((always_inline)) {
+    if (cb.lb[slot * K + e] <= Uf) {
+      const uint32_t j = cb.j[slot * K + e];
+      double d = 0.0;
+      for (int k = 0; k < 12; ++k) {
+        double x = w64 ? w64[12 * (int64_t)j + k] : (double)w32[12 * (int64_t)j + k];
+        double t = qv[k] - x;
+        d = fma(t, t, d);
       }
+      const uint32_t o = perm[j];
+      if (d < best || (d == best && o < bo)) {
+        best = d;
+        bo = o;
+      }
+      ++nc;
+    }
+  };
+  if (FLAT) {
+    for (int it = lane; it < slots * K; it += 64) {
+      const int sl = it / K, e = it - sl * K;
+      const int64_t slot = p * slots + sl;
+      const int c = cb.count[slot];
+      const int raw = c & ~kOverflowBit;
+      if (e == 0) ovf = ovf || (c & kOverflowBit) || raw > K;
+      if (e < (raw < K ? raw : K)) rerank(slot, e);
+    }
+  } else {
+    for (int sl = lane; sl < slots; sl += 64) {
+      const int64_t slot = p * slots + sl;   // (p S + s) P + part with sl = s P + part
+      const int c = cb.count[slot];
+      const int raw = c & ~kOverflowBit;
+      ovf = ovf || (c & kOverflowBit) || raw > K;
+      const int n = raw < K ? raw : K;
+      for (int e = 0; e < n; ++e) rerank(slot, e);
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -300,14 +316,22 @@ dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
                               Outputs out, int* fb_list, int* fb_count, unsigned long long* n_cand,
                               hipStream_t st) {
   if (list_len_max <= 0) return DD_OK;
-  if (cb.S * cb.P <= 8)
+  // few slots: a thread per query for large batches, a wavefront per query
+  // over the (slot, entry) pairs for small ones; many slots: a wavefront per
+  // query over the slots
+  if (cb.S * cb.P <= 8 && list_len_max < 16384 && cb.S * cb.P * cb.K <= 256)
+    hipLaunchKernelGGL(merge_rerank_wave_kernel<true>, dim3(grid1(list_len_max, 4)), dim3(256), 0,
+                       st, L, cb, Uq, Q.qw, Q.invalid, D.w64.as<double>(),
+                       D.w64.p ? nullptr : D.w32.as<float>(), D.perm.as<uint32_t>(), out, fb_list,
+                       fb_count, n_cand);
+  else if (cb.S * cb.P <= 8)
     hipLaunchKernelGGL(merge_rerank_thread_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, cb,
                        Uq, Q.qw, Q.invalid, D.w64.as<double>(),
                        D.w64.p ? nullptr : D.w32.as<float>(), D.perm.as<uint32_t>(), out, fb_list,
                        fb_count, n_cand);
   else
-    hipLaunchKernelGGL(merge_rerank_wave_kernel, dim3(grid1(list_len_max, 4)), dim3(256), 0, st, L,
-                       cb, Uq, Q.qw, Q.invalid, D.w64.as<double>(),
+    hipLaunchKernelGGL(merge_rerank_wave_kernel<false>, dim3(grid1(list_len_max, 4)), dim3(256), 0,
+                       st, L, cb, Uq, Q.qw, Q.invalid, D.w64.as<double>(),
                        D.w64.p ? nullptr : D.w32.as<float>(), D.perm.as<uint32_t>(), out, fb_list,
                        fb_count, n_cand);
   DD_HIP(hipGetLastError());
