@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense bf16 MFMA
+FP32_PEAK_TFLOPS = 157.3      # MI355X fp32 MFMA
 FP64_PEAK_TFLOPS = 78.6       # MI355X fp64 MFMA
 FLOPS_PER_PAIR = 24.0         # K = 12 dot product per (query, data point)
 
@@ -65,6 +66,31 @@ def profile_traffic(name, workload):
     if fields.get("workload") != workload:
         return None
     return float(fields["traffic_bytes_per_launch"])
+
+
+def host_cpu():
+    """CPU model, sockets, physical cores and logical CPUs of this host (for the
+    CPU baseline), from /proc/cpuinfo and the scheduler's affinity mask."""
+    model, phys = "unknown", set()
+    try:
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if "physical id" in cur and "core id" in cur:
+                    phys.add((cur["physical id"], cur["core id"]))
+                cur = {}
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            cur[k] = v
+            if k == "model name":
+                model = v
+        if "physical id" in cur and "core id" in cur:
+            phys.add((cur["physical id"], cur["core id"]))
+    except OSError:
+        pass
+    return {"model": model, "sockets": len({p for p, _ in phys}) or None,
+            "physical_cores": len(phys) or None, "logical_cpus": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0))}
 
 
 def dd_solve_latency(L, C, R):
@@ -231,17 +257,27 @@ def ann_leg(L, C, steps, budgets=(4, 64), solve=True, index="ann", fds=()):
     log(f"{index} 1e9 dd_solve 16^3 with skipping: {skip_ms:.0f} ms, skipped {rs['skipped']} of "
         f"{rs['iterations'] * 8 * n ** 3} projections")
     sched = []
-    for budget, ramp in ((4, 0), (4, 10), (16, 10)):
+    runs = [dict(ann_budget=4), dict(ann_budget=4, ann_ramp=10),
+            dict(ann_budget=4, ann_ramp=10, local_accuracy=True), dict(ann_budget=16, ann_ramp=10),
+            dict(ann_budget=16, ann_ramp=10, local_accuracy=True)]
+    if kmt:
+        runs += [dict(ann_fd=0.4, ann_ramp=10), dict(ann_fd=0.4, ann_ramp=10, local_accuracy=True),
+                 dict(ann_fd=0.0, ann_ramp=10), dict(ann_fd=0.0, ann_ramp=10, local_accuracy=True)]
+    for kw in runs:
         t = time.time()
-        rb = L.dd_solve(ds, (n, n, n), mask, force, init, mode=index, ann_budget=budget,
-                        ann_ramp=ramp)
+        rb = L.dd_solve(ds, (n, n, n), mask, force, init, mode=index, **kw)
         ms_b = (time.time() - t) * 1e3
         err = float(np.linalg.norm(rb["u"] - r["u"]) / np.linalg.norm(r["u"]))
-        sched.append({"budget": budget, "ramp": ramp, "ms": round(ms_b, 1),
-                      "iterations": rb["iterations"], "stop_reason": rb["stop_reason"],
-                      "u_rel_err_vs_exact": err})
-        log(f"{index} 1e9 dd_solve 16^3 budget {budget} ramp {ramp}: {ms_b:.0f} ms, "
-            f"{rb['iterations']} iterations, u rel err {err:.3e}")
+        row = {"budget": kw.get("ann_budget", 0), "ramp": kw.get("ann_ramp", 0),
+               "f_d_final": kw.get("ann_fd", 1.0), "local_accuracy": kw.get("local_accuracy", False),
+               "ms": round(ms_b, 1), "search_ms": round(rb["project_ms"], 1),
+               "iterations": rb["iterations"], "stop_reason": rb["stop_reason"],
+               "final_global_distance": float(rb["d_full"][-1]), "u_rel_err_vs_exact": err}
+        sched.append(row)
+        log(f"{index} 1e9 dd_solve 16^3 {kw}: {ms_b:.0f} ms (search {rb['project_ms']:.0f} ms), "
+            f"{rb['iterations']} iterations, final distance {rb['d_full'][-1]:.5g}, "
+            f"u rel err {err:.3e}")
+    out["dd_solve_16cube_exact_distance"] = float(r["d_full"][-1])
     out["dd_solve_16cube_budgeted"] = sched
     ds.close()
     return out
@@ -416,12 +452,16 @@ def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_0
         build_s = round(time.time() - t, 2)
         for fd in kmeans_fds:
             ramp = kmeans_ramp if fd < 1.0 else 0
-            run = {"N": N, "f_d_final": fd, "ramp_iterations": ramp, "dataset_build_s": build_s}
-            run.update(solves(ds, N, mode="kmeans", ann_fd=fd, ann_ramp=ramp))
-            out["kmeans_runs"].append(run)
-            log(f"paper example N={N}, k-means tree f_d^f {fd}: {run['mean_iterations']} "
-                f"iterations, final distance {run['mean_final_global_distance']:.4g}, "
-                f"{run['mean_solve_ms']} ms (search {run['mean_search_ms']} ms)")
+            for local in ((False, True) if fd < 1.0 else (False,)):
+                run = {"N": N, "f_d_final": fd, "ramp_iterations": ramp, "local_accuracy": local,
+                       "dataset_build_s": build_s}
+                run.update(solves(ds, N, mode="kmeans", ann_fd=fd, ann_ramp=ramp,
+                                  local_accuracy=local))
+                out["kmeans_runs"].append(run)
+                log(f"paper example N={N}, k-means tree f_d^f {fd}{' local' if local else ''}: "
+                    f"{run['mean_iterations']} iterations, final distance "
+                    f"{run['mean_final_global_distance']:.4g}, {run['mean_solve_ms']} ms "
+                    f"(search {run['mean_search_ms']} ms)")
         ds.close()
         torch.cuda.empty_cache()
     return out
@@ -436,16 +476,21 @@ def main():
     ap.add_argument("--m", type=int, default=65536)
     ap.add_argument("--mode", default="bf16", choices=["bf16", "fp16", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-queries", type=int, default=48)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=256)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--tile", type=int, default=1024)
     ap.add_argument("--passes", type=int, default=0)
-    ap.add_argument("--dd-solves", type=int, default=20,
+    ap.add_argument("--dd-solves", type=int, default=100,
                     help="DD solves (8^3 hex, N=1e6) timed for the p50/p99 latency leg; 0 = skip")
     ap.add_argument("--skip-ann", action="store_true", help="skip the N=1e9 ANN leg")
-    ap.add_argument("--serve-solves", type=int, default=12,
+    ap.add_argument("--serve-solves", type=int, default=200,
                     help="solves per Poisson run of the serving leg (N=2^26); 0 = skip")
+    ap.add_argument("--serve-modes", default="ann",
+                    help="projection modes of the serving leg, comma separated (bf16 serves "
+                         "about 0.7 solves/s of this mix: 200 solves take minutes per rate)")
     ap.add_argument("--paper-seeds", type=int, default=3,
                     help="random starts per data-set size in the paper-example leg; 0 = skip")
     ap.add_argument("--paper-only", action="store_true",
@@ -482,7 +527,9 @@ def main():
               flush=True)
         return
     if args.serve_only:
-        print(json.dumps({"serving": serve_leg(L, C, args.serve_solves)}), flush=True)
+        print(json.dumps({"serving": serve_leg(L, C, args.serve_solves,
+                                               modes=tuple(args.serve_modes.split(",")))}),
+              flush=True)
         return
     if args.ann_only:
         res = {"ann": ann_leg(L, C, args.steps, solve=not args.ann_no_solve)}
@@ -601,6 +648,38 @@ def main():
                                                   / dist_mixed))}
         log(f"fp64: {wall * 1e3:.1f} ms/step, indices equal to {args.mode}: {same}")
 
+    fp32 = None
+    if not args.skip_fp32 and args.mode != "fp64":
+        # the FP32 MFMA scan of the same batch (its own pack; FP64 rerank and fallback)
+        ds.close()
+        torch.cuda.empty_cache()
+        t = time.time()
+        ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C,
+                                 packs=0x1 | 0x2, tile=args.tile)
+        torch.cuda.synchronize()
+        log(f"FP32 dataset built in {time.time() - t:.2f}s")
+        L.dd_project(ds, states, mode="fp32")
+        walls, scans = [], []
+        for _ in range(args.fp32_steps):
+            torch.cuda.synchronize()
+            t = time.time()
+            i32, d32, st = L.dd_project(ds, states, mode="fp32", stats=True)
+            torch.cuda.synchronize()
+            walls.append(time.time() - t)
+            scans.append(st["scan_ms"])
+        wall, scan = sum(walls) / len(walls), sum(scans) / len(scans)
+        same = bool(np.array_equal(i32.cpu().numpy(), idx_mixed))
+        ach = FLOPS_PER_PAIR * N * m / (scan / 1e3) / 1e12
+        fp32 = {"proj_per_s": round(m / wall, 2), "ms_per_step": round(wall * 1e3, 2),
+                "scan_ms": round(scan, 2), "achieved_tflops": round(ach, 2),
+                "frac_fp32_mfma": round(ach / FP32_PEAK_TFLOPS, 4),
+                "kernel": "scan32_kernel (v_mfma_f32_32x32x2_f32, K=12, norms as accumulator input)",
+                "candidates_per_query": round(st["candidates"] / m, 3),
+                "fallback_queries": st["overflowed"], "indices_equal_mixed": same,
+                "dist_equal_mixed": bool(np.array_equal(d32.cpu().numpy(), dist_mixed))}
+        log(f"fp32: {wall * 1e3:.1f} ms/step, scan {scan:.1f} ms ({ach:.1f} TFLOP/s, "
+            f"{ach / FP32_PEAK_TFLOPS:.3f} of peak), indices equal to {args.mode}: {same}")
+
     dd = None
     if args.dd_solves > 0:
         dd = dd_solve_latency(L, C, args.dd_solves)
@@ -615,26 +694,36 @@ def main():
         kmeans = ann_leg(L, C, args.steps, index="kmeans", fds=(0.5, 0.8))
     serving = None
     if args.serve_solves > 0:
-        serving = serve_leg(L, C, args.serve_solves)
+        serving = serve_leg(L, C, args.serve_solves, modes=tuple(args.serve_modes.split(",")))
     paper = None
     if args.paper_seeds > 0:
         paper = paper_leg(L, seeds=args.paper_seeds)
 
     cpu = None
     if not args.skip_cpu:
+        # the oracle's whitened brute force (equal to its raw-metric form on the
+        # N = 65536 workload, a CPU test) over a sample of the queries against
+        # all N points; the whitening of the data set is set-up, not timed
         import oracle
         k = args.cpu_queries
+        W = oracle.whiten(e, s, C)
+        QW = oracle.whiten(qe[:k], qs[:k], C)
         t = time.time()
-        oi, od, o2 = oracle.pd_raw(e, s, C, qe[:k], qs[:k])
+        oi, od, o2 = oracle.pd_white(W, QW)
         cpu_s = time.time() - t
+        del W
         clear = o2 > od * (1 + 1e-12)
         agree = bool(np.array_equal(oi[clear], idx_mixed[:k][clear]))
+        host = host_cpu()
         cpu = {"value": round(k / cpu_s, 4), "unit": "projections/s", "cores": oracle.threads(),
                "kind": "oracle",
-               "sample": f"{k} of the {m} queries against all N={N} points, raw-metric FP64 "
-                         f"brute force, {cpu_s:.1f}s",
-               "indices_equal_gpu": agree}
-        log(f"cpu oracle: {k} queries in {cpu_s:.1f}s ({oracle.threads()} threads), agree={agree}")
+               "sample": f"{k} of the {m} queries against all N={N} points, the oracle's "
+                         f"whitened FP64 brute force (1/2 |q - x|^2 in index order, OpenMP over "
+                         f"queries), {cpu_s:.1f}s",
+               "per_core": round(k / cpu_s / oracle.threads(), 4),
+               "host": host, "indices_equal_gpu": agree}
+        log(f"cpu oracle: {k} queries in {cpu_s:.1f}s ({oracle.threads()} threads, {host}), "
+            f"agree={agree}")
 
     out = {
         "metric": "NN projections/s at N=2^27 (FP64 scan vs BF16+rerank); p50/p99 DD solve latency",
@@ -649,6 +738,7 @@ def main():
                    "slow_tiles_per_step": slow / args.steps, "tile": args.tile},
         "roofline": roofline,
         "fp64_scan": fp64,
+        "fp32_scan": fp32,
         "exact_tree_walk": walk,
         "dd_solve": dd,
         "ann": ann,

@@ -67,7 +67,10 @@ typedef enum dd_mode {
    * form), candidates inside a proven FP64 error margin reranked in the direct
    * FP64 form.  Exact (indices of the FP64 nearest neighbour). */
   DD_EXACT_FP64 = 0,
-  /* FP32 MFMA scan + FP64 rerank of the certified candidates.  Exact. */
+  /* FP32 MFMA scan of the whole data set (pack DD_PACK_FP32, expanded form
+   * with the stored FP32 norms), every candidate inside the proven FP32 error
+   * margin a = 2^-18 (|q| + max|x|)^2 reranked in the direct FP64 form; queries
+   * whose candidate lists overflow are rescanned in FP64.  Exact. */
   DD_MIXED_FP32 = 1,
   /* BF16 MFMA scan with FP32 accumulation on tile-centred coordinates, every
    * candidate inside the proven BF16 error margin reranked in FP64; queries
@@ -102,7 +105,8 @@ typedef enum dd_mode {
 } dd_mode;
 
 /* Packs a dataset can hold (dd_dataset_opts.packs bit mask). */
-#define DD_PACK_FP64 0x1u   /* whitened FP64 [N][12] + norms: DD_EXACT_FP64, DD_DIRECT_FP64, rerank */
+#define DD_PACK_FP64 0x1u   /* whitened FP64 [N][12] + norms: DD_EXACT_FP64, DD_DIRECT_FP64, the
+                               rerank and fallback of every mode; every dataset holds it */
 #define DD_PACK_FP32 0x2u   /* whitened FP32 [N][12] + norms: DD_MIXED_FP32 */
 #define DD_PACK_BF16 0x4u   /* tile-centred BF16 [N][16] + tile centres/radii: DD_MIXED_BF16 */
 #define DD_PACK_FP16 0x8u   /* tile-centred FP16 [N][16]: DD_MIXED_FP16 */
@@ -142,7 +146,8 @@ typedef struct dd_project_opts {
   int32_t ann_budget;       /* DD_ANN, DD_KMEANS: max leaves visited per query;
                                0 = unlimited (exact) */
   int32_t passes;           /* 16-bit modes: 1 = marking pass only, 2 = a bound-seeding pass over
-                               every 64th tile first; 0 = automatic (2 without a warm start) */
+                               every 64th tile first; 0 = automatic (2 without a warm start);
+                               any other value is DD_ERR_ARG */
   dd_project_stats* stats;  /* optional host pointer; filling it synchronises the stream */
   double ann_radius_discount;  /* DD_KMEANS: 1 - f_d in [0, 1], the part of a child's radius
                                   the ball test |q - c| - f_d r leaves out (Section 4.2):
@@ -239,6 +244,8 @@ dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
  *   kind 3: round A[512] (taken as FP32) to bf16 with the packed conversion of
  *           the query operands and widen back into D[512] (B unused)
  *   kind 4: the same for IEEE half
+ *   kind 5: fp32 32x32x2 (A [32][2], B [2][32], D [32][32]) with the accumulator
+ *           input C[i][j] = i (the role of the FP32 scan's row norms): D = A B + C
  * Arrays are row-major float64 host memory; D is written.  Synchronous.
  */
 dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D);
@@ -259,7 +266,8 @@ typedef struct dd_solve_opts {
   int32_t max_iter;      /* 0 = 500 */
   int32_t mode;          /* projection mode (dd_mode), default DD_EXACT_FP64 */
   int32_t cg_max_iter;   /* 0 = 20000 */
-  int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG */
+  int32_t flags;         /* DD_SOLVE_NO_GRAPH: launch the CG kernels one by one; DD_SOLVE_CG,
+                            DD_SOLVE_SKIP, DD_SOLVE_LOCAL_ACCURACY (below) */
   double cg_tol;         /* relative residual of the two P_C solves; 0 = 1e-13 */
   int32_t ann_budget;    /* DD_ANN, DD_KMEANS: leaves per projection (0 = exact walk) */
   int32_t ann_ramp;      /* DD_ANN, DD_KMEANS: > 0 = accuracy schedule.  With a budget,
@@ -290,6 +298,16 @@ typedef struct dd_solve_opts {
  * change, by the triangle inequality: the paper's criterion for unmoved
  * queries).  The walk then certifies two neighbours; results are unchanged. */
 #define DD_SOLVE_SKIP 0x4
+/* Approximate DD_ANN and DD_KMEANS solves (a budget or f_d < 1): the accuracy of
+ * each material point's search also depends on the distances (Section 4: the
+ * accuracy parameter as a function of the global distance, the local distance
+ * and the iteration).  From the second iteration on, with rho = d_e / dbar
+ * (d_e the point's distance to its association after the previous projection,
+ * dbar = D_full / sum of the weights), a point at least as far from the data
+ * as the mean keeps the schedule's f_d and leaf budget, a nearer one gets
+ * f_d + (1 - f_d)(1 - rho) and budget * ceil(1 / rho) leaves (at most 16 times
+ * the budget): points closing in on the data search more accurately. */
+#define DD_SOLVE_LOCAL_ACCURACY 0x8
 
 /* Results of dd_solve; every array is HOST memory provided by the caller and
  * may be NULL when not wanted. */
@@ -390,7 +408,12 @@ typedef struct dd_server_stats {
 /*
  * Create a server over ds (which must outlive it).  hbm_budget_bytes bounds the
  * summed device footprint of admitted solves (their P_C buffers, states and
- * projection scratch); 0 = half of the free device memory.  opts NULL = BF16
+ * projection scratch) plus the K^-1 inverses the server forms (from admission
+ * of the solve that needs one, and for as long as the dataset's cache keeps
+ * it); an inverse is formed on a builder thread while the other solves go on,
+ * and a solve whose inverse cannot fit next to it even on an idle server is
+ * run by CG (dd_solve's DD_SOLVE_CG trajectory); 0 = half of the free device
+ * memory.  opts NULL = BF16
  * projections, defaults above.  Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED (mode
  * without its pack), DD_ERR_OOM, DD_ERR_DEVICE.
  */

@@ -237,7 +237,7 @@ def dd_metric_pca(strain, stress, stream=None) -> np.ndarray:
 def dd_selftest_mfma(kind: int, A: np.ndarray, B: np.ndarray) -> np.ndarray:
     A = np.ascontiguousarray(A, dtype=np.float64)
     B = np.ascontiguousarray(np.zeros(1) if B is None else B, dtype=np.float64)
-    shape = (16, 16) if kind == 2 else ((512,) if kind >= 3 else (32, 32))
+    shape = (16, 16) if kind == 2 else ((512,) if kind in (3, 4) else (32, 32))
     D = np.zeros(shape, dtype=np.float64)
     _check(_lib.dd_selftest_mfma(kind, A.ctypes.data, B.ctypes.data, D.ctypes.data),
            "dd_selftest_mfma")
@@ -290,11 +290,13 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
              max_iter: int = 500, history: bool = False, cg_tol: float = 0.0,
              cg_max_iter: int = 0, graph: bool = True, ann_budget: int = 0, cg: bool = False,
              ann_ramp: int = 0, skip: bool = False, dirichlet_values=None, stream=None,
-             ann_fd: float | None = None):
+             ann_fd: float | None = None, local_accuracy: bool = False):
     """dd_solve: mesh = (nx, ny, nz[, lx, ly, lz]); host numpy mask/force/init arrays.
 
     ann_fd is the final f_d of the k-means walk (None = 1, exact), passed as
     ann_radius_discount = 1 - f_d; with ann_ramp it is reached linearly from 0.
+    local_accuracy sets DD_SOLVE_LOCAL_ACCURACY (per-point accuracy from the
+    local and global distances).
 
     Returns a dict with u, idx, eps, sig, d_half, d_full, changed, history
     (when requested), iterations, converged, cg_iterations, cg_max_residual,
@@ -321,7 +323,8 @@ def dd_solve(ds: Dataset, mesh, dirichlet_mask, nodal_force, init_idx, mode="fp6
     if dirichlet_values is not None:
         dv = np.ascontiguousarray(np.asarray(dirichlet_values, dtype=np.float64).reshape(n_dof))
     opts = dd_solve_opts(max_iter, MODES[mode] if isinstance(mode, str) else int(mode),
-                         cg_max_iter, (0 if graph else 1) | (2 if cg else 0) | (4 if skip else 0),
+                         cg_max_iter, (0 if graph else 1) | (2 if cg else 0) | (4 if skip else 0)
+                         | (8 if local_accuracy else 0),
                          cg_tol, ann_budget, ann_ramp, dv.ctypes.data if dv is not None else None,
                          0.0 if ann_fd is None else 1.0 - float(ann_fd))
     st = _lib.dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,

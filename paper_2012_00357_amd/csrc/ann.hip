@@ -78,6 +78,10 @@ struct AnnArgs {
   const uint32_t* slot_pos;
   const uint32_t* pos_slot;
   float fd;
+  // optional per-query accuracy (indexed by query): radius factor of the
+  // k-means walk and leaf budget, replacing fd and budget
+  const float* fd_q;
+  const int* budget_q;
   double* dist2;                  // TOP2: distance to the second nearest point (1/2 d^2)
   int* fb_list;
   int* fb_count;
@@ -305,6 +309,8 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   const int64_t p = (int64_t)blockIdx.x * kWaves + wv;
   if (p >= list_len(A.L)) return;
   const int64_t q = list_query(A.L, p);
+  const float fd = (KMT && A.fd_q) ? A.fd_q[q] : A.fd;
+  const int budget = A.budget_q ? A.budget_q[q] : A.budget;
   if (A.invalid[q]) {
     if (lane == 0) {
       A.out.idx[q] = -1;
@@ -338,7 +344,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   float U1 = INFINITY;
   // approximate k-means search: Ua, the best upper bound over the points the
   // walk has evaluated, decides which branches are entered
-  const bool approx = KMT && A.fd != 1.0f;
+  const bool approx = KMT && fd != 1.0f;
   float Ua = INFINITY;
   int nc = 0;
   bool ovf = false;
@@ -386,7 +392,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
       const float delta = kEps20 * amax + 1e-30f;
       if (lane < cnt) {
         float dc;
-        const float lb = record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, A.fd,
+        const float lb = record_lb(A.kmt_child + kKmtRecord * (c0 + lane), qf, yq, slack, fd,
                                    plo, phi, delta, val, dc);
         if (lb <= (approx ? Ua : U)) {
           bnd = fmaxf(lb, 0.0f);
@@ -516,7 +522,7 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     }
     __builtin_amdgcn_wave_barrier();
     nc += cnt;
-    if (A.budget > 0 && leaves >= (unsigned long long)A.budget) stop = true;
+    if (budget > 0 && leaves >= (unsigned long long)budget) stop = true;
   };
 
   auto expand_node = [&](uint32_t node) __attribute__((always_inline)) {
@@ -643,8 +649,8 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
                           const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
                           unsigned long long* counters, double* dist2, hipStream_t st, bool kmt,
-                          double fd) {
-  if (dist2 && (budget != 0 || (kmt && fd != 1.0)))
+                          double fd, const float* fd_q, const int* budget_q) {
+  if (dist2 && (budget != 0 || (kmt && fd != 1.0) || fd_q || budget_q))
     return set_error(DD_ERR_ARG, "second distances need the exact walk");
   if (!(fd >= 0.0 && fd <= 1.0)) return set_error(DD_ERR_ARG, "f_d must be in [0, 1]");
   if (len_max <= 0) return DD_OK;
@@ -678,6 +684,8 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
   for (int i = 0; i < 144; ++i) A.V[i] = D.V[i];
   A.xmax = __builtin_nextafterf((float)D.xmax, INFINITY);
   A.budget = budget;
+  A.fd_q = kmt ? fd_q : nullptr;
+  A.budget_q = budget_q;
   A.L = L;
   A.qw = Q.qw;
   A.qn2 = Q.qn2;

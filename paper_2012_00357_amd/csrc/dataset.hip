@@ -196,22 +196,38 @@ __global__ __launch_bounds__(256) void tile_stats_kernel(const double* __restric
   }
 }
 
+// Tile centres and radii to the scaled coordinates of the 16-bit scans.  The
+// scale is a power of two, so the products are exact for normal values; the
+// radius keeps its absolute floor so that it still bounds the scaled offsets
+// where they fall into the subnormal range.
+__global__ void scale_tiles_kernel(int64_t n_tiles, float scale, float* __restrict__ centre,
+                                   float* __restrict__ radius) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  for (int k = 0; k < 12; ++k) centre[12 * t + k] *= scale;
+  radius[t] = radius[t] * scale + 1e-30f;
+}
+
 // 16-bit tile-centred pack: row j of tile T holds
-//   (-2 x'_0 .. -2 x'_11, n_hi, n_mid, n_lo, 0),  x' = round16(x_j - c_T),
-//   n = |x'|^2 (exact in FP64) split into three 16-bit terms.
-// Padding rows: zeros with n_hi = kPadNorm (never a candidate).
+//   (-2 x'_0 .. -2 x'_11, n_hi, n_mid, n_lo, 0),  x' = round16(s x_j - c_T),
+//   n = |x'|^2 (exact in FP64) split into three 16-bit terms,
+// with s the dataset's power-of-two scale and c_T the scaled tile centre.
+// Padding rows (the tail of the last tile) repeat the last point, so that every
+// score a scan forms is the distance to a real point; the extraction and the
+// merge never report a row >= N.
 template <class T16>
 __global__ void pack16_kernel(const double* __restrict__ w, int64_t n, int64_t n_rows, int tile,
-                              const float* __restrict__ centre, uint16_t* __restrict__ out) {
+                              double scale, const float* __restrict__ centre,
+                              uint16_t* __restrict__ out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
   uint16_t row[16];
-  if (i < n) {
-    const double* x = w + 12 * i;
+  {
+    const double* x = w + 12 * (i < n ? i : n - 1);   // row n - 1 lies in the last tile too
     const float* c = centre + 12 * (i / tile);
     double nn = 0.0;
     for (int k = 0; k < 12; ++k) {
-      float xf = (float)(x[k] - (double)c[k]);
+      float xf = (float)(x[k] * scale - (double)c[k]);
       uint16_t b = T16::from_float(xf);
       double v = (double)T16::to_float(b);
       nn = fma(v, v, nn);
@@ -226,9 +242,6 @@ __global__ void pack16_kernel(const double* __restrict__ w, int64_t n, int64_t n
     row[13] = mid;
     row[14] = lo;
     row[15] = 0;
-  } else {
-    for (int k = 0; k < 16; ++k) row[k] = 0;
-    row[12] = T16::from_float(kPadNorm);
   }
   uint4 a, b;
   a.x = row[0] | ((uint32_t)row[1] << 16);
@@ -429,6 +442,41 @@ struct FillSource : Source {
   }
 };
 
+// Scale of the 16-bit scans (see Scale16): the power of two s that brings the
+// largest tile radius into [1, 2), bounded so that the scaled centres stay far
+// inside the FP32 range; then the scaled mean of the data and, per format, the
+// query radius around it inside which the centred query coordinates cannot
+// overflow.  Scales the tile centres and radii in place.
+static dd_status choose_scale16(Dataset& D, hipStream_t st) {
+  std::vector<float> cen(12 * (size_t)D.n_tiles), rad((size_t)D.n_tiles);
+  DD_HIP(hipMemcpyAsync(cen.data(), D.centre.p, sizeof(float) * cen.size(), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipMemcpyAsync(rad.data(), D.radius.p, sizeof(float) * rad.size(), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  double rmax = 0.0, cmax = 0.0;
+  for (float r : rad) rmax = std::max(rmax, (double)r);
+  for (float c : cen) cmax = std::max(cmax, std::fabs((double)c));
+  int k = -(int)std::floor(std::log2(std::max(rmax, 1e-300)));
+  k = std::max(-100, std::min(k, 100));
+  while (k > -100 && std::ldexp(std::max(cmax, rmax), k) > 0x1p100) --k;
+  const double s = std::ldexp(1.0, k);
+  D.sc16.s = (float)s;
+  double span = 0.0;
+  for (int k2 = 0; k2 < 12; ++k2) D.sc16.mean[k2] = (float)(D.mean[k2] * s);
+  for (int64_t t = 0; t < D.n_tiles; ++t) {
+    double a = 0.0;
+    for (int k2 = 0; k2 < 12; ++k2) {
+      const double d = (double)cen[12 * t + k2] * s - (double)D.sc16.mean[k2];
+      a += d * d;
+    }
+    span = std::max(span, std::sqrt(a));
+  }
+  D.span16 = span * (1.0 + 1e-6);
+  hipLaunchKernelGGL(scale_tiles_kernel, dim3(grid_for(D.n_tiles)), dim3(256), 0, st, D.n_tiles,
+                     (float)s, D.centre.as<float>(), D.radius.as<float>());
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
 static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_dataset_opts* opts,
                              hipStream_t st, Dataset& D) {
   uint32_t packs = (opts && opts->packs) ? opts->packs : DD_PACK_DEFAULT;
@@ -439,11 +487,9 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN |
                 DD_PACK_KMEANS))
     return set_error(DD_ERR_ARG, "unknown pack bits");
-  // the ANN tree and its compact leaves are built from the sorted FP64 pack,
-  // which also serves its rerank; so are the 16-bit packs
-  if (packs & (DD_PACK_ANN | DD_PACK_KMEANS)) packs |= DD_PACK_FP64;
-  if (packs & (DD_PACK_BF16 | DD_PACK_FP16)) packs |= DD_PACK_FP64;
-  if (!(packs & (DD_PACK_FP64 | DD_PACK_FP32))) packs |= DD_PACK_FP64;
+  // every dataset holds the FP64 pack: the trees and the 16-bit packs are built
+  // from it, and the FP64 rerank, the fallback scans and dd_solve read it
+  packs |= DD_PACK_FP64;
   D.N = N;
   D.packs = packs;
   D.tile = tile;
@@ -602,17 +648,18 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
     hipLaunchKernelGGL(tile_stats_kernel, dim3((unsigned)D.n_tiles), dim3(256), 0, st,
                        D.w64.as<double>(), N, tile, D.centre.as<float>(), D.radius.as<float>());
     DD_HIP(hipGetLastError());
+    DD_TRY(choose_scale16(D, st));
     if (packs & DD_PACK_BF16) {
       DD_TRY(D.wbf16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
       hipLaunchKernelGGL(pack16_kernel<Bf16>, dim3(grid_for(rows)), dim3(256), 0, st,
-                         D.w64.as<double>(), N, rows, tile, D.centre.as<float>(),
+                         D.w64.as<double>(), N, rows, tile, (double)D.sc16.s, D.centre.as<float>(),
                          D.wbf16.as<uint16_t>());
       DD_HIP(hipGetLastError());
     }
     if (packs & DD_PACK_FP16) {
       DD_TRY(D.wfp16.alloc(sizeof(uint16_t) * 16 * (size_t)rows));
       hipLaunchKernelGGL(pack16_kernel<Fp16>, dim3(grid_for(rows)), dim3(256), 0, st,
-                         D.w64.as<double>(), N, rows, tile, D.centre.as<float>(),
+                         D.w64.as<double>(), N, rows, tile, (double)D.sc16.s, D.centre.as<float>(),
                          D.wfp16.as<uint16_t>());
       DD_HIP(hipGetLastError());
     }

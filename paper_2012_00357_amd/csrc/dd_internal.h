@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/dd.h"
+#include "pack16.h"
 
 namespace dd {
 
@@ -132,11 +133,13 @@ struct Dataset {
   DevBuf w32;      // float [n_pad32][12]
   DevBuf n32;      // float [n_pad32] |x|^2 of the FP32 values (padding: +inf)
   double xmax32 = 0;
-  // 16-bit packs (tile-centred)
+  // 16-bit packs (tile-centred), in coordinates scaled by sc16.s (a power of two)
   int tile = 256;
   int64_t n_tiles = 0;
-  DevBuf centre;   // float [n_tiles][12]
-  DevBuf radius;   // float [n_tiles]  upper bound of |x_j - c_T| over the tile
+  DevBuf centre;   // float [n_tiles][12] scaled tile centres
+  DevBuf radius;   // float [n_tiles]  upper bound of |s x_j - c_T| over the tile
+  Scale16 sc16{1.0f, 0.0f, {0}};   // scale and scaled data mean (far set per format)
+  double span16 = 0.0;             // max_T |c_T - scaled mean|
   DevBuf wbf16;    // uint16 [n_tiles*tile][16]
   DevBuf wfp16;    // uint16 [n_tiles*tile][16]
   // principal axes of the whitened data (sample estimate): V[12*k + a] is

@@ -8,8 +8,23 @@ namespace dd {
 // Rows per LDS tile of the FP64 and FP32 scans (padding granularity of those packs).
 constexpr int kTile64 = 128;
 constexpr int kTile32 = 256;
-// Norm slot of padding rows in the 16-bit packs: far above any real score.
-constexpr float kPadNorm = 30000.0f;
+
+// Coordinates of the 16-bit scans: the whitened data, tile centres, radii and
+// queries multiplied by a per-dataset power of two s, chosen so that the
+// largest tile radius lies in [1, 2).  The scaling is exact (no rounding), so
+// the certified bounds hold unchanged in the scaled units, and it keeps |x'|^2
+// inside the FP16 range whatever the units of the data (Pa or MPa).  A query
+// is scanned only while |s q - mean| < far (else its candidate list stays
+// empty and the FP64 fallback answers it): with far = limit - max_T |c_T - mean|
+// every centred query coordinate stays below the limit, far below the largest
+// finite value of the format.
+struct Scale16 {
+  float s;          // power of two
+  float far;        // <= 0: no query is scanned in this format
+  float mean[12];   // scaled mean of the data
+};
+constexpr float kFarLimitFp16 = 16384.0f;
+constexpr float kFarLimitBf16 = 1.0e30f;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;

@@ -174,6 +174,35 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
   return DD_OK;
 }
 
+// FP32 MFMA scan over list L, merge and FP64 rerank; the queries whose lists
+// overflowed (or that the scan leaves out) go to the FP64 MFMA scan.
+dd_status mixed32(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max, int splits,
+                  Outputs out, Scratch& sc, int* d_counters, hipStream_t st, int64_t* n_fallback,
+                  Timing* tm) {
+  const int64_t qblocks = (len_max + 255) / 256;
+  const int S = choose_splits(qblocks, D.n_pad32 / kTile32, splits);
+  CandBuf cb;
+  DD_TRY(alloc_cands(sc, len_max, S, 2, 16, cb));
+  if (tm) DD_TRY(tm->mark(1, st));
+  DD_TRY(launch_scan32(D, Q, L, len_max, cb, st));
+  if (tm) DD_TRY(tm->mark(2, st));
+  int* fb = nullptr;
+  DD_TRY(sc.get(fb, (size_t)len_max));
+  unsigned long long* n_cand =
+      (tm && tm->on) ? reinterpret_cast<unsigned long long*>(d_counters + 2) : nullptr;
+  DD_TRY(launch_merge_rerank(D, Q, L, len_max, cb, nullptr, out, fb, d_counters, n_cand, st));
+  uint32_t* hw = sc.host_word(1);
+  DD_HIP(hipMemcpyAsync(hw, d_counters, sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  const int h = (int)*hw;
+  if (n_fallback) *n_fallback += h;
+  if (h > 0) {
+    QueryList L1{fb, d_counters, h};
+    DD_TRY(exact64(D, Q, L1, h, 0, out, sc, d_counters, st, nullptr, nullptr));
+  }
+  return DD_OK;
+}
+
 }  // namespace
 
 }  // namespace dd
@@ -183,7 +212,8 @@ namespace dd {
 dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
                           int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
-                          hipStream_t st);
+                          hipStream_t st, const float* fd_q = nullptr,
+                          const int* budget_q = nullptr);
 
 dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                        const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
@@ -193,11 +223,13 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
 }
 
 // As project_impl; dist2_out_dev (exact DD_ANN only) receives the distance to
-// the second nearest point, -1 where it is not certified.
+// the second nearest point, -1 where it is not certified; fd_q / budget_q
+// (walk modes, device arrays over the m states) give each state its own
+// radius factor and leaf budget.
 dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
                           int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
-                          hipStream_t st) {
+                          hipStream_t st, const float* fd_q, const int* budget_q) {
   if (m < 0 || m > 0x7FFFFFFFll) return set_error(DD_ERR_ARG, "m must be in [0, 2^31-1]");
   if (m == 0) return DD_OK;
   if (!states_dev || !idx_out_dev) return set_error(DD_ERR_ARG, "NULL states or idx_out");
@@ -206,6 +238,8 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   if (splits < 0) return set_error(DD_ERR_ARG, "splits must be >= 0");
   const int budget = opts ? opts->ann_budget : 0;
   if (budget < 0) return set_error(DD_ERR_ARG, "ann_budget must be >= 0");
+  if (opts && (opts->passes < 0 || opts->passes > 2))
+    return set_error(DD_ERR_ARG, "passes must be 0, 1 or 2");
   const double discount = opts ? opts->ann_radius_discount : 0.0;
   if (!(discount >= 0.0 && discount <= 1.0))
     return set_error(DD_ERR_ARG, "ann_radius_discount must be in [0, 1]");
@@ -216,6 +250,10 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     case DD_EXACT_FP64:
     case DD_DIRECT_FP64:
       if (!(D.packs & DD_PACK_FP64)) return set_error(DD_ERR_UNSUPPORTED, "dataset has no FP64 pack");
+      break;
+    case DD_MIXED_FP32:
+      if (!(D.packs & DD_PACK_FP32) || !(D.packs & DD_PACK_FP64))
+        return set_error(DD_ERR_UNSUPPORTED, "FP32 mode needs the FP32 and FP64 packs");
       break;
     case DD_MIXED_BF16:
       if (!(D.packs & DD_PACK_BF16) || !(D.packs & DD_PACK_FP64))
@@ -256,7 +294,9 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   int* counters = nullptr;
   DD_TRY(sc.get(counters, kNumCounters));
   DD_HIP(hipMemsetAsync(counters, 0, kNumCounters * sizeof(int), st));
-  DD_TRY(prepare_queries(D, states_dev, whitened, m, warm_start_idx_dev, Q, st));
+  const bool scan16 = (mode == DD_MIXED_BF16 || mode == DD_MIXED_FP16);
+  DD_TRY(prepare_queries(D, states_dev, whitened, m, warm_start_idx_dev,
+                         scan16 ? (double)D.sc16.s : 1.0, Q, st));
   Outputs out{idx_out_dev, dist_out_dev};
   QueryList all{nullptr, nullptr, m};
   int64_t n_fallback = 0;
@@ -269,6 +309,8 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(timing.mark(2, st));
   } else if (mode == DD_EXACT_FP64) {
     DD_TRY(exact64(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));
+  } else if (mode == DD_MIXED_FP32) {
+    DD_TRY(mixed32(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));
   } else if (walk_mode(mode)) {
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
@@ -277,7 +319,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     if (dist2_out_dev && (budget != 0 || fd < 1.0))
       return set_error(DD_ERR_ARG, "second distances need the exact walk");
     DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb, counters, ann,
-                           dist2_out_dev, st, mode == DD_KMEANS, fd));
+                           dist2_out_dev, st, mode == DD_KMEANS, fd, fd_q, budget_q));
     DD_TRY(timing.mark(2, st));
     uint32_t* hw = sc.host_word(1);
     DD_HIP(hipMemcpyAsync(hw, counters, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -392,13 +434,14 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
                            double* dist_out, hipStream_t st, double* dist2_out, double fd,
-                           int passes) {
+                           int passes, const float* fd_q, const int* budget_q) {
   dd_project_opts o{};
   o.mode = mode;
   o.passes = passes;
   o.ann_budget = ann_budget;
   o.ann_radius_discount = 1.0 - fd;
-  return project_impl_ex(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, dist2_out, st);
+  return project_impl_ex(D, qw_dev, true, m, warm_dev, &o, idx_out, dist_out, dist2_out, st, fd_q,
+                         budget_q);
 }
 
 }  // namespace dd

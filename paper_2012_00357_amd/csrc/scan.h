@@ -9,7 +9,8 @@ struct QueryPrep {
   double* qw = nullptr;     // [m][12] whitened queries (zero rows for invalid states)
   double* qn2 = nullptr;    // [m] |q|^2
   double* u64 = nullptr;    // [m] FP64-path initial bound on min d (warm start) or +inf
-  float* u32 = nullptr;     // [m] sqrt-space initial bound (warm start) or +inf
+  float* u32 = nullptr;     // [m] sqrt-space initial bound (warm start) or +inf, in the
+                            // scaled coordinates of the 16-bit scans in those modes
   int* invalid = nullptr;   // [m] 1 for non-finite states
 };
 
@@ -35,12 +36,17 @@ struct Outputs {
   double* dist = nullptr;       // [m] 1/2 d^2 or nullptr
 };
 
-// Whiten m states (or take them as already whitened), |q|^2, warm-start bounds.
+// Whiten m states (or take them as already whitened), |q|^2, warm-start bounds
+// (the sqrt-space one multiplied by u32_scale: the 16-bit scans' scale, else 1).
 dd_status prepare_queries(const Dataset& D, const double* states, bool whitened, int64_t m,
-                          const int64_t* warm, QueryPrep& Q, hipStream_t st);
+                          const int64_t* warm, double u32_scale, QueryPrep& Q, hipStream_t st);
 
 // FP64 MFMA scan (expanded form) over the list; fills cb (P = 4, d-space bounds).
 dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len,
+                        const CandBuf& cb, hipStream_t st);
+// FP32 MFMA scan (expanded form, stored norms as the accumulator input) over the
+// list; fills cb (P = 2, d-space bounds), like the FP64 scan.
+dd_status launch_scan32(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len,
                         const CandBuf& cb, hipStream_t st);
 // 16-bit MFMA scan over tile-centred data (sqrt-space bounds), in phases:
 //   kBound    streaming pass: U_out[p][S] = split bounds (tiles visited with stride)
@@ -103,10 +109,13 @@ int choose_splits16(int64_t n_query_blocks, int64_t n_tiles, int requested);
 // budget = max leaves per query, 0 = exact.
 // With dist2 (exact walk only) the walk certifies the two nearest points and
 // writes the second distance (1/2 d^2; -1 when the query went to the fallback).
+// fd_q / budget_q (device, indexed by query, optional): per-query radius factor
+// (k-means walk) and leaf budget in place of fd and budget.
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
                           const int64_t* warm, int budget, Outputs out, int* fb_list, int* fb_count,
                           unsigned long long* counters, double* dist2, hipStream_t st,
-                          bool kmt = false, double fd = 1.0);
+                          bool kmt = false, double fd = 1.0, const float* fd_q = nullptr,
+                          const int* budget_q = nullptr);
 
 // u32[q] = min(u32[q], min over the S split bounds U[p][S]).
 dd_status launch_reduce_bounds(QueryList L, int64_t list_len_max, const float* U, int S, float* u32,

@@ -60,9 +60,10 @@ struct Mats {
 __global__ void prep_kernel(const double* __restrict__ states, int64_t m, Mats M,
                             const int64_t* __restrict__ warm, int64_t N,
                             const uint32_t* __restrict__ iperm, const double* __restrict__ w64,
-                            const float* __restrict__ w32, double* __restrict__ qw,
-                            double* __restrict__ qn2, double* __restrict__ u64,
-                            float* __restrict__ u32, int* __restrict__ invalid) {
+                            const float* __restrict__ w32, double u32_scale,
+                            double* __restrict__ qw, double* __restrict__ qn2,
+                            double* __restrict__ u64, float* __restrict__ u32,
+                            int* __restrict__ invalid) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   double y[12];
@@ -102,7 +103,7 @@ __global__ void prep_kernel(const double* __restrict__ states, int64_t m, Mats M
       }
       // the FP64 sum carries at most ~13 ulp of relative error: inflate by 2^-40
       ub = d * (1.0 + 0x1p-40) + 1e-300;
-      ub32 = __double2float_ru(sqrt(ub) * (1.0 + 0x1p-40));
+      ub32 = __double2float_ru(sqrt(ub) * (1.0 + 0x1p-40) * u32_scale);
     }
   }
   u64[i] = ub;
@@ -110,7 +111,7 @@ __global__ void prep_kernel(const double* __restrict__ states, int64_t m, Mats M
 }
 
 dd_status prepare_queries(const Dataset& D, const double* states, bool whitened, int64_t m,
-                          const int64_t* warm, QueryPrep& Q, hipStream_t st) {
+                          const int64_t* warm, double u32_scale, QueryPrep& Q, hipStream_t st) {
   Mats M;
   for (int i = 0; i < 36; ++i) {
     const double id = (i % 7 == 0) ? 1.0 : 0.0;   // identity: states already whitened
@@ -118,8 +119,8 @@ dd_status prepare_queries(const Dataset& D, const double* states, bool whitened,
     M.G[i] = whitened ? id : D.G[i];
   }
   hipLaunchKernelGGL(prep_kernel, dim3(grid1(m)), dim3(256), 0, st, states, m, M, warm, D.N,
-                     D.iperm.as<uint32_t>(), D.w64.as<double>(), D.w32.as<float>(), Q.qw, Q.qn2,
-                     Q.u64, Q.u32, Q.invalid);
+                     D.iperm.as<uint32_t>(), D.w64.as<double>(), D.w32.as<float>(), u32_scale,
+                     Q.qw, Q.qn2, Q.u64, Q.u32, Q.invalid);
   DD_HIP(hipGetLastError());
   return DD_OK;
 }

@@ -5,6 +5,7 @@
 // semantics (its inputs are finite: invalid queries are zeroed by the
 // preparation kernel), so that min reductions of matrix-core results need no
 // canonicalisation, and with matrix results kept in ordinary VGPRs.
+#include <algorithm>
 #include <cmath>
 
 #include "pack16.h"
@@ -13,6 +14,18 @@
 namespace dd {
 
 __device__ static inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }   // 1 ulp
+
+// Running minimum over 16 new values: 17 inputs, eight 3-input minima.
+__device__ inline float min16(float run, const f32x16_t& a) {
+  float m0 = fminf(fminf(a[0], a[1]), a[2]);
+  float m1 = fminf(fminf(a[3], a[4]), a[5]);
+  float m2 = fminf(fminf(a[6], a[7]), a[8]);
+  float m3 = fminf(fminf(a[9], a[10]), a[11]);
+  float m4 = fminf(fminf(a[12], a[13]), a[14]);
+  float m5 = fminf(fminf(m0, m1), m2);
+  float m6 = fminf(fminf(m3, m4), a[15]);
+  return fminf(fminf(run, m5), m6);
+}
 
 // ---------------------------------------------------------------------------
 // FP64 MFMA scan.  v_mfma_f64_16x16x4: A (16 data rows x 4 k) one double per
@@ -164,6 +177,195 @@ dd_status launch_scan64(const Dataset& D, const QueryPrep& Q, QueryList L, int64
 }
 
 // ---------------------------------------------------------------------------
+// FP32 MFMA scan.  v_mfma_f32_32x32x2_f32: A (32 data rows x 2 k): lane supplies
+// row lane%32, k = lane/32; B (2 k x 32 queries): lane supplies query lane%32,
+// k = lane/32; C and D: lane holds rows 8*(i/4) + 4*(lane/32) + i%4 (i < 16) of
+// query lane%32.  Six MFMAs cover K = 12 with the data rows x^ = fl32(x) and
+// the query column -2 q^, q^ = fl32(q); the accumulator input of the first is
+// the rows' stored norms n^ = fl32(|x^|^2), so the matrix core returns
+// s_j = n^_j - 2 q^.x^_j and d~_j = s_j + o, o = fl32(|q^|^2).
+//
+// Bound (d-space, u = 2^-24, Q = |q|, X >= max |x|): the stored operands move
+// |q - x| by at most u (Q + X), hence |q - x|^2 by at most (2u + u^2)(Q + X)^2;
+// the thirteen terms of the accumulation (twelve products and n^), the
+// roundings of n^ and o and the final addition add at most 16.1 u (Q + X)^2 in
+// any summation order; the FP32 evaluation of d~ +- a and of the minimum adds
+// about 3 u (Q + X)^2.  a = 2^-18 (Q + X)^2 = 64 u (Q + X)^2 covers the sum
+// (about 22 u) three times over.  A query with Q + X >= 2^60 (where (Q + X)^2
+// could leave the FP32 range) is not scanned; the FP64 scan answers it.
+// ---------------------------------------------------------------------------
+constexpr int kG32 = 2;                                  // 32-query groups per wave
+constexpr int kQ32 = 4 * kG32 * 32;                      // queries per workgroup (4 waves)
+static_assert(kG32 == 2, "the inner loop interleaves two query groups");
+
+__device__ inline f32x16_t mfma_f32(float a, float b, f32x16_t c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256, 3) void scan32_kernel(
+    const float* __restrict__ w32, const float* __restrict__ n32, int64_t n_tiles, int64_t N,
+    const double* __restrict__ qw, const double* __restrict__ qn2, const double* __restrict__ u64,
+    const int* __restrict__ invalid, float xmax, QueryList L, CandBuf cb) {
+  // xs[buf][s][h][row] = x^[row][2 s + h]; ns[buf][row] = n^[row]
+  __shared__ float xs[2][6][2][kTile32];
+  __shared__ __attribute__((aligned(16))) float ns[2][kTile32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, h = lane >> 5;
+  const int S = cb.S;
+  const int split = blockIdx.x % S;
+  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ32;
+  const int64_t len = list_len(L);
+  if (qbase >= len) return;
+  const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
+
+  float b[kG32][6], o[kG32], U[kG32], a[kG32];
+  bool valid[kG32], ovf[kG32];
+  int64_t pos[kG32];
+  int cnt[kG32];
+#pragma unroll
+  for (int g = 0; g < kG32; ++g) {
+    const int64_t p = qbase + wave * 32 * kG32 + g * 32 + col;
+    bool v = p < len;
+    const int64_t q = v ? list_query(L, p) : 0;
+    const float qa = v ? (float)sqrt(qn2[q]) + xmax : 0.0f;
+    v = v && !invalid[q] && qa < 0x1p60f;
+    valid[g] = v;
+    pos[g] = p;
+    double oo = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double qk = v ? (double)(float)qw[12 * q + k] : 0.0;   // q^ = fl32(q)
+      oo = fma(qk, qk, oo);
+      if ((k & 1) == h) b[g][k >> 1] = (float)(-2.0 * qk);
+    }
+    o[g] = (float)oo;
+    a[g] = 0x1p-18f * qa * qa + 1e-30f;
+    U[g] = v ? __double2float_ru(u64[q]) : INFINITY;
+    cnt[g] = 0;
+    ovf[g] = false;
+  }
+
+  if (t0 < t1) {
+    // staging: thread t holds float4 number t + 256 v (v < 3) of the tile's
+    // rows and the norm of row t
+    auto load = [&](int64_t t, float4 (&reg)[3], float& nreg) {
+      const float4* src = reinterpret_cast<const float4*>(w32 + t * kTile32 * 12);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) reg[v] = src[tid + 256 * v];
+      nreg = n32[t * kTile32 + tid];
+    };
+    auto store = [&](int buf, const float4 (&reg)[3], float nreg) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const int e = 4 * (tid + 256 * v), row = e / 12, k = e % 12;   // k in {0, 4, 8}
+        xs[buf][k / 2][0][row] = reg[v].x;
+        xs[buf][k / 2][1][row] = reg[v].y;
+        xs[buf][k / 2 + 1][0][row] = reg[v].z;
+        xs[buf][k / 2 + 1][1][row] = reg[v].w;
+      }
+      ns[buf][tid] = nreg;
+    };
+    static_assert(kTile32 == 256, "one staged row norm per thread");
+    float4 reg[3];
+    float nreg;
+    load(t0, reg, nreg);
+    store(0, reg, nreg);
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+      const int cur = (int)((t - t0) & 1);
+      const bool more = t + 1 < t1;
+      if (more) load(t + 1, reg, nreg);
+      float tm0 = INFINITY, tm1 = INFINITY;
+#pragma unroll 1
+      for (int rb = 0; rb < kTile32 / 32; ++rb) {
+        float A[6];
+#pragma unroll
+        for (int sk = 0; sk < 6; ++sk) A[sk] = xs[cur][sk][h][rb * 32 + col];
+        f32x16_t cn;
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+          const float4 v4 = *reinterpret_cast<const float4*>(&ns[cur][rb * 32 + 8 * g4 + 4 * h]);
+          cn[4 * g4 + 0] = v4.x;
+          cn[4 * g4 + 1] = v4.y;
+          cn[4 * g4 + 2] = v4.z;
+          cn[4 * g4 + 3] = v4.w;
+        }
+        f32x16_t acc0 = mfma_f32(A[0], b[0][0], cn);
+        f32x16_t acc1 = mfma_f32(A[0], b[1][0], cn);
+#pragma unroll
+        for (int sk = 1; sk < 6; ++sk) {
+          acc0 = mfma_f32(A[sk], b[0][sk], acc0);
+          acc1 = mfma_f32(A[sk], b[1][sk], acc1);
+        }
+        tm0 = min16(tm0, acc0);
+        tm1 = min16(tm1, acc1);
+      }
+      const float tmg[kG32] = {tm0, tm1};
+#pragma unroll
+      for (int g = 0; g < kG32; ++g) {
+        const float v = fminf(tmg[g], __shfl_xor(tmg[g], 32));
+        const float dmin = v + o[g];
+        const float Un = fminf(U[g], dmin + a[g]);
+        const bool need = valid[g] && (dmin - a[g] <= Un);
+        U[g] = Un;
+        if (__any(need)) {
+          // rare once the bound is tight: recompute the tile and log every row
+          // whose lower bound d~ - a is within the bound
+          const int64_t slot = (pos[g] * S + split) * 2 + h;
+#pragma unroll 1
+          for (int rb = 0; rb < kTile32 / 32; ++rb) {
+            f32x16_t cn;
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+              const float4 v4 =
+                  *reinterpret_cast<const float4*>(&ns[cur][rb * 32 + 8 * g4 + 4 * h]);
+              cn[4 * g4 + 0] = v4.x;
+              cn[4 * g4 + 1] = v4.y;
+              cn[4 * g4 + 2] = v4.z;
+              cn[4 * g4 + 3] = v4.w;
+            }
+            f32x16_t acc = cn;
+#pragma unroll
+            for (int sk = 0; sk < 6; ++sk) acc = mfma_f32(xs[cur][sk][h][rb * 32 + col], b[g][sk], acc);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+              const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+              const int64_t j = t * kTile32 + row;
+              const float lb = (acc[i] + o[g]) - a[g];
+              if (valid[g] && j < N && lb <= U[g])
+                cand_append(cb, slot, cnt[g], ovf[g], lb, (uint32_t)j, U[g]);
+            }
+          }
+        }
+      }
+      if (more) store(cur ^ 1, reg, nreg);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < kG32; ++g) {
+    if (pos[g] < len) {
+      const int64_t slot = (pos[g] * S + split) * 2 + h;
+      cb.count[slot] = cnt[g] | (ovf[g] ? kOverflowBit : 0);
+      if (h == 0) cb.U[pos[g] * S + split] = U[g];
+    }
+  }
+}
+
+dd_status launch_scan32(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len_max,
+                        const CandBuf& cb, hipStream_t st) {
+  if (list_len_max <= 0) return DD_OK;
+  if (cb.P != 2) return set_error(DD_ERR_ARG, "FP32 scan: two candidate lists per split");
+  const int64_t qblocks = (list_len_max + kQ32 - 1) / kQ32;
+  const int64_t n_tiles = D.n_pad32 / kTile32;
+  hipLaunchKernelGGL(scan32_kernel, dim3((unsigned)(qblocks * cb.S)), dim3(256), 0, st,
+                     D.w32.as<float>(), D.n32.as<float>(), n_tiles, D.N, Q.qw, Q.qn2, Q.u64,
+                     Q.invalid, (float)D.xmax32, L, cb);
+  DD_HIP(hipGetLastError());
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // 16-bit MFMA scan over tile-centred data.  v_mfma_f32_32x32x16_{bf16,f16}:
 // A (32 data rows x 16 k): lane supplies row lane%32, k = 8*(lane/32)..+7;
 // B (16 k x 32 queries): lane supplies query lane%32, same k range;
@@ -211,18 +413,6 @@ template <> struct Vec16<Fp16> {
   }
 };
 
-// Running minimum over 16 new values: 17 inputs, eight 3-input minima.
-__device__ inline float min16(float run, const f32x16_t& a) {
-  float m0 = fminf(fminf(a[0], a[1]), a[2]);
-  float m1 = fminf(fminf(a[3], a[4]), a[5]);
-  float m2 = fminf(fminf(a[6], a[7]), a[8]);
-  float m3 = fminf(fminf(a[9], a[10]), a[11]);
-  float m4 = fminf(fminf(a[12], a[13]), a[14]);
-  float m5 = fminf(fminf(m0, m1), m2);
-  float m6 = fminf(fminf(m3, m4), a[15]);
-  return fminf(fminf(run, m5), m6);
-}
-
 constexpr int kG16 = 2;                                  // 32-query groups per wave
 constexpr int kW16 = 8;                                  // waves per workgroup
 constexpr int kT16 = 64 * kW16;                          // threads per workgroup
@@ -255,14 +445,26 @@ __device__ inline void tile_operands(const float (&qf)[8], float qabs, const flo
 }
 
 // Lane's query coordinates for the B operand: lanes of half h hold k = 8h..8h+7
-// (coordinates 0..11, then the constant slots 1, 1, 1, 0).
+// (scaled coordinates 0..11, then the constant slots 1, 1, 1, 0).
 __device__ inline void load_query_column(const double* __restrict__ qw, int64_t q, bool v, int h,
-                                         float (&qf)[8]) {
+                                         double scale, float (&qf)[8]) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     int k = 8 * h + i;
-    qf[i] = (k < 12) ? (v ? (float)qw[12 * q + k] : 0.0f) : (k < 15 ? 1.0f : 0.0f);
+    qf[i] = (k < 12) ? (v ? (float)(qw[12 * q + k] * scale) : 0.0f) : (k < 15 ? 1.0f : 0.0f);
   }
+}
+
+// The query lies inside the radius around the data's mean within which its
+// centred coordinates stay finite in the 16-bit format (see Scale16).
+__device__ inline bool near16(const double* __restrict__ qw, int64_t q, const Scale16& sc) {
+  float a = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const float t = (float)(qw[12 * q + k] * (double)sc.s) - sc.mean[k];
+    a = fmaf(t, t, a);
+  }
+  return sc.far > 0.0f && a < sc.far * sc.far;
 }
 
 __device__ inline void centre_select(const float* __restrict__ cp, int h, float (&cs)[8]) {
@@ -284,7 +486,7 @@ __global__ __launch_bounds__(kT16, 4) void scan16_pass_kernel(
     int64_t n_tiles, int stride, const double* __restrict__ qw, const double* __restrict__ qn2,
     const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L, int S,
     float* __restrict__ U_out, WorkItem* __restrict__ items, unsigned* __restrict__ n_items,
-    unsigned item_cap) {
+    unsigned item_cap, Scale16 sc) {
   typedef Vec16<T16> VT;
   typedef typename VT::type vec_t;
   constexpr int V = (TILE * 2 + kT16 - 1) / kT16;   // uint4 per thread per tile
@@ -308,11 +510,11 @@ __global__ __launch_bounds__(kT16, 4) void scan16_pass_kernel(
     int64_t p = qbase + wave * 32 * kG16 + g * 32 + col;
     bool v = p < len;
     int64_t q = v ? list_query(L, p) : 0;
-    v = v && !invalid[q];
+    v = v && !invalid[q] && near16(qw, q, sc);
     valid[g] = v;
     pos[g] = p;
-    load_query_column(qw, q, v, h, qf[g]);
-    qabs[g] = v ? (float)sqrt(qn2[q]) : 0.0f;
+    load_query_column(qw, q, v, h, (double)sc.s, qf[g]);
+    qabs[g] = v ? (float)(sqrt(qn2[q]) * (double)sc.s) : 0.0f;
     U[g] = v ? u32[q] : INFINITY;
   }
   // element e of a tile (uint4 e = 2 row + half) lives at lds[half * TILE + row]
@@ -421,7 +623,7 @@ __global__ __launch_bounds__(256) void scan16_extract_kernel(
     int64_t N, const double* __restrict__ qw, const double* __restrict__ qn2,
     const float* __restrict__ u32, const int* __restrict__ invalid, QueryList L,
     const WorkItem* __restrict__ items, const unsigned* __restrict__ n_items, unsigned item_cap,
-    CandBuf cb) {
+    CandBuf cb, Scale16 sc) {
   typedef Vec16<T16> VT;
   typedef typename VT::type vec_t;
   const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
@@ -433,10 +635,10 @@ __global__ __launch_bounds__(256) void scan16_extract_kernel(
   const int64_t p = (int64_t)it.group * 32 + col;
   bool v = p < len;
   const int64_t q = v ? list_query(L, p) : 0;
-  v = v && !invalid[q];
+  v = v && !invalid[q] && near16(qw, q, sc);
   float qf[8];
-  load_query_column(qw, q, v, h, qf);
-  const float qabs = v ? (float)sqrt(qn2[q]) : 0.0f;
+  load_query_column(qw, q, v, h, (double)sc.s, qf);
+  const float qabs = v ? (float)(sqrt(qn2[q]) * (double)sc.s) : 0.0f;
   const float Uq = v ? u32[q] : -INFINITY;
   const int64_t t = it.tile;
   float cs[8];
@@ -471,23 +673,26 @@ template <class T16, int TILE>
 static dd_status launch16(const Dataset& D, const uint16_t* pack, const Scan16Call& c, hipStream_t st) {
   const uint4* wp = reinterpret_cast<const uint4*>(pack);
   const int64_t qblocks = (c.list_len_max + kQ16 - 1) / kQ16;
+  Scale16 sc = D.sc16;
+  const double limit = T16::kUnit < 0.001f ? kFarLimitFp16 : kFarLimitBf16;
+  sc.far = (float)std::max(0.0, limit - D.span16);
   if (c.phase == Scan16Call::kExtract) {
     const unsigned waves = c.item_cap;   // grid sized for the capacity; extra waves exit
     const unsigned blocks = (unsigned)(((uint64_t)waves * 64 + 255) / 256);
     if (blocks == 0) return DD_OK;
     hipLaunchKernelGGL((scan16_extract_kernel<T16, TILE>), dim3(blocks), dim3(256), 0, st, wp,
                        D.centre.as<float>(), D.radius.as<float>(), D.N, c.Q->qw, c.Q->qn2,
-                       c.Q->u32, c.Q->invalid, c.L, c.items, c.n_items, c.item_cap, c.cb);
+                       c.Q->u32, c.Q->invalid, c.L, c.items, c.n_items, c.item_cap, c.cb, sc);
   } else if (c.phase == Scan16Call::kMark) {
     hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, true>), dim3((unsigned)(qblocks * c.S)),
                        dim3(kT16), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
                        c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
-                       c.items, c.n_items, c.item_cap);
+                       c.items, c.n_items, c.item_cap, sc);
   } else {
     hipLaunchKernelGGL((scan16_pass_kernel<T16, TILE, false>), dim3((unsigned)(qblocks * c.S)),
                        dim3(kT16), 0, st, wp, D.centre.as<float>(), D.radius.as<float>(), D.n_tiles,
                        c.stride, c.Q->qw, c.Q->qn2, c.Q->u32, c.Q->invalid, c.L, c.S, c.U_out,
-                       c.items, c.n_items, c.item_cap);
+                       c.items, c.n_items, c.item_cap, sc);
   }
   DD_HIP(hipGetLastError());
   return DD_OK;

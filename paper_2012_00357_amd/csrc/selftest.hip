@@ -37,6 +37,16 @@ __global__ void mfma64_probe(const double* A, const double* B, double* D) {
   for (int i = 0; i < 4; ++i) D[((l / 16) + 4 * i) * 16 + (l % 16)] = acc[i];
 }
 
+// FP32 32x32x2 with an accumulator input in the output layout: C[i][j] = i.
+__global__ void mfma32f_probe(const float* A, const float* B, float* D) {
+  const int l = threadIdx.x;
+  f32x16_t c;
+  for (int i = 0; i < 16; ++i) c[i] = (float)(8 * (i / 4) + 4 * (l / 32) + (i % 4));
+  f32x16_t acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[(l % 32) * 2 + l / 32],
+                                                      B[(l / 32) * 32 + (l % 32)], c, 0, 0, 0);
+  for (int i = 0; i < 16; ++i) D[(8 * (i / 4) + 4 * (l / 32) + (i % 4)) * 32 + (l % 32)] = acc[i];
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
 
@@ -61,8 +71,21 @@ __global__ void cvt_probe(const float* in, float* out, int use_f16) {
 
 extern "C" dd_status dd_selftest_mfma(int kind, const double* A, const double* B, double* D) {
   using namespace dd;
-  if (!A || !D || kind < 0 || kind > 4 || (kind < 3 && !B))
+  if (!A || !D || kind < 0 || kind > 5 || ((kind < 3 || kind == 5) && !B))
     return set_error(DD_ERR_ARG, "selftest arguments");
+  if (kind == 5) {
+    float Af[64], Bf[64], Df[1024];
+    for (int i = 0; i < 64; ++i) { Af[i] = (float)A[i]; Bf[i] = (float)B[i]; }
+    DevBuf a, b, d;
+    DD_TRY(a.alloc(sizeof(Af))); DD_TRY(b.alloc(sizeof(Bf))); DD_TRY(d.alloc(sizeof(Df)));
+    DD_HIP(hipMemcpy(a.p, Af, sizeof(Af), hipMemcpyHostToDevice));
+    DD_HIP(hipMemcpy(b.p, Bf, sizeof(Bf), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(mfma32f_probe, dim3(1), dim3(64), 0, 0, a.as<float>(), b.as<float>(), d.as<float>());
+    DD_HIP(hipGetLastError());
+    DD_HIP(hipMemcpy(Df, d.p, sizeof(Df), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 1024; ++i) D[i] = Df[i];
+    return DD_OK;
+  }
   if (kind >= 3) {
     float in[512], outv[512];
     for (int i = 0; i < 512; ++i) in[i] = (float)A[i];

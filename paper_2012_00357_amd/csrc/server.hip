@@ -13,6 +13,14 @@
 // their streams and queue for the next batch (continuous batching).  Every
 // solve's arithmetic is the one of dd_solve, so its result does not depend on
 // the mix it ran in.
+//
+// Device memory.  A solve is charged its solver buffers and projection scratch
+// while it is admitted.  A mesh that dd_solve would solve through a cached K^-1
+// and whose inverse the dataset does not hold yet is charged that inverse too:
+// the inverse is formed on a builder thread (the solve waits, the others go
+// on) and stays charged to the server while the dataset's cache keeps it.  A
+// solve whose inverse could not fit next to it even on an idle server is run
+// by CG instead (the trajectory of dd_solve with DD_SOLVE_CG).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -20,6 +28,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -54,9 +63,12 @@ struct Job {
   int max_iter = 500;
   double deadline_s = 0.0;
   int64_t footprint = 0;
+  int64_t inv_bytes = 0;       // K^-1 the solve would use (0: solved by CG)
+  bool use_cg = false;         // run by CG: its K^-1 does not fit the budget
+  std::string inv_key;         // mesh and Dirichlet pattern of its K^-1
   int64_t n_mp = 0, n_dof = 0;
 
-  enum Phase { kQueued, kCg, kReady, kInBatch, kScalars, kDone };
+  enum Phase { kQueued, kInverse, kCg, kReady, kInBatch, kScalars, kDone };
   Phase phase = kQueued;       // scheduler thread only
   bool done = false;           // results published (guarded by mu): the waiter may free the job
   bool cancel = false;
@@ -107,6 +119,15 @@ struct Server {
   // scheduler-thread state
   std::vector<Job*> active;
   int64_t used = 0;
+  // K^-1 formed ahead of setup: builds in flight (key -> result, bytes) and the
+  // inverses this server formed that the dataset still caches (key -> bytes)
+  struct Build {
+    std::shared_future<std::pair<dd_status, std::string>> done;
+    int64_t bytes;
+  };
+  std::map<std::string, Build> building;
+  std::map<std::string, int64_t> formed;
+  int64_t held_bytes();
   std::atomic<int64_t> n_active{0};
 
   // projection thread
@@ -132,6 +153,7 @@ struct Server {
   void scheduler();
   void projector();
   dd_status admit(Job* j);
+  dd_status admit_setup(Job* j);
   void finish(Job* j, dd_status st, const std::string& msg);
   bool step(Job* j);
   void launch_batch();
@@ -141,13 +163,62 @@ struct Server {
 // ---------------------------------------------------------------------------
 // scheduler thread
 // ---------------------------------------------------------------------------
+// Bytes of the inverses in flight and of those this server formed that the
+// dataset still caches (dropped from the charge once the cache lets them go).
+int64_t Server::held_bytes() {
+  int64_t b = 0;
+  for (const auto& kv : building) b += kv.second.bytes;
+  for (auto it = formed.begin(); it != formed.end();) {
+    dd_mesh m;
+    std::memcpy(&m, it->first.data(), sizeof(m));
+    const uint8_t* mask = reinterpret_cast<const uint8_t*>(it->first.data() + sizeof(m));
+    if (DDSolver::inverse_cached(*D, m, mask)) {
+      b += it->second;
+      ++it;
+    } else {
+      it = formed.erase(it);
+    }
+  }
+  return b;
+}
+
 dd_status Server::admit(Job* j) {
   DD_HIP(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
+  if (j->inv_bytes > 0 && !j->use_cg && !DDSolver::inverse_cached(*D, j->mesh, j->mask.data())) {
+    // form K^-1 on a builder thread (or wait for the build of the same
+    // inverse already in flight); the solve waits in kInverse
+    if (!building.count(j->inv_key)) {
+      const Dataset* ds = D;
+      const int dev = device;
+      const dd_mesh mesh = j->mesh;
+      std::vector<uint8_t> mask = j->mask;
+      auto fut = std::async(std::launch::async, [ds, dev, mesh, mask]() {
+        std::pair<dd_status, std::string> r{DD_OK, std::string()};
+        hipStream_t s = nullptr;
+        if (hipSetDevice(dev) != hipSuccess ||
+            hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+          r.first = set_error(DD_ERR_DEVICE, "K^-1 builder: no stream");
+        } else {
+          r.first = DDSolver::prepare_inverse(*ds, mesh, mask.data(), s);
+          (void)hipStreamDestroy(s);
+        }
+        if (r.first != DD_OK) r.second = dd_last_error();
+        return r;
+      });
+      building[j->inv_key] = Build{fut.share(), j->inv_bytes};
+    }
+    j->phase = Job::kInverse;
+    return DD_OK;
+  }
+  return admit_setup(j);
+}
+
+dd_status Server::admit_setup(Job* j) {
   j->S.reset(new DDSolver());
   dd_solve_opts o{};
   o.mode = mode;
   o.ann_budget = ann_budget;
-  o.flags = DD_SOLVE_NO_GRAPH;
+  o.flags = DD_SOLVE_NO_GRAPH | (j->use_cg ? DD_SOLVE_CG : 0);
   DD_TRY(j->S->setup(*D, j->mesh, j->mask.data(), j->force.data(), &o, j->stream));
   DD_TRY(j->S->set_assignment(j->init.data()));
   DD_TRY(j->S->async_init());
@@ -170,7 +241,7 @@ void Server::finish(Job* j, dd_status st, const std::string& msg) {
     }
   }
   std::string err = (st == DD_OK) ? std::string() : (msg.empty() ? std::string(dd_last_error()) : msg);
-  j->S.reset();
+  if (j->S) j->S.reset();
   if (j->stream) (void)hipStreamDestroy(j->stream);
   j->stream = nullptr;
   used -= j->footprint;
@@ -201,6 +272,14 @@ bool Server::step(Job* j) {
     cancel = true;
   if (cancel && j->phase != Job::kInBatch) {
     finish(j, DD_ERR_CANCELLED, "solve cancelled");
+    return true;
+  }
+  if (j->phase == Job::kInverse) {
+    // the build was swept when it ended; setup() then finds the inverse cached
+    // (or, after a failed build, forms it itself and reports its error)
+    if (building.count(j->inv_key)) return false;
+    const dd_status st = admit_setup(j);
+    if (st != DD_OK) finish(j, st, "");
     return true;
   }
   DDSolver& S = *j->S;
@@ -341,6 +420,16 @@ void Server::scheduler() {
   (void)hipSetDevice(device);
   for (;;) {
     bool progress = false;
+    // finished K^-1 builds: charged while the dataset caches the inverse
+    for (auto it = building.begin(); it != building.end();) {
+      if (it->second.done.wait_for(std::chrono::seconds(0)) == std::future_status::ready) {
+        if (it->second.done.get().first == DD_OK) formed[it->first] = it->second.bytes;
+        it = building.erase(it);
+        progress = true;
+      } else {
+        ++it;
+      }
+    }
     // admission: arrival order, as long as the footprint fits
     {
       std::unique_lock<std::mutex> lk(mu);
@@ -362,20 +451,31 @@ void Server::scheduler() {
           ++it;
         }
       }
-      while (!queue.empty() && (int)active.size() < max_active &&
-             used + queue.front()->footprint <= budget) {
+      while (!queue.empty() && (int)active.size() < max_active) {
         Job* j = queue.front();
+        // the K^-1 this solve would form: charged from admission on; one that
+        // cannot fit next to the solve even on an idle server means CG
+        int64_t extra = 0;
+        if (j->inv_bytes > 0 && !j->use_cg && !building.count(j->inv_key) &&
+            !DDSolver::inverse_cached(*D, j->mesh, j->mask.data())) {
+          if (j->footprint + j->inv_bytes > budget)
+            j->use_cg = true;
+          else
+            extra = j->inv_bytes;
+        }
+        const int64_t held = held_bytes();
+        if (used + held + j->footprint + extra > budget) break;
         queue.pop_front();
         j->t_admit = Clock::now();
         lat_queue.push_back(ms_since(j->t_submit, j->t_admit));
         used += j->footprint;
         active.push_back(j);
         peak_active = std::max<int64_t>(peak_active, (int64_t)active.size());
-        peak_used = std::max(peak_used, used);
         lk.unlock();
         dd_status st = admit(j);
         if (st != DD_OK) finish(j, st, "");
         lk.lock();
+        peak_used = std::max(peak_used, used + held_bytes());
         progress = true;
       }
     }
@@ -547,6 +647,7 @@ extern "C" dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_by
     return set_error(DD_ERR_ARG, "dd_server_opts: negative field or reserved != 0");
   const bool ok = (mode == DD_EXACT_FP64 && (D.packs & DD_PACK_FP64)) ||
                   (mode == DD_DIRECT_FP64 && (D.packs & DD_PACK_FP64)) ||
+                  (mode == DD_MIXED_FP32 && (D.packs & DD_PACK_FP32)) ||
                   (mode == DD_MIXED_BF16 && (D.packs & DD_PACK_BF16)) ||
                   (mode == DD_MIXED_FP16 && (D.packs & DD_PACK_FP16)) ||
                   (mode == DD_ANN && (D.packs & DD_PACK_ANN)) ||
@@ -616,6 +717,20 @@ extern "C" dd_status dd_server_submit(dd_server* h, const dd_solve_request* r, u
   j->max_iter = r->max_iter > 0 ? r->max_iter : 500;
   j->deadline_s = r->deadline_s;
   j->footprint = DDSolver::footprint_bytes(r->mesh) + kBytesPerQuery * j->n_mp;
+  j->inv_bytes = DDSolver::inverse_bytes(r->mesh);
+  {
+    dd_mesh key_mesh;
+    std::memset(&key_mesh, 0, sizeof(key_mesh));   // no padding bytes of the caller's struct
+    key_mesh.nx = r->mesh.nx;
+    key_mesh.ny = r->mesh.ny;
+    key_mesh.nz = r->mesh.nz;
+    key_mesh.lx = r->mesh.lx;
+    key_mesh.ly = r->mesh.ly;
+    key_mesh.lz = r->mesh.lz;
+    j->mesh = key_mesh;
+    j->inv_key.assign(reinterpret_cast<const char*>(&key_mesh), sizeof(key_mesh));
+    j->inv_key.append(reinterpret_cast<const char*>(j->mask.data()), j->mask.size());
+  }
   std::lock_guard<std::mutex> lk(s.mu);
   if (s.stop) return set_error(DD_ERR_CANCELLED, "server is shutting down");
   if (j->footprint > s.budget) {

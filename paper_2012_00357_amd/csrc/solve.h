@@ -22,10 +22,13 @@ struct FEMesh {
 // where not certified.
 // fd: radius factor of the k-means walk's ball test (1 = exact).
 // passes: as dd_project_opts.passes (0 = the default for the warm start given).
+// fd_q / budget_q (walk modes, device arrays over the m states, optional): a
+// radius factor and a leaf budget per state in place of fd and ann_budget.
 dd_status project_whitened(const Dataset& D, const double* qw_dev, int64_t m,
                            const int64_t* warm_dev, int mode, int ann_budget, int64_t* idx_out,
                            double* dist_out, hipStream_t st, double* dist2_out = nullptr,
-                           double fd = 1.0, int passes = 0);
+                           double fd = 1.0, int passes = 0, const float* fd_q = nullptr,
+                           const int* budget_q = nullptr);
 
 // K^-1 for the mesh and Dirichlet pattern, formed on st from the CSR matrix on
 // first use and cached on the dataset.
@@ -66,6 +69,14 @@ class DDSolver {
   // after ev_scal: (d_half, d_full, changed, bad flag); swaps in the new association
   void scalars_end(double sc[3], int* bad);
   static int64_t footprint_bytes(const dd_mesh& mesh);
+  // Device bytes of the K^-1 that setup() uses for the mesh (0: the mesh is
+  // solved by CG), whether the dataset already caches it for the Dirichlet
+  // pattern, and its formation ahead of setup() (a no-op when cached or when
+  // the mesh is solved by CG; synchronises st).
+  static int64_t inverse_bytes(const dd_mesh& mesh);
+  static bool inverse_cached(const Dataset& D, const dd_mesh& mesh, const uint8_t* mask);
+  static dd_status prepare_inverse(const Dataset& D, const dd_mesh& mesh, const uint8_t* mask,
+                                   hipStream_t st);
   hipEvent_t ev_cg = nullptr, ev_ready = nullptr, ev_scal = nullptr;
   char* h_pin = nullptr;
   int cg_it = 0;
@@ -93,6 +104,11 @@ class DDSolver {
   }
   // iteration it projects approximately
   bool approximate_at(int it) const { return budget_at(it) > 0 || fd_at(it) < 1.0; }
+  // accuracy that also depends on the distances (DD_SOLVE_LOCAL_ACCURACY): per
+  // material point, from its latest local distance and the latest global one
+  bool local_on = false;
+  double last_full = INFINITY;     // D_full of the latest iteration
+  DevBuf d_fdq, d_budq;            // per-point radius factor and leaf budget
   // associations the previous iteration changed (-1 before the first)
   int64_t last_changed = -1;
   // passes of the 16-bit scans at iteration it: the bound-seeding pass runs

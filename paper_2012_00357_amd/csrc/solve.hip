@@ -639,6 +639,28 @@ __global__ void unskip_kernel(int n, const int* __restrict__ list, const int64_t
   }
 }
 
+// Accuracy of each material point's search from its latest local distance
+// d_e (the distance of the previous projection) and the latest global one
+// (the mean local distance dbar = D_full / sum of the weights) at an iteration
+// whose schedule gives the radius factor f and the leaf budget b (Section 4's
+// accuracy parameter as a function of the global distance, the local distance
+// and the iteration).  With rho = d_e / dbar, points at least as far from the
+// data as the mean keep (f, b); nearer points get more accuracy, up to the
+// exact search at the data: f_e = f + (1 - f)(1 - rho), b_e = b ceil(1 / rho)
+// (at most 16 b).
+__global__ void local_accuracy_kernel(int64_t nm, const double* __restrict__ dist, double inv_dbar,
+                                      float f, int b, float* __restrict__ fdq,
+                                      int* __restrict__ bq) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nm) return;
+  const double rho = dist[e] * inv_dbar;
+  const double near = rho < 1.0 ? 1.0 - rho : 0.0;
+  fdq[e] = (float)fmin(1.0, (double)f + (1.0 - (double)f) * near);
+  int be = b;
+  if (b > 0 && rho < 1.0) be = b * (int)fmin(16.0, ceil(1.0 / fmax(rho, 1.0 / 16.0)));
+  bq[e] = be;
+}
+
 static unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ---------------------------------------------------------------------------
@@ -669,6 +691,9 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
       return set_error(DD_ERR_ARG, "dd_solve_opts: ann_radius_discount applies to DD_KMEANS only");
     ann_fd = 1.0 - discount;
   }
+  if (opts && (opts->flags & ~(DD_SOLVE_NO_GRAPH | DD_SOLVE_CG | DD_SOLVE_SKIP |
+                               DD_SOLVE_LOCAL_ACCURACY)))
+    return set_error(DD_ERR_ARG, "dd_solve_opts: unknown flag bits");
   use_graph = !(opts && (opts->flags & DD_SOLVE_NO_GRAPH));
   cg_tol = (opts && opts->cg_tol > 0) ? opts->cg_tol : 1e-13;
   cg_max_iter = (opts && opts->cg_max_iter > 0) ? opts->cg_max_iter : 20000;
@@ -795,6 +820,13 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
                              d_val.as<double>(), dense, st));
   skip_on = (walk_mode(mode) && ann_budget == 0 && fd_at(1) >= 1.0 && opts &&
              (opts->flags & DD_SOLVE_SKIP));
+  local_on = walk_mode(mode) && opts && (opts->flags & DD_SOLVE_LOCAL_ACCURACY) &&
+             (ann_budget > 0 || ann_fd < 1.0);
+  last_full = INFINITY;
+  if (local_on) {
+    DD_TRY(d_fdq.alloc(sizeof(float) * nm));
+    DD_TRY(d_budq.alloc(sizeof(int) * nm));
+  }
   if (skip_on) {
     DD_TRY(d_qref.alloc(sizeof(double) * 12 * nm));
     DD_TRY(d_gap.alloc(sizeof(double) * nm));
@@ -814,6 +846,16 @@ dd_status DDSolver::setup(const Dataset& D, const dd_mesh& mesh, const uint8_t* 
 
 dd_status DDSolver::project_step(int it) {
   const int64_t nm = M.n_mp;
+  if (local_on && approximate_at(it) && std::isfinite(last_full) && last_full > 0.0) {
+    const double dbar = last_full / ((double)nm * M.w);
+    hipLaunchKernelGGL(local_accuracy_kernel, dim3(g256(nm)), dim3(256), 0, st, nm,
+                       d_dist.as<double>(), 1.0 / dbar, (float)fd_at(it), budget_at(it),
+                       d_fdq.as<float>(), d_budq.as<int>());
+    DD_HIP(hipGetLastError());
+    return project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, budget_at(it),
+                            d_idx_new.as<int64_t>(), d_dist.as<double>(), st, nullptr, fd_at(it),
+                            0, d_fdq.as<float>(), d_budq.as<int>());
+  }
   if (!skip_on)
     return project_whitened(*ds, d_yw.as<double>(), nm, d_idx.as<int64_t>(), mode, budget_at(it),
                             d_idx_new.as<int64_t>(), d_dist.as<double>(), st, nullptr, fd_at(it),
@@ -856,6 +898,42 @@ int64_t DDSolver::footprint_bytes(const dd_mesh& m) {
   const int64_t nb = (nd + kCgBlock - 1) / kCgBlock, nbs = (nd + kRowsPerBlock - 1) / kRowsPerBlock;
   return 4 * (nd + 1) + 12 * nnz + (8 + 1 + 8 + 16 + 16 + 64) * nd + (8 + 8 + 8 + 3 * 96) * nm +
          8 * (4 + 3 * kScalBlocks) + 64 + 64 * (nb + nbs) + (int64_t)sizeof(CGState);
+}
+
+int64_t DDSolver::inverse_bytes(const dd_mesh& m) {
+  const int64_t nd = 3 * (int64_t)(m.nx + 1) * (m.ny + 1) * (m.nz + 1);
+  if (nd > kDenseMaxDof) return 0;
+  const int64_t n_pad = (nd + 63) / 64 * 64;   // the Gauss-Jordan block size
+  return n_pad * n_pad * (int64_t)sizeof(double);
+}
+
+bool DDSolver::inverse_cached(const Dataset& D, const dd_mesh& m, const uint8_t* mask) {
+  std::unique_ptr<FEMesh> M(new FEMesh());
+  M->init(m);
+  return dense_inverse_cached(D, *M, mask) != nullptr;
+}
+
+dd_status DDSolver::prepare_inverse(const Dataset& D, const dd_mesh& m, const uint8_t* mask,
+                                    hipStream_t st) {
+  std::unique_ptr<FEMesh> M(new FEMesh());
+  M->init(m);
+  if (M->n_dof > kDenseMaxDof || dense_inverse_cached(D, *M, mask)) return DD_OK;
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val, dinv;
+  assemble_csr(*M, D.C, mask, rowptr, col, val, dinv);
+  DevBuf r, c, v;
+  DD_TRY(r.alloc(sizeof(int32_t) * rowptr.size()));
+  DD_TRY(c.alloc(sizeof(int32_t) * std::max<size_t>(col.size(), 1)));
+  DD_TRY(v.alloc(sizeof(double) * std::max<size_t>(val.size(), 1)));
+  DD_HIP(hipMemcpyAsync(r.p, rowptr.data(), sizeof(int32_t) * rowptr.size(), hipMemcpyHostToDevice, st));
+  if (!col.empty()) {
+    DD_HIP(hipMemcpyAsync(c.p, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, st));
+    DD_HIP(hipMemcpyAsync(v.p, val.data(), sizeof(double) * val.size(), hipMemcpyHostToDevice, st));
+  }
+  std::shared_ptr<DenseInverse> out;
+  DD_TRY(dense_inverse_for(D, *M, mask, r.as<int32_t>(), c.as<int32_t>(), v.as<double>(), out, st));
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
 }
 
 // Pinned layout: [0, 128) CG state, [128, 152) iteration scalars, [160, 164) bad flag.
@@ -1196,6 +1274,7 @@ dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
       break;
     }
     prev_full = sc[1];
+    last_full = sc[1];
   }
   if (it > max_iter) it = max_iter;
   if (res) {

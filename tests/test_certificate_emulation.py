@@ -43,10 +43,14 @@ def round16(x, fmt):
     return (u.astype(np.uint32) << 16).view(np.float32)
 
 
-def tile_pack(w, fmt):
-    """Centre, radius and A operand rows (-2x', n_hi, n_mid, n_lo, 0) of one tile."""
-    c = (w.sum(0) / len(w)).astype(np.float32)
-    r = np.sqrt(((w - c.astype(np.float64)) ** 2).sum(1)).max()
+def tile_pack(w, fmt, n_real=None):
+    """Centre, radius and A operand rows (-2x', n_hi, n_mid, n_lo, 0) of one tile;
+    with n_real, rows from n_real on are padding (copies of the last real row)
+    and the centre and radius cover the real rows only."""
+    n_real = len(w) if n_real is None else n_real
+    w = np.concatenate([w[:n_real], np.repeat(w[n_real - 1:n_real], len(w) - n_real, 0)])
+    c = (w[:n_real].sum(0) / n_real).astype(np.float32)
+    r = np.sqrt(((w[:n_real] - c.astype(np.float64)) ** 2).sum(1)).max()
     r = np.nextafter(np.float32(r * (1.0 + 1e-12) + 1e-30), np.float32(np.inf))
     xf = (w - c.astype(np.float64)).astype(np.float32)
     v = round16(xf, fmt)
@@ -76,10 +80,10 @@ def pairwise_fp32(terms):
     return t[..., 0]
 
 
-def bounds(qw, tile_w, fmt, order):
+def bounds(qw, tile_w, fmt, order, n_real=None):
     """(lower, upper) sqrt-space bounds of every (query, point) pair of one tile."""
     unit, absf = FORMATS[fmt]
-    c, rad, A = tile_pack(tile_w, fmt)
+    c, rad, A = tile_pack(tile_w, fmt, n_real)
     qf = qw.astype(np.float32)
     qp = round16((qf - c).astype(np.float32), fmt)
     B = np.concatenate([qp, np.ones((len(qw), 3), np.float32), np.zeros((len(qw), 1), np.float32)],
@@ -150,3 +154,56 @@ def test_candidates_keep_the_exact_nearest_point(fmt, C0):
     cand = lo_all <= U[:, None]
     assert np.all(cand[np.arange(len(q)), oi])
     assert np.median(cand.sum(1)) <= 8
+
+
+def scale16(w, tile):
+    """The 16-bit scans' power-of-two scale: the largest tile radius into [1, 2)."""
+    rmax = 0.0
+    for t0 in range(0, len(w), tile):
+        tw = w[t0:t0 + tile]
+        c = (tw.sum(0) / len(tw)).astype(np.float32).astype(np.float64)
+        rmax = max(rmax, float(np.sqrt(((tw - c) ** 2).sum(1)).max()))
+    return 2.0 ** -np.floor(np.log2(rmax))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_si_units_scaled_pack_and_padded_tail(fmt, C0):
+    """Stresses and metric in Pa: whitened offsets inside a tile reach squared
+    norms beyond the FP16 range (65504), so the packs are built from the data
+    multiplied by the power of two that brings the largest tile radius into
+    [1, 2) (exact, so the bounds hold in scaled units).  The last tile is padded
+    with copies of the last point: the scores of the padding rows are distances
+    to a real point, so U stays an upper bound of the true minimum, and the
+    exact nearest point (lowest index on ties) is always a candidate."""
+    n, tile = 2048 + 300, 1024
+    e, s = ddsynth.data_points(n, 4105)
+    s = s * 1e6
+    C = C0 * 1e6
+    qe, qs, _ = ddsynth.queries(e, s / 1e6, 96, 4106)
+    qs = qs * 1e6
+    qe = np.concatenate([qe, e[-3:]])
+    qs = np.concatenate([qs, s[-3:]])
+    w = oracle.whiten(e, s, C)
+    q = oracle.whiten(qe, qs, C)
+    oi, _, _ = oracle.pd_raw(e, s, C, qe, qs)
+    # unscaled, the FP16 norm slot of this data would overflow
+    c0 = (w[:tile].sum(0) / tile).astype(np.float32).astype(np.float64)
+    assert ((w[:tile] - c0) ** 2).sum(1).max() > 65504.0
+    sc = scale16(w, tile)
+    ws, qsc = w * sc, q * sc
+    lo_all, hi_all = [], []
+    for t0 in range(0, n, tile):
+        real = min(tile, n - t0)
+        tw = np.concatenate([ws[t0:t0 + real], np.zeros((tile - real, 12))])
+        for order in ("pairwise", list(range(16))):
+            lo, hi = bounds(qsc, tw, fmt, order, n_real=real)
+            padded = np.concatenate([ws[t0:t0 + real], np.repeat(ws[t0 + real - 1:t0 + real],
+                                                                  tile - real, 0)])
+            true = np.sqrt(((qsc[:, None, :] - padded[None, :, :]) ** 2).sum(2))
+            assert np.all(lo <= true) and np.all(true <= hi), (fmt, t0, order)
+        lo_all.append(lo[:, :real])
+        hi_all.append(hi)              # padding rows take part in U (distances to a real point)
+    U = np.concatenate(hi_all, 1).min(1)
+    cand = np.concatenate(lo_all, 1) <= U[:, None]
+    assert np.all(cand[np.arange(len(q)), oi])
+    assert np.array_equal(oi[-3:], np.arange(n - 3, n))

@@ -7,7 +7,8 @@ import pytest
 
 import ddsynth
 import oracle
-from gpu_util import compare_to_oracle, to_dev
+from oracle import fe
+from gpu_util import assert_matches_oracle_solve, compare_to_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -143,13 +144,18 @@ def test_dd_solve_accuracy_schedule(L, C0):
     states = to_dev(np.concatenate([ramp["eps"], ramp["sig"]], axis=1))
     idx, _ = L.dd_project(ds, states, mode="fp64")
     assert np.array_equal(idx.cpu().numpy(), ramp["idx"])
+    oi, od, o2 = oracle.pd_raw(e, s, C0, ramp["eps"], ramp["sig"])
+    clear = o2 > od * (1 + 1e-12)
+    _say(f"schedule: final association vs oracle, {(~clear).sum()} near ties")
+    assert np.array_equal(ramp["idx"][clear], oi[clear])
 
 
 @pytest.mark.parametrize("n", [4, 8])
 def test_dd_solve_skips_unmoved_points_exactly(L, C0, n):
     """Skipping material points that moved less than half their certified gap
     leaves the trajectory bitwise unchanged (same associations, distances and
-    u as projecting every point, and as the FP64 scan)."""
+    u as projecting every point, and as the FP64 scan); at 4^3 the skipping
+    solve also follows the oracle's DD loop from the same start."""
     e, s = ddsynth.data_points(200000, 1010)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN)
     mask, force = ddsynth.box_bc(n, 100.0)
@@ -165,3 +171,7 @@ def test_dd_solve_skips_unmoved_points_exactly(L, C0, n):
         assert np.array_equal(a["history"], r["history"])
         assert np.array_equal(a["u"], r["u"])
         assert np.array_equal(a["d_full"], r["d_full"]) and np.array_equal(a["d_half"], r["d_half"])
+    if n == 4:
+        ref = fe.dd_solve(e, s, C0, fe.Mesh(n), mask, force, init, record_history=True)
+        assert ref.converged and a["converged"]
+        assert_matches_oracle_solve(a, ref)

@@ -11,7 +11,8 @@ import pytest
 
 import ddsynth
 import oracle
-from gpu_util import compare_to_oracle, to_dev
+from oracle import fe
+from gpu_util import assert_matches_oracle_solve, compare_to_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -192,7 +193,8 @@ def test_kmeans_repeated_points(L, C0):
 @pytest.mark.parametrize("n", [4, 8])
 def test_dd_solve_kmeans_equals_fp64_trajectory(L, C0, n):
     """DD solves projecting by the exact k-means walk (with and without the
-    skipping of unmoved points) follow the FP64 scan's trajectory bit for bit."""
+    skipping of unmoved points) follow the FP64 scan's trajectory bit for bit;
+    at 4^3 the skipping solve also follows the oracle's DD loop."""
     e, s = ddsynth.data_points(200000, 1010)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | KMEANS)
     mask, force = ddsynth.box_bc(n, 100.0)
@@ -206,6 +208,10 @@ def test_dd_solve_kmeans_equals_fp64_trajectory(L, C0, n):
         assert np.array_equal(a["history"], r["history"])
         assert np.array_equal(a["u"], r["u"])
         assert np.array_equal(a["d_full"], r["d_full"])
+    if n == 4:
+        ref = fe.dd_solve(e, s, C0, fe.Mesh(n), mask, force, init, record_history=True)
+        assert ref.converged and b["converged"]
+        assert_matches_oracle_solve(b, ref)
 
 
 def test_dd_solve_kmeans_fd_schedule(L, C0):
@@ -243,6 +249,59 @@ def test_dd_solve_kmeans_fd_schedule(L, C0):
     with pytest.raises(L.DDError) as ex:
         L.dd_solve(ds, (n, n, n), mask, force, init, mode="fp64", ann_fd=0.5)
     assert ex.value.status == 1
+
+
+@pytest.mark.parametrize("mode,kw", [("kmeans", dict(ann_fd=0.4, ann_ramp=6)),
+                                     ("kmeans", dict(ann_fd=0.0, ann_ramp=0)),
+                                     ("ann", dict(ann_budget=2, ann_ramp=6)),
+                                     ("ann", dict(ann_budget=1, ann_ramp=0))])
+def test_dd_solve_local_accuracy(L, C0, mode, kw):
+    """DD_SOLVE_LOCAL_ACCURACY (accuracy from the local and the global distance
+    and the iteration): every point of the last projection lies between its
+    exact nearest neighbour (oracle) and its previous association, the stopping
+    rules of approximate solves apply, and with an exact walk the flag changes
+    nothing."""
+    n = 4
+    e, s = ddsynth.data_points(200000, 1012)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | ANN | KMEANS)
+    mask, force = ddsynth.box_bc(n, 100.0)
+    init = ddsynth.indices(8 * n ** 3, 200000, 13)
+    base = L.dd_solve(ds, (n, n, n), mask, force, init, mode=mode, history=True, **kw)
+    r = L.dd_solve(ds, (n, n, n), mask, force, init, mode=mode, history=True,
+                   local_accuracy=True, **kw)
+    k = r["iterations"]
+    _say(f"{mode} {kw}: local {k} iterations (stop {r['stop_reason']}), final distance "
+         f"{r['d_full'][-1]:.6g}, search {r['project_ms']:.2f} ms; schedule alone "
+         f"{base['iterations']} iterations, {base['d_full'][-1]:.6g}, {base['project_ms']:.2f} ms")
+    assert r["stop_reason"] in (1, 2) and k >= kw["ann_ramp"]
+    hist = r["history"]
+    assert hist.min() >= 0 and hist.max() < 200000
+    got = oracle.pair_dist_raw(r["eps"], r["sig"], e[hist[k]], s[hist[k]], C0)
+    prev = oracle.pair_dist_raw(r["eps"], r["sig"], e[hist[k - 1]], s[hist[k - 1]], C0)
+    _, od, _ = oracle.pd_raw(e, s, C0, r["eps"], r["sig"])
+    assert np.all(got >= od * (1 - 1e-12))
+    assert np.all(got <= prev * (1 + 1e-12))
+    # the first iteration has no previous distance: it follows the schedule alone
+    assert np.array_equal(r["history"][1], base["history"][1])
+    exact = L.dd_solve(ds, (n, n, n), mask, force, init, mode=mode, history=True)
+    same = L.dd_solve(ds, (n, n, n), mask, force, init, mode=mode, history=True,
+                      local_accuracy=True)
+    assert np.array_equal(exact["history"], same["history"])
+
+
+def test_dd_solve_unknown_flag_is_refused(L, C0):
+    e, s = ddsynth.data_points(1000, 1013)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64)
+    mask, force = ddsynth.box_bc(2, 100.0)
+    init = ddsynth.indices(64, 1000, 14)
+    opts = L.dd_solve_opts(0, 0, 0, 0x40, 0.0, 0, 0, None, 0.0)
+    res = L.dd_solve_result()
+    import ctypes
+    m = L.dd_mesh(2, 2, 2, 1.0, 1.0, 1.0)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    st = L.lib().dd_solve(ds.handle, ctypes.byref(m), mask.ctypes.data, force.ctypes.data,
+                          init.ctypes.data, ctypes.byref(opts), ctypes.byref(res), None)
+    assert st == 1
 
 
 def test_server_kmeans_mode(L, C0):

@@ -10,8 +10,8 @@ from gpu_util import compare_to_oracle, to_dev
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["direct", "fp64", "bf16", "fp16", "ann"]
-ALL_PACKS = 0x1 | 0x4 | 0x8 | 0x10
+MODES = ["direct", "fp64", "fp32", "bf16", "fp16", "ann"]
+ALL_PACKS = 0x1 | 0x2 | 0x4 | 0x8 | 0x10
 
 
 @pytest.fixture(scope="module")
@@ -40,6 +40,15 @@ def test_mfma_lane_layouts(L, kind):
         B = rng.integers(-8, 9, (16, 32)).astype(float)
     D = L.dd_selftest_mfma(kind, A, B)
     np.testing.assert_array_equal(D, A @ B)
+
+
+def test_mfma_fp32_lane_layout_with_accumulator_input(L):
+    """The FP32 scan's layouts, its norms entering as the accumulator input."""
+    rng = np.random.default_rng(5)
+    A = rng.integers(-8, 9, (32, 2)).astype(float)
+    B = rng.integers(-8, 9, (2, 32)).astype(float)
+    D = L.dd_selftest_mfma(5, A, B)
+    np.testing.assert_array_equal(D, A @ B + np.arange(32.0)[:, None])
 
 
 def _bf16_rne(x):
@@ -129,6 +138,39 @@ def test_queries_on_data_points_and_duplicates(L, C0, mode):
     idx, dist = L.dd_project(ds, states, mode=mode)
     assert idx.cpu().tolist() == [dup_of, dup_of, 10, 10, 0, n - 1, 3333]
     assert np.all(dist.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_si_units_padded_tail_and_far_queries(L, C0, mode):
+    """Stresses and metric in Pa (whitened coordinates about 1000 times those in
+    MPa, tile offsets whose squared norms exceed the FP16 range unless the
+    16-bit scans rescale), a last tile padded past N, queries on points of that
+    tile, and queries so far from the data that their centred coordinates would
+    overflow FP16 (answered by the FP64 fallback): every mode equals the oracle."""
+    _say("SI units", mode)
+    n = 5003
+    e, s = ddsynth.data_points(n, 6100)
+    s = s * 1e6
+    C = C0 * 1e6
+    qe, qs, _ = ddsynth.queries(e, s / 1e6, 200, 6101)
+    qs = qs * 1e6
+    tail = np.arange(n - 5, n)
+    qe = np.concatenate([qe, e[tail], qe[:8] * 1e4, qe[:4] * 1e9])
+    qs = np.concatenate([qs, s[tail], qs[:8] * 1e4, qs[:4] * 1e9])
+    oi, od, o2 = oracle.pd_raw(e, s, C, qe, qs)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C, packs=ALL_PACKS, tile=1024)
+    idx, dist, st = L.dd_project(ds, to_dev(ddsynth.states(qe, qs)), mode=mode, stats=True)
+    _say(f"  {mode}: overflowed {st['overflowed']}, candidates {st['candidates']}")
+    compare_to_oracle(idx.cpu().numpy(), dist.cpu().numpy(), oi, od, o2)
+    assert np.array_equal(idx.cpu().numpy()[200:205], tail)
+
+
+def test_passes_out_of_range_is_refused(L, config0):
+    for passes in (-1, 3):
+        with pytest.raises(L.DDError) as ex:
+            L.dd_project(config0["ds"], config0["states"][:4].contiguous(), mode="bf16",
+                         passes=passes)
+        assert ex.value.status == 1
 
 
 @pytest.mark.parametrize("mode", ["fp64", "bf16", "ann"])
@@ -230,7 +272,7 @@ def test_error_paths(L, C0):
         L.dd_dataset_create(to_dev(e2), to_dev(s), C0)
     assert ex.value.status == 1
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1)
-    for mode in ("bf16", "fp16", "ann"):
+    for mode in ("fp32", "bf16", "fp16", "ann"):
         with pytest.raises(L.DDError) as ex:
             L.dd_project(ds, torch.zeros((3, 12), dtype=torch.float64, device="cuda"), mode=mode)
         assert ex.value.status == 8

@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import ddsynth
-from gpu_util import to_dev
+from oracle import fe
+from gpu_util import assert_matches_oracle_solve, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +34,7 @@ def data(L, C0):
     N = 1 << 18
     e, s = ddsynth.data_points(N, 1004)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | BF16)
-    return dict(N=N, ds=ds)
+    return dict(N=N, ds=ds, e=e, s=s)
 
 
 def _requests(N, sizes, seed):
@@ -87,6 +88,38 @@ def test_results_alone_equal_results_in_the_mix(L, data):
         srv.close()
 
 
+def test_served_solves_match_oracle(L, data, C0):
+    """Solves served in a mix of 2^3 and 3^3 meshes (staggered arrivals, one
+    server) follow the oracle's DD loop from the same initial association:
+    same iteration count and final association, u, strains and stresses to
+    1e-10 of their maxima, distances to 1e-9."""
+    N, ds, e, s = data["N"], data["ds"], data["e"], data["s"]
+    rng = np.random.default_rng(21)
+    probs = []
+    for k, n in enumerate((2, 3, 2, 3, 3, 2)):
+        m = fe.Mesh(n)
+        t = float(rng.uniform(50.0, 200.0))
+        probs.append((m, m.clamp_mask(), m.traction_x1(t),
+                      ddsynth.indices(m.n_mp, N, 700 + k)))
+    srv = L.DDServer(ds, mode="bf16")
+    try:
+        tickets = []
+        for k, (m, mask, f, init) in enumerate(probs):
+            n = m.n
+            tickets.append(srv.submit((n, n, n), mask, f, init))
+            if k % 2 == 1:
+                time.sleep(0.002)
+        served = [srv.wait(t) for t in tickets]
+        assert srv.stats()["peak_active"] > 1
+    finally:
+        srv.close()
+    for (m, mask, f, init), got in zip(probs, served):
+        ref = fe.dd_solve(e, s, C0, m, mask, f, init)
+        _say(f"served {m.n}^3 vs oracle: {got['iterations']} / {ref.iterations} iterations")
+        assert got["status"] == 0 and got["converged"] and ref.converged
+        assert_matches_oracle_solve(got, ref, history=False)
+
+
 def test_large_mesh_spans_batches(L, data):
     """A solve with more material points than a batch holds is projected in
     several batches and still gives the dd_solve result."""
@@ -128,6 +161,52 @@ def test_admission_by_footprint(L, data):
         assert srv.stats()["rejected"] == 1
     finally:
         srv.close()
+
+
+def test_inverse_beyond_budget_runs_by_cg(L, C0):
+    """An 8^3 solve's buffers fit a 20 MB budget but its K^-1 (40 MB) does not:
+    on a dataset that has not formed that inverse, the server runs the solve
+    by CG (the trajectory of dd_solve with DD_SOLVE_CG, bit for bit) and never
+    charges more than the budget."""
+    N = 1 << 16
+    e, s = ddsynth.data_points(N, 1030)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | BF16)
+    mask, force = ddsynth.box_bc(8, 120.0)
+    init = ddsynth.indices(8 * 8 ** 3, N, 31)
+    srv = L.DDServer(ds, hbm_budget_bytes=20_000_000, mode="bf16")
+    try:
+        got = srv.wait(srv.submit((8, 8, 8), mask, force, init))
+        st = srv.stats()
+    finally:
+        srv.close()
+    _say("cg fallback", st["peak_bytes"], st["budget_bytes"], got["cg_iterations"])
+    assert got["cg_iterations"] > 0 and st["peak_bytes"] <= st["budget_bytes"]
+    _same(L.dd_solve(ds, (8, 8, 8), mask, force, init, mode="bf16", cg=True, graph=False), got)
+    ds.close()
+
+
+def test_inverse_formed_off_the_scheduler_and_charged(L, C0):
+    """Solves whose K^-1 the dataset does not hold yet: the server forms the
+    inverses on a builder thread while the other solves run, charges them
+    against the budget, and every result equals dd_solve's (which then finds
+    the same inverses in the dataset's cache)."""
+    N = 1 << 16
+    e, s = ddsynth.data_points(N, 1031)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | BF16)
+    reqs = _requests(N, [8, 3, 2, 3], 7)
+    srv = L.DDServer(ds, mode="bf16")
+    try:
+        got = [srv.wait(t) for t in [srv.submit(*r) for r in reqs]]
+        st = srv.stats()
+    finally:
+        srv.close()
+    _say("async inverses", st["peak_bytes"], st["peak_active"])
+    n_pad = (3 * 9 ** 3 + 63) // 64 * 64
+    assert st["peak_bytes"] >= 8 * n_pad * n_pad          # the 8^3 inverse was charged
+    for r, g in zip(reqs, got):
+        assert g["cg_iterations"] == 0
+        _same(L.dd_solve(ds, *r, mode="bf16"), g)
+    ds.close()
 
 
 def test_cancel_failures_and_limits(L, data):

@@ -101,14 +101,16 @@ def test_dd_solve_linear_law_planted(L, C0):
     np.testing.assert_allclose(got["u"], want, atol=1e-15)
 
 
-def test_dd_solve_config1_stepwise(L, C0):
-    """8^3 mesh, N = 1e6, clamp + 100 MPa: every P_C of the GPU trajectory is
-    recomputed by the oracle from the GPU's association, and every P_D is
-    checked on 48 sampled material points by oracle brute force."""
+@pytest.mark.parametrize("mode", ["bf16", "fp64"])
+def test_dd_solve_config1_stepwise(L, C0, mode):
+    """8^3 mesh, N = 1e6, clamp + 100 MPa, in the BF16 and the FP64 mode: every
+    P_C of the GPU trajectory is recomputed by the oracle from the GPU's
+    association, and every P_D is checked on 48 sampled material points by
+    oracle brute force."""
     e, s, m, mask, f, init = _problem(8, 1_000_000, 1001)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x4)
-    got = L.dd_solve(ds, (8, 8, 8), mask, f, init, mode="bf16", history=True)
-    print(f"config 1: {got['iterations']} iterations, converged {got['converged']}, "
+    got = L.dd_solve(ds, (8, 8, 8), mask, f, init, mode=mode, history=True)
+    print(f"config 1 ({mode}): {got['iterations']} iterations, converged {got['converged']}, "
           f"{got['elapsed_ms']:.1f} ms, cg {got['cg_iterations']}", flush=True)
     assert got["converged"]
     pc = fe.ConstraintProjector(m, C0, mask, f)

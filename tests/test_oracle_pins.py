@@ -206,6 +206,23 @@ def test_pd_few_queries_path_matches_many_queries_path(C0):
     assert np.array_equal(i32, ref[0]) and np.array_equal(d32, ref[1])
 
 
+def test_pd_whitened_equals_raw_on_exact_projection_workload(C0):
+    """The oracle's whitened brute force (the timed CPU baseline and the check of
+    the 2^27 sample) gives the raw-metric brute force's answer on the whole
+    N = 65536, m = 4096 workload: equal indices wherever the raw best is clear
+    of the runner-up by 1e-12, distances within 1e-13 relative (the two forms
+    differ only in rounding)."""
+    e, s = ddsynth.data_points(65536, 1000)
+    qe, qs, _ = ddsynth.queries(e, s, 4096, 2000)
+    ri, rd, r2 = oracle.pd_raw(e, s, C0, qe, qs)
+    wi, wd, w2 = oracle.pd_white(oracle.whiten(e, s, C0), oracle.whiten(qe, qs, C0))
+    clear = r2 > rd * (1 + 1e-12)
+    assert clear.mean() > 0.99
+    assert np.array_equal(wi[clear], ri[clear])
+    np.testing.assert_allclose(wd, rd, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(w2, r2, rtol=1e-13, atol=0)
+
+
 # ----------------------------------------------------------------------------
 # Finite elements
 # ----------------------------------------------------------------------------
