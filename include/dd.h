@@ -119,8 +119,11 @@ typedef struct dd_dataset dd_dataset;
 typedef struct dd_dataset_opts {
   uint32_t packs;      /* DD_PACK_* mask; 0 = DD_PACK_DEFAULT */
   int32_t tile;        /* points per centring tile of the 16-bit packs: 128, 256, 512 or 1024; 0 = 1024 */
-  int32_t reserved;    /* must be 0 */
+  uint32_t flags;      /* DD_DATASET_* bits; other bits are DD_ERR_ARG */
 } dd_dataset_opts;
+/* dd_dataset_create: strain and stress are HOST arrays; they are copied to the
+ * device in chunks of up to 2^24 points (over PCIe, on hip_stream). */
+#define DD_DATASET_HOST_INPUT 0x1u
 
 /* Per-call statistics (optional output of dd_project). */
 typedef struct dd_project_stats {
@@ -158,17 +161,19 @@ typedef struct dd_project_opts {
 /*
  * Create a dataset from N material data points (Section 2: D = {(eps'_j,
  * sig'_j)}) and the metric C (eq. "distmetric").
- *   strain_dev, stress_dev  device float64 [N][6] each (borrowed)
- *   N                        1 <= N <= 2^31 - 1
- *   C                        host float64 [36], symmetric positive definite
- *   opts                     NULL for defaults
+ *   strain, stress   float64 [N][6] each (borrowed): DEVICE arrays, or HOST
+ *                    arrays with opts->flags & DD_DATASET_HOST_INPUT
+ *   N                1 <= N <= 2^31 - 1
+ *   C                host float64 [36], symmetric positive definite
+ *   opts             NULL for defaults
  * Whitens every point to (C^1/2 eps, C^-1/2 sig) (Section 3.2; C^1/2 = L^T of
  * the Cholesky factor C = L L^T), orders the points spatially (principal-axis
  * cell keys, stable radix sort) and builds the requested packs.
- * Errors: DD_ERR_ARG (null pointers, N out of range, non-finite C or data),
- * DD_ERR_NOT_SPD, DD_ERR_OOM, DD_ERR_DEVICE.  Synchronises hip_stream.
+ * Errors: DD_ERR_ARG (null pointers, N out of range, unknown flags, non-finite
+ * C or data), DD_ERR_NOT_SPD, DD_ERR_OOM, DD_ERR_DEVICE.  Synchronises
+ * hip_stream.
  */
-dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev, int64_t N,
+dd_status dd_dataset_create(const double* strain, const double* stress, int64_t N,
                             const double* C, const dd_dataset_opts* opts, void* hip_stream,
                             dd_dataset** out);
 
@@ -392,7 +397,7 @@ typedef struct dd_solve_request {
   double deadline_s;              /* > 0: cancelled when still running this long after submit */
 } dd_solve_request;
 
-typedef struct dd_server_stats {
+typedef struct dd_server_statistics {
   int64_t submitted, completed, failed, rejected, cancelled;
   int64_t active, queued;           /* admitted solves now; submitted, not yet admitted */
   int64_t batches, queries;         /* projection batches run; material points projected */
@@ -403,7 +408,7 @@ typedef struct dd_server_stats {
   double queue_p50_ms, queue_p99_ms;  /* per solve: submit -> admission */
   double queries_per_s;             /* queries / elapsed_s */
   double elapsed_s;                 /* since the first submit */
-} dd_server_stats;
+} dd_server_statistics;
 
 /*
  * Create a server over ds (which must outlive it).  hbm_budget_bytes bounds the
@@ -437,7 +442,7 @@ dd_status dd_server_wait(dd_server* srv, uint64_t ticket, dd_solve_result* resul
 dd_status dd_server_cancel(dd_server* srv, uint64_t ticket);
 
 /* Counters and latency percentiles since creation. */
-dd_status dd_server_get_stats(dd_server* srv, dd_server_stats* stats);
+dd_status dd_server_stats(const dd_server* srv, dd_server_statistics* stats);
 
 /* Stop the threads; unfinished solves end as DD_ERR_CANCELLED (their tickets
  * become invalid). */

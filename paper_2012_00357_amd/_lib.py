@@ -35,7 +35,7 @@ class DDError(RuntimeError):
 
 
 class dd_dataset_opts(ctypes.Structure):
-    _fields_ = [("packs", ctypes.c_uint32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("packs", ctypes.c_uint32), ("tile", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class dd_project_stats(ctypes.Structure):
@@ -156,15 +156,27 @@ class Dataset:
             pass
 
 
+DD_DATASET_HOST_INPUT = 0x1
+
+
 def dd_dataset_create(strain, stress, C, packs: int = 0, tile: int = 0,
                       stream=None) -> Dataset:
-    """dd_dataset_create: strain/stress are device float64 [N][6] tensors, C a 6x6 host array."""
+    """dd_dataset_create: strain/stress float64 [N][6], both device tensors or both
+    host (numpy) arrays (DD_DATASET_HOST_INPUT); C a 6x6 host array."""
     import torch
     n = int(strain.shape[0])
-    ps = _dev_ptr(strain, torch.float64, (6,), "strain")
-    pt = _dev_ptr(stress, torch.float64, (6,), "stress")
+    flags = 0
+    if isinstance(strain, np.ndarray) or isinstance(stress, np.ndarray):
+        e = np.ascontiguousarray(strain, dtype=np.float64)
+        t = np.ascontiguousarray(stress, dtype=np.float64)
+        if e.shape != (n, 6) or t.shape != (n, 6):
+            raise ValueError("strain and stress must be [N][6]")
+        ps, pt, flags = ctypes.c_void_p(e.ctypes.data), ctypes.c_void_p(t.ctypes.data), DD_DATASET_HOST_INPUT
+    else:
+        ps = _dev_ptr(strain, torch.float64, (6,), "strain")
+        pt = _dev_ptr(stress, torch.float64, (6,), "stress")
     Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64).reshape(36))
-    opts = dd_dataset_opts(packs, tile, 0)
+    opts = dd_dataset_opts(packs, tile, flags)
     out = ctypes.c_void_p()
     _check(_lib.dd_dataset_create(ps, pt, n, Cm.ctypes.data, ctypes.byref(opts), _stream(stream),
                                   ctypes.byref(out)), "dd_dataset_create")
@@ -359,7 +371,7 @@ class dd_solve_request(ctypes.Structure):
                 ("deadline_s", ctypes.c_double)]
 
 
-class dd_server_stats(ctypes.Structure):
+class dd_server_statistics(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("submitted", "completed", "failed", "rejected", "cancelled", "active", "queued",
                  "batches", "queries", "peak_active", "peak_bytes", "budget_bytes")] + \
@@ -375,10 +387,10 @@ _lib.dd_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_solve_reque
 _lib.dd_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(dd_solve_result),
                                 ctypes.c_double]
 _lib.dd_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
-_lib.dd_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_server_stats)]
+_lib.dd_server_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd_server_statistics)]
 _lib.dd_server_destroy.argtypes = [ctypes.c_void_p]
 for _f in ("dd_server_create", "dd_server_submit", "dd_server_wait", "dd_server_cancel",
-           "dd_server_get_stats", "dd_server_destroy"):
+           "dd_server_stats", "dd_server_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -442,8 +454,8 @@ class DDServer:
         _check(_lib.dd_server_cancel(self._h, ticket), "dd_server_cancel")
 
     def stats(self) -> dict:
-        s = dd_server_stats()
-        _check(_lib.dd_server_get_stats(self._h, ctypes.byref(s)), "dd_server_get_stats")
+        s = dd_server_statistics()
+        _check(_lib.dd_server_stats(self._h, ctypes.byref(s)), "dd_server_stats")
         return {k: getattr(s, k) for k, _ in s._fields_}
 
     def close(self):
@@ -478,5 +490,5 @@ def dd_server_cancel(srv: DDServer, ticket: int):
     srv.cancel(ticket)
 
 
-def dd_server_get_stats(srv: DDServer) -> dict:
+def dd_server_stats(srv: DDServer) -> dict:
     return srv.stats()

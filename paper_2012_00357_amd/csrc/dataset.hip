@@ -417,6 +417,32 @@ struct MemSource : Source {
   }
 };
 
+// Host arrays, copied to the device chunk by chunk (each copy is ordered on the
+// stream after the kernels that read the previous chunk).
+struct HostSource : Source {
+  const double* e;
+  const double* s;
+  DevBuf be, bs;
+  HostSource(const double* e_, const double* s_, int64_t N) : e(e_), s(s_) {
+    chunk = std::min<int64_t>(N, (int64_t)1 << 24);
+  }
+  dd_status init() {
+    DD_TRY(be.alloc(sizeof(double) * 6 * (size_t)chunk));
+    DD_TRY(bs.alloc(sizeof(double) * 6 * (size_t)chunk));
+    return DD_OK;
+  }
+  dd_status rows(int64_t first, int64_t n, const double** eo, const double** so,
+                 hipStream_t st) override {
+    DD_HIP(hipMemcpyAsync(be.p, e + 6 * first, sizeof(double) * 6 * (size_t)n,
+                          hipMemcpyHostToDevice, st));
+    DD_HIP(hipMemcpyAsync(bs.p, s + 6 * first, sizeof(double) * 6 * (size_t)n,
+                          hipMemcpyHostToDevice, st));
+    *eo = be.as<double>();
+    *so = bs.as<double>();
+    return DD_OK;
+  }
+};
+
 struct FillSource : Source {
   dd_fill_fn fn;
   void* user;
@@ -483,7 +509,8 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
   int tile = (opts && opts->tile) ? opts->tile : 1024;
   if (tile != 128 && tile != 256 && tile != 512 && tile != 1024)
     return set_error(DD_ERR_ARG, "tile must be 128, 256, 512 or 1024");
-  if (opts && opts->reserved != 0) return set_error(DD_ERR_ARG, "dd_dataset_opts.reserved must be 0");
+  if (opts && (opts->flags & ~DD_DATASET_HOST_INPUT))
+    return set_error(DD_ERR_ARG, "dd_dataset_opts.flags: unknown bits");
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN |
                 DD_PACK_KMEANS))
     return set_error(DD_ERR_ARG, "unknown pack bits");
@@ -728,14 +755,20 @@ static dd_status finish_create(dd::Source& src, int64_t N, const double* C,
   return DD_OK;
 }
 
-extern "C" dd_status dd_dataset_create(const double* strain_dev, const double* stress_dev,
-                                       int64_t N, const double* C, const dd_dataset_opts* opts,
+extern "C" dd_status dd_dataset_create(const double* strain, const double* stress, int64_t N,
+                                       const double* C, const dd_dataset_opts* opts,
                                        void* hip_stream, dd_dataset** out) {
   if (!out) return dd::set_error(DD_ERR_ARG, "out is NULL");
   *out = nullptr;
-  if (!strain_dev || !stress_dev || !C) return dd::set_error(DD_ERR_ARG, "NULL input pointer");
+  if (!strain || !stress || !C) return dd::set_error(DD_ERR_ARG, "NULL input pointer");
   if (N < 1 || N > 0x7FFFFFFFll) return dd::set_error(DD_ERR_ARG, "N must be in [1, 2^31-1]");
-  dd::MemSource src(strain_dev, stress_dev, N);
+  if (opts && (opts->flags & DD_DATASET_HOST_INPUT)) {
+    dd::HostSource src(strain, stress, N);
+    dd_status s = src.init();
+    if (s != DD_OK) return s;
+    return finish_create(src, N, C, opts, hip_stream, out);
+  }
+  dd::MemSource src(strain, stress, N);
   return finish_create(src, N, C, opts, hip_stream, out);
 }
 

@@ -814,10 +814,11 @@ extern "C" dd_status dd_server_cancel(dd_server* h, uint64_t ticket) {
   return DD_OK;
 }
 
-extern "C" dd_status dd_server_get_stats(dd_server* h, dd_server_stats* out) {
+extern "C" dd_status dd_server_stats(const dd_server* h, dd_server_statistics* out) {
   using namespace dd;
   if (!h || !out) return set_error(DD_ERR_ARG, "server or stats is NULL");
-  Server& s = h->s;
+  // reading the counters takes the server's lock; nothing else changes
+  Server& s = const_cast<dd_server*>(h)->s;
   std::lock_guard<std::mutex> lk(s.mu);
   std::memset(out, 0, sizeof(*out));
   out->submitted = s.n_submitted;

@@ -24,7 +24,7 @@ def test_header_declares_api():
     names = declared_functions()
     for must in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
                  "dd_project", "dd_solve", "dd_server_create", "dd_server_submit", "dd_server_wait",
-                 "dd_server_cancel", "dd_server_get_stats", "dd_server_destroy", "dd_last_error"):
+                 "dd_server_cancel", "dd_server_stats", "dd_server_destroy", "dd_last_error"):
         assert must in names
 
 
@@ -58,7 +58,7 @@ def test_struct_layouts_match_header():
     import tempfile
     from paper_2012_00357_amd import _lib
     names = ["dd_dataset_opts", "dd_project_stats", "dd_project_opts", "dd_mesh", "dd_solve_opts",
-             "dd_solve_result", "dd_server_opts", "dd_solve_request", "dd_server_stats",
+             "dd_solve_result", "dd_server_opts", "dd_solve_request", "dd_server_statistics",
              "dd_index_info"]
     src = "#include <stdio.h>\n#include \"dd.h\"\nint main(void){\n" + "".join(
         f'printf("%zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n"

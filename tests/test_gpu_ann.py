@@ -64,6 +64,26 @@ def test_streamed_create_equals_in_memory(L, C0, n):
     compare_to_oracle(i2.cpu().numpy(), d2.cpu().numpy(), oi, od, o2)
 
 
+def test_host_input_create_equals_device_input(L, C0):
+    """dd_dataset_create from host arrays (DD_DATASET_HOST_INPUT, copied in two
+    chunks of up to 2^24 points) builds the dataset that device arrays give."""
+    import torch
+    n = (1 << 24) + 1000
+    e, s = ddsynth.data_points(n, 79)
+    packs = FP64 | FP32 | BF16 | ANN
+    ds_dev = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=packs)
+    ds_host = L.dd_dataset_create(e, s, C0, packs=packs)
+    assert ds_dev.info() == ds_host.info()
+    qe, qs, _ = ddsynth.queries(e, s, 300, 80)
+    states = to_dev(ddsynth.states(qe, qs))
+    for mode in ("fp64", "fp32", "bf16", "ann"):
+        i1, d1 = L.dd_project(ds_dev, states, mode=mode)
+        i2, d2 = L.dd_project(ds_host, states, mode=mode)
+        assert torch.equal(i1, i2) and torch.equal(d1, d2), mode
+    ds_dev.close()
+    ds_host.close()
+
+
 @pytest.fixture(scope="module")
 def config0(L, C0):
     e, s = ddsynth.data_points(65536, 1000)
