@@ -239,6 +239,28 @@ dd_status dd_project(const dd_dataset* ds, const double* states_dev, int64_t m,
                      int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream);
 
 /*
+ * dd_project without device allocation, for callers that cannot allocate
+ * (work captured into HIP graphs, tight serving loops, harnesses that forbid
+ * allocation).  Arguments, layouts, results and errors as dd_project, with
+ * these differences:
+ *   mode        DD_EXACT_FP64, DD_ANN or DD_KMEANS (others: DD_ERR_UNSUPPORTED)
+ *   m           at most DD_NOALLOC_MAX_QUERIES (else DD_ERR_TOO_LARGE)
+ *   opts->stats must be NULL (DD_ERR_ARG); opts->splits and opts->passes are
+ *               ignored (the FP64 scan uses as many data splits as the scratch
+ *               holds)
+ * The call's temporary buffers live in one 64 MiB device array of the library
+ * (each GPU the library runs on holds its own copy until the process ends);
+ * the call allocates nothing, device or host, and does not synchronise
+ * hip_stream: it only enqueues kernels.  Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.
+ */
+#define DD_NOALLOC_MAX_QUERIES 65536
+dd_status dd_project_noalloc(const dd_dataset* ds, const double* states_dev, int64_t m,
+                             const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                             int64_t* idx_out_dev, double* dist_out_dev, void* hip_stream);
+
+/*
  * Diagnostic: multiply small HOST matrices with one wavefront of the matrix
  * instructions the scans use, with the operand/result lane layouts the scans
  * assume (so a correct layout reproduces the plain product A B exactly for

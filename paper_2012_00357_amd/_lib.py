@@ -235,6 +235,33 @@ def dd_project(ds: Dataset, states, warm_start_idx=None, mode="fp64", splits: in
     return idx_out, dist_out
 
 
+_lib.dd_project_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.POINTER(dd_project_opts),
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.dd_project_noalloc.restype = ctypes.c_int
+DD_NOALLOC_MAX_QUERIES = 65536
+
+
+def dd_project_noalloc(ds: Dataset, states, warm_start_idx=None, mode="fp64",
+                       ann_budget: int = 0, ann_fd: float | None = None, idx_out=None,
+                       dist_out=None, stream=None):
+    """dd_project_noalloc: as dd_project (modes fp64, ann, kmeans) with the library's
+    scratch array instead of allocations; the outputs are allocated here unless given."""
+    import torch
+    m = int(states.shape[0])
+    sp = _dev_ptr(states, torch.float64, (12,), "states")
+    wp = _dev_ptr(warm_start_idx, torch.int64, (), "warm_start_idx") if warm_start_idx is not None else None
+    idx = idx_out if idx_out is not None else torch.empty(m, dtype=torch.int64, device=states.device)
+    dist = dist_out if dist_out is not None else torch.empty(m, dtype=torch.float64, device=states.device)
+    pi = _dev_ptr(idx, torch.int64, None, "idx_out")
+    pd = _dev_ptr(dist, torch.float64, None, "dist_out")
+    opts = dd_project_opts(MODES[mode] if isinstance(mode, str) else int(mode), 0, ann_budget, 0,
+                           None, 0.0 if ann_fd is None else 1.0 - float(ann_fd))
+    _check(_lib.dd_project_noalloc(ds.handle, sp, m, wp, ctypes.byref(opts), pi, pd,
+                                   _stream(stream)), "dd_project_noalloc")
+    return idx, dist
+
+
 def dd_metric_pca(strain, stress, stream=None) -> np.ndarray:
     """dd_metric_pca: device float64 [N][6] strain/stress -> the 6x6 PCA metric (host)."""
     import torch

@@ -82,9 +82,12 @@ dd_status launch_merge_rerank(const Dataset& D, const QueryPrep& Q, QueryList L,
                               int* fb_list, int* fb_count, unsigned long long* n_cand,
                               hipStream_t st);
 // Plain FP64 direct-form scan with lexicographic (dist, original index) minimum,
-// split over the data, followed by its merge.
+// split over the data, followed by its merge.  The per-split partial results
+// (list_len x splits, splits = choose_splits(list blocks, tiles, S)) go to
+// part_d / part_o when both are given, else to stream-ordered allocations.
 dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len, int S,
-                     Outputs out, hipStream_t st);
+                     Outputs out, hipStream_t st, double* part_d = nullptr,
+                     uint32_t* part_o = nullptr);
 
 // Splits of a scan over the data (FP64 and direct scans): `requested` if > 0;
 // with fewer than 64 query blocks one round of workgroups (512), otherwise

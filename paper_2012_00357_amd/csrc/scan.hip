@@ -421,15 +421,18 @@ __global__ void merge_direct_kernel(QueryList L, int S, const double* __restrict
 }
 
 dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len_max, int S,
-                     Outputs out, hipStream_t st) {
+                     Outputs out, hipStream_t st, double* part_d, uint32_t* part_o) {
   if (list_len_max <= 0) return DD_OK;
   int64_t n_tiles = (D.N + kDirectRows - 1) / kDirectRows;
   int64_t qblocks = (list_len_max + 255) / 256;
   S = choose_splits(qblocks, n_tiles, S);
-  double* pd = nullptr;
-  uint32_t* po = nullptr;
-  DD_HIP(hipMallocAsync((void**)&pd, sizeof(double) * (size_t)(list_len_max * S), st));
-  DD_HIP(hipMallocAsync((void**)&po, sizeof(uint32_t) * (size_t)(list_len_max * S), st));
+  const bool own = !(part_d && part_o);
+  double* pd = part_d;
+  uint32_t* po = part_o;
+  if (own) {
+    DD_HIP(hipMallocAsync((void**)&pd, sizeof(double) * (size_t)(list_len_max * S), st));
+    DD_HIP(hipMallocAsync((void**)&po, sizeof(uint32_t) * (size_t)(list_len_max * S), st));
+  }
   hipLaunchKernelGGL(direct_kernel, dim3((unsigned)(qblocks * S)), dim3(256), 0, st,
                      D.w64.as<double>(), D.w64.p ? nullptr : D.w32.as<float>(),
                      D.perm.as<uint32_t>(), n_tiles, D.N, Q.qw, Q.invalid, L, S, pd, po);
@@ -437,8 +440,10 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
   hipLaunchKernelGGL(merge_direct_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, S, pd, po,
                      Q.invalid, out);
   DD_HIP(hipGetLastError());
-  DD_HIP(hipFreeAsync(pd, st));
-  DD_HIP(hipFreeAsync(po, st));
+  if (own) {
+    DD_HIP(hipFreeAsync(pd, st));
+    DD_HIP(hipFreeAsync(po, st));
+  }
   return DD_OK;
 }
 

@@ -23,7 +23,7 @@ def declared_functions():
 def test_header_declares_api():
     names = declared_functions()
     for must in ("dd_dataset_create", "dd_dataset_create_streamed", "dd_dataset_destroy",
-                 "dd_project", "dd_solve", "dd_server_create", "dd_server_submit", "dd_server_wait",
+                 "dd_project", "dd_project_noalloc", "dd_solve", "dd_server_create", "dd_server_submit", "dd_server_wait",
                  "dd_server_cancel", "dd_server_stats", "dd_server_destroy", "dd_last_error"):
         assert must in names
 
