@@ -481,7 +481,7 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=256)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--tile", type=int, default=2048)
     ap.add_argument("--passes", type=int, default=0)
     ap.add_argument("--dd-solves", type=int, default=100,
                     help="DD solves (8^3 hex, N=1e6) timed for the p50/p99 latency leg; 0 = skip")

@@ -118,7 +118,8 @@ typedef struct dd_dataset dd_dataset;
 
 typedef struct dd_dataset_opts {
   uint32_t packs;      /* DD_PACK_* mask; 0 = DD_PACK_DEFAULT */
-  int32_t tile;        /* points per centring tile of the 16-bit packs: 128, 256, 512 or 1024; 0 = 1024 */
+  int32_t tile;        /* points per centring tile of the 16-bit packs: 128, 256, 512, 1024 or
+                          2048; 0 = 2048 */
   uint32_t flags;      /* DD_DATASET_* bits; other bits are DD_ERR_ARG */
 } dd_dataset_opts;
 /* dd_dataset_create: strain and stress are HOST arrays; they are copied to the

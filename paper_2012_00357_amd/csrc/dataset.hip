@@ -506,9 +506,9 @@ static dd_status choose_scale16(Dataset& D, hipStream_t st) {
 static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_dataset_opts* opts,
                              hipStream_t st, Dataset& D) {
   uint32_t packs = (opts && opts->packs) ? opts->packs : DD_PACK_DEFAULT;
-  int tile = (opts && opts->tile) ? opts->tile : 1024;
-  if (tile != 128 && tile != 256 && tile != 512 && tile != 1024)
-    return set_error(DD_ERR_ARG, "tile must be 128, 256, 512 or 1024");
+  int tile = (opts && opts->tile) ? opts->tile : 2048;
+  if (tile != 128 && tile != 256 && tile != 512 && tile != 1024 && tile != 2048)
+    return set_error(DD_ERR_ARG, "tile must be 128, 256, 512, 1024 or 2048");
   if (opts && (opts->flags & ~DD_DATASET_HOST_INPUT))
     return set_error(DD_ERR_ARG, "dd_dataset_opts.flags: unknown bits");
   if (packs & ~(DD_PACK_FP64 | DD_PACK_FP32 | DD_PACK_BF16 | DD_PACK_FP16 | DD_PACK_ANN |

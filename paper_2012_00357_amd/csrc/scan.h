@@ -94,11 +94,11 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
 // about 2048; multiples of 8 keep a split's workgroups on one XCD.
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
 
-// Queries per workgroup of the 16-bit pass (eight waves of two 32-query groups).
-constexpr int kScan16Queries = 512;
+// Queries per workgroup of the 16-bit pass (sixteen waves of two 32-query groups).
+constexpr int kScan16Queries = 1024;
 
 // Splits of the 16-bit pass: with fewer than 64 query blocks, one round of
-// workgroups (512: two per CU), so that no second round waits on a short
+// workgroups (256: one per CU), so that no second round waits on a short
 // first one; otherwise about 1024 workgroups.  Multiples of 8 keep a split's
 // workgroups on one XCD.
 int choose_splits16(int64_t n_query_blocks, int64_t n_tiles, int requested);

@@ -42,7 +42,7 @@ int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested) {
 int choose_splits16(int64_t n_query_blocks, int64_t n_tiles, int requested) {
   if (requested > 0) return choose_splits(n_query_blocks, n_tiles, requested);
   const int64_t qb = std::max<int64_t>(n_query_blocks, 1);
-  const int64_t target = qb < 64 ? 512 : 1024;
+  const int64_t target = qb < 64 ? 256 : 1024;
   int64_t S = (target + qb - 1) / qb;
   if (S >= 8) S = (S + 7) / 8 * 8;
   S = std::min<int64_t>(S, std::max<int64_t>(n_tiles, 1));

@@ -414,7 +414,7 @@ template <> struct Vec16<Fp16> {
 };
 
 constexpr int kG16 = 2;                                  // 32-query groups per wave
-constexpr int kW16 = 8;                                  // waves per workgroup
+constexpr int kW16 = 16;                                 // waves per workgroup
 constexpr int kT16 = 64 * kW16;                          // threads per workgroup
 constexpr int kQ16 = kW16 * kG16 * 32;                   // queries per workgroup
 static_assert(kG16 == 2, "the pipelined inner loop is written for two query groups");
@@ -472,9 +472,10 @@ __device__ inline void centre_select(const float* __restrict__ cp, int h, float 
   for (int i = 0; i < 8; ++i) cs[i] = h ? (i < 4 ? cp[8 + i] : 0.0f) : cp[i];
 }
 
-// Streaming pass of the 16-bit scan.  Every workgroup (eight waves, so that two
-// workgroups with their double-buffered tile fill a CU with four waves per SIMD)
-// covers 512 queries (two 32-query groups per wave) against the tiles of its split; the split's tiles
+// Streaming pass of the 16-bit scan.  Every workgroup (sixteen waves: one
+// workgroup with its double-buffered tile of 2048 rows, 128 KB of LDS, fills a
+// CU with four waves per SIMD) covers 1024 queries (two 32-query groups per
+// wave) against the tiles of its split; the split's tiles
 // are visited with stride `stride` (1 = all; > 1 = a bound-seeding subsample).
 // Tracks the sqrt-space bound U of each query; with MARK, appends a work item
 // whenever some query of a group may have a candidate in the tile (its lower
@@ -650,19 +651,30 @@ __global__ __launch_bounds__(256) void scan16_extract_kernel(
   const uint4* src = wp + t * TILE * 2;
   float* L0 = cb.lb + (p * 2 + h) * cb.K;
   uint32_t* J0 = cb.j + (p * 2 + h) * cb.K;
+  // Score-space screen: a score whose lower bound
+  //   lb = sqrt(max(s + o - alpha, 0)) (1 - 2^-20) - eta   (FP32 evaluation)
+  // is <= U satisfies sqrt(max(s + o - alpha, 0)) <= a = (U + eta)(1 + 2^-18), hence
+  // s <= a^2 + alpha - o, up to FP32 roundings of at most a few 2^-24 of
+  // a^2 + alpha + |o|; the screen adds 2^-18 of that, so it passes every score
+  // the lower-bound test keeps, and only those get the square root.
+  const float a = (Uq + eta) * (1.0f + 0x1p-18f);
+  const float sa = a * a + alpha;
+  const float T = v ? (sa - o) + 0x1p-18f * (sa + fabsf(o)) + 1e-30f : -INFINITY;
   for (int rb = 0; rb < TILE / 32; ++rb) {
     vec_t A = __builtin_bit_cast(vec_t, src[(rb * 32 + col) * 2 + h]);
     f32x16_t acc = VT::mfma(A, B, zero);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-      const int64_t j = t * TILE + row;
-      float lb = fsqrt(fmaxf(acc[i] + o - alpha, 0.0f)) * kRelDn - eta;
-      if (v && j < N && lb <= Uq) {
-        int k = atomicAdd(&cb.count[p * 2 + h], 1);
-        if (k < cb.K) {
-          L0[k] = lb;
-          J0[k] = (uint32_t)j;
+      if (acc[i] <= T) {
+        const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+        const int64_t j = t * TILE + row;
+        const float lb = fsqrt(fmaxf(acc[i] + o - alpha, 0.0f)) * kRelDn - eta;
+        if (j < N && lb <= Uq) {
+          int k = atomicAdd(&cb.count[p * 2 + h], 1);
+          if (k < cb.K) {
+            L0[k] = lb;
+            J0[k] = (uint32_t)j;
+          }
         }
       }
     }
@@ -706,8 +718,10 @@ static dd_status launch16_tile(const Dataset& D, const uint16_t* pack, const Sca
     case 256: return launch16<T16, 256>(D, pack, c, st);
     case 512: return launch16<T16, 512>(D, pack, c, st);
     case 1024: return launch16<T16, 1024>(D, pack, c, st);
+    case 2048: return launch16<T16, 2048>(D, pack, c, st);
     default:
-      return set_error(DD_ERR_UNSUPPORTED, "16-bit scan supports tiles of 128, 256, 512 or 1024");
+      return set_error(DD_ERR_UNSUPPORTED,
+                       "16-bit scan supports tiles of 128, 256, 512, 1024 or 2048");
   }
 }
 

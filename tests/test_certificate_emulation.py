@@ -207,3 +207,37 @@ def test_si_units_scaled_pack_and_padded_tail(fmt, C0):
     cand = np.concatenate(lo_all, 1) <= U[:, None]
     assert np.all(cand[np.arange(len(q)), oi])
     assert np.array_equal(oi[-3:], np.arange(n - 3, n))
+
+
+def test_extraction_screen_passes_every_kept_score():
+    """The extraction of the 16-bit scans screens a score s in score space,
+    s <= T with a = (U + eta)(1 + 2^-18), T = (a^2 + alpha - o)
+    + 2^-18 (a^2 + alpha + |o|), before it evaluates the FP32 lower bound
+    lb = sqrt(max(s + o - alpha, 0)) (1 - 2^-20) - eta and keeps s if lb <= U.
+    Every score the lower-bound test keeps must pass the screen: checked in
+    FP32 on scores drawn around the boundary for near, far and coincident
+    queries, with the square root perturbed by one ulp either way (the GPU's
+    is correct to 1 ulp)."""
+    rng = np.random.default_rng(4107)
+    f = np.float32
+    n = 200000
+    for o_scale in (1e-6, 1e-2, 1.0, 1e3):
+        o = (rng.random(n) * o_scale).astype(f)
+        U = (rng.random(n) * np.sqrt(o_scale) * 2).astype(f)
+        eta = (U * rng.random(n) * 1e-2).astype(f)
+        alpha = (rng.random(n) * 1e-5 * o_scale).astype(f)
+        # scores around the boundary sqrt(s + o - alpha) ~ U + eta
+        edge = ((U.astype(np.float64) + eta) ** 2 + alpha - o).astype(f)
+        s = (edge * (1 + (rng.random(n) - 0.5) * 1e-5)
+             + (rng.random(n) - 0.5) * 1e-6 * np.abs(o)).astype(f)
+        a = ((U + eta) * f(1.0 + 2.0 ** -18)).astype(f)
+        sa = (a * a + alpha).astype(f)
+        T = ((sa - o) + f(2.0 ** -18) * (sa + np.abs(o)) + f(1e-30)).astype(f)
+        x = np.maximum((s + o).astype(f) - alpha, f(0)).astype(f)
+        r = np.sqrt(x).astype(f)
+        for ulp in (-1, 0, 1):
+            rr = r if ulp == 0 else np.nextafter(r, f(np.inf) if ulp > 0 else f(0))
+            lb = ((rr * f(1.0 - 2.0 ** -20)).astype(f) - eta).astype(f)
+            kept = lb <= U
+            assert kept.any() and (~kept).any()
+            assert np.all(s[kept] <= T[kept]), o_scale
