@@ -61,7 +61,7 @@ struct AnnArgs {
   const uint32_t* perm;
   const uint32_t* iperm;
   int64_t N;
-  double V[144];
+  const float* yq;         // [m][12] queries on the principal axes (rotate_queries_kernel)
   float xmax;
   int budget;
   QueryList L;
@@ -309,8 +309,12 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   const int64_t p = (int64_t)blockIdx.x * kWaves + wv;
   if (p >= list_len(A.L)) return;
   const int64_t q = list_query(A.L, p);
-  const float fd = (KMT && A.fd_q) ? A.fd_q[q] : A.fd;
-  const int budget = A.budget_q ? A.budget_q[q] : A.budget;
+  // one wave per query: the per-query accuracy is wave-uniform (scalar registers)
+  float fd = A.fd;
+  int budget = A.budget;
+  if (KMT && A.fd_q)
+    fd = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, A.fd_q[q])));
+  if (A.budget_q) budget = __builtin_amdgcn_readfirstlane(A.budget_q[q]);
   if (A.invalid[q]) {
     if (lane == 0) {
       A.out.idx[q] = -1;
@@ -320,20 +324,10 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
     return;
   }
   float qf[12], yq[12];
-  {
-    double qd[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      qd[k] = A.qw[12 * q + k];
-      qf[k] = (float)qd[k];
-    }
-#pragma unroll
-    for (int a = 0; a < 12; ++a) {
-      double y = 0.0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) y = fma(A.V[12 * k + a], qd[k], y);
-      yq[a] = (float)y;
-    }
+  for (int k = 0; k < 12; ++k) {
+    qf[k] = (float)A.qw[12 * q + k];
+    yq[k] = A.yq[12 * q + k];
   }
   const float qnorm = (float)sqrt(A.qn2[q]);
   const float ebase = kEps20 * qnorm;
@@ -644,6 +638,20 @@ __global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
   }
 }
 
+// Queries on the principal axes of the trees: yq[q][a] = sum_k V[k][a] q[k]
+// (FP64, rounded to FP32), one thread per (query, axis).
+__global__ void rotate_queries_kernel(const double* __restrict__ qw, int64_t m,
+                                      const double* __restrict__ V, float* __restrict__ yq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 12 * m) return;
+  const int64_t q = i / 12;
+  const int a = (int)(i - 12 * q);
+  double y = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) y = fma(V[12 * k + a], qw[12 * q + k], y);
+  yq[i] = (float)y;
+}
+
 }  // namespace
 
 dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max,
@@ -681,7 +689,14 @@ dd_status launch_ann_walk(const Dataset& D, const QueryPrep& Q, QueryList L, int
   A.perm = D.perm.as<uint32_t>();
   A.iperm = D.iperm.as<uint32_t>();
   A.N = D.N;
-  for (int i = 0; i < 144; ++i) A.V[i] = D.V[i];
+  // the walk runs over all states of the call (the identity list), whose
+  // rotated coordinates are formed first
+  if (L.list || !Q.yq || !D.vrot.p)
+    return set_error(DD_ERR_ARG, "walk: identity query list and room for the rotated queries");
+  hipLaunchKernelGGL(rotate_queries_kernel, dim3((unsigned)((12 * L.m + 255) / 256)), dim3(256), 0,
+                     st, Q.qw, L.m, D.vrot.as<double>(), Q.yq);
+  DD_HIP(hipGetLastError());
+  A.yq = Q.yq;
   A.xmax = __builtin_nextafterf((float)D.xmax, INFINITY);
   A.budget = budget;
   A.fd_q = kmt ? fd_q : nullptr;

@@ -586,6 +586,8 @@ static dd_status create_impl(Source& src, int64_t N, const double* C, const dd_d
           cov[12 * a + b] += (samp[12 * s + a] - mean[a]) * (samp[12 * s + b] - mean[b]);
     double ev[12];
     sym_eigen(12, cov, ev, D.V);
+    DD_TRY(D.vrot.alloc(sizeof(D.V)));
+    DD_HIP(hipMemcpyAsync(D.vrot.p, D.V, sizeof(D.V), hipMemcpyHostToDevice, st));
     for (int a = 0; a < kKeyAxes; ++a)
       for (int k = 0; k < 12; ++k) P.axes[kDim * a + k] = D.V[12 * k + a];
     for (int k = 0; k < 12; ++k) P.mean[k] = mean[k];

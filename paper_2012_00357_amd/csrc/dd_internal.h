@@ -145,6 +145,7 @@ struct Dataset {
   // principal axes of the whitened data (sample estimate): V[12*k + a] is
   // component k of axis a, axes by decreasing variance
   double V[kDim * kDim];
+  DevBuf vrot;     // double [144]: V on the device (the walks rotate their queries with it)
   double mean[kDim];
   double lo[kKeyAxes], hi[kKeyAxes];
   // ANN box tree over the sorted order: level 0 boxes bound leaves of kAnnLeaf

@@ -160,6 +160,8 @@ extern "C" dd_status dd_project_noalloc(const dd_dataset* ds, const double* stat
   const QueryList all{nullptr, nullptr, m};
   if (mode == DD_EXACT_FP64)
     return exact_from_scratch(D, Q, all, m, out, c, fb2, counters + 1, st);
+  if (!c.get(Q.yq, (size_t)m * 12))
+    return set_error(DD_ERR_TOO_LARGE, "dd_project_noalloc: scratch too small");
   unsigned long long* walk_stats = reinterpret_cast<unsigned long long*>(counters + 32);
   DD_TRY(launch_ann_walk(D, Q, all, m, warm_start_idx_dev, budget, out, fb1, counters, walk_stats,
                          nullptr, st, mode == DD_KMEANS, 1.0 - discount));

@@ -314,6 +314,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   } else if (walk_mode(mode)) {
     int* fb = nullptr;
     DD_TRY(sc.get(fb, (size_t)m));
+    DD_TRY(sc.get(Q.yq, (size_t)m * 12));
     ann = reinterpret_cast<unsigned long long*>(counters + 32);
     DD_TRY(timing.mark(1, st));
     if (dist2_out_dev && (budget != 0 || fd < 1.0))

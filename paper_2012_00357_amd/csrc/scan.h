@@ -12,6 +12,8 @@ struct QueryPrep {
   float* u32 = nullptr;     // [m] sqrt-space initial bound (warm start) or +inf, in the
                             // scaled coordinates of the 16-bit scans in those modes
   int* invalid = nullptr;   // [m] 1 for non-finite states
+  float* yq = nullptr;      // [m][12] queries on the principal axes of the dataset's trees
+                            // (walk modes; written by launch_ann_walk)
 };
 
 // Candidate lists written by the scans: slot = (list position * S + split) * P + part.
@@ -104,6 +106,7 @@ constexpr int kScan16Queries = 1024;
 int choose_splits16(int64_t n_query_blocks, int64_t n_tiles, int requested);
 
 // DD_ANN walk over the dataset's box tree (kmt: DD_KMEANS walk over its
+// k-means tree); Q.yq must hold room for the rotated queries.
 // k-means tree with radius factor fd) for the queries of L (one wavefront
 // each): writes outputs, appends overflowed queries to fb_list / fb_count, adds
 // (points visited, boxes tested, leaves visited, candidates reranked, leaf
