@@ -376,7 +376,7 @@ def serve_leg(L, C, n_solves, fracs=(0.5, 0.9), n_cap=8, modes=("bf16", "ann")):
 
 def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_000_000_000),
               seeds=5, mode="ann", kmeans_Ns=(100_000_000, 1_000_000_000),
-              kmeans_fds=(1.0, 0.0, 0.4), kmeans_ramp=20):
+              kmeans_fds=(1.0, 0.0, 0.4, 0.6, 0.8), kmeans_ramp=20):
     """The paper's own example (Section 3): cube of edge 10 mm, 20^3 hexahedra
     (64000 material points), bottom fixed, top rotated by 2 degrees; data from
     the nonlinear law with strains in +-0.025; metric from the PCA of the data;
@@ -452,7 +452,7 @@ def paper_leg(L, C=None, Ns=(1_000, 10_000, 100_000, 1_000_000, 100_000_000, 1_0
         build_s = round(time.time() - t, 2)
         for fd in kmeans_fds:
             ramp = kmeans_ramp if fd < 1.0 else 0
-            for local in ((False, True) if fd < 1.0 else (False,)):
+            for local in ((False, True) if 0.0 <= fd <= 0.4 else (False,)):
                 run = {"N": N, "f_d_final": fd, "ramp_iterations": ramp, "local_accuracy": local,
                        "dataset_build_s": build_s}
                 run.update(solves(ds, N, mode="kmeans", ann_fd=fd, ann_ramp=ramp,
