@@ -27,6 +27,21 @@ __device__ inline float min16(float run, const f32x16_t& a) {
   return fminf(fminf(run, m5), m6);
 }
 
+// Split and query block of this workgroup in a grid of (query blocks x S)
+// workgroups.  The command processor deals workgroups to the eight XCDs in
+// turn (workgroup b runs on XCD b % 8), so the grid is renumbered to give XCD x
+// the x-th eighth of the split-major order, every query block of one split
+// before the next: the workgroups an XCD holds at once then stream the same
+// data through its L2 instead of two or more splits competing for it.  A grid
+// whose size is not a multiple of eight keeps the plain order.
+__device__ inline void split_qblock(int S, int& split, int64_t& qblock) {
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned t = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+  const unsigned qblocks = G / (unsigned)S;
+  split = (int)(t / qblocks);
+  qblock = (int64_t)(t % qblocks);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 MFMA scan.  v_mfma_f64_16x16x4: A (16 data rows x 4 k) one double per
 // lane (row = lane%16, k = lane/16), B (4 k x 16 queries) one double per lane
@@ -46,8 +61,10 @@ __global__ __launch_bounds__(256) void scan64_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
   const int S = cb.S;
-  const int split = blockIdx.x % S;
-  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ64;
+  int split;
+  int64_t qblock;
+  split_qblock(S, split, qblock);
+  const int64_t qbase = qblock * kQ64;
   const int64_t len = list_len(L);
   if (qbase >= len) return;
   const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
@@ -212,8 +229,10 @@ __global__ __launch_bounds__(256, 3) void scan32_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, h = lane >> 5;
   const int S = cb.S;
-  const int split = blockIdx.x % S;
-  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ32;
+  int split;
+  int64_t qblock;
+  split_qblock(S, split, qblock);
+  const int64_t qbase = qblock * kQ32;
   const int64_t len = list_len(L);
   if (qbase >= len) return;
   const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
@@ -497,8 +516,10 @@ __global__ __launch_bounds__(kT16, 4) void scan16_pass_kernel(
   __shared__ uint4 lds[2][2 * TILE];  // [buffer][half * TILE + row]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, col = lane & 31;
-  const int split = blockIdx.x % S;
-  const int64_t qbase = (int64_t)(blockIdx.x / S) * kQ16;
+  int split;
+  int64_t qblock;
+  split_qblock(S, split, qblock);
+  const int64_t qbase = qblock * kQ16;
   const int64_t len = list_len(L);
   if (qbase >= len) return;
   const int64_t t0 = (int64_t)split * n_tiles / S, t1 = (int64_t)(split + 1) * n_tiles / S;
