@@ -431,19 +431,24 @@ typedef struct dd_server_statistics {
   double queue_p50_ms, queue_p99_ms;  /* per solve: submit -> admission */
   double queries_per_s;             /* queries / elapsed_s */
   double elapsed_s;                 /* since the first submit */
+  int64_t reserve_bytes;            /* the server's fixed reserve (batch buffers and the
+                                       scratch of a full projection batch), part of peak_bytes */
 } dd_server_statistics;
 
 /*
  * Create a server over ds (which must outlive it).  hbm_budget_bytes bounds the
- * summed device footprint of admitted solves (their P_C buffers, states and
- * projection scratch) plus the K^-1 inverses the server forms (from admission
- * of the solve that needs one, and for as long as the dataset's cache keeps
- * it); an inverse is formed on a builder thread while the other solves go on,
- * and a solve whose inverse cannot fit next to it even on an idle server is
- * run by CG (dd_solve's DD_SOLVE_CG trajectory); 0 = half of the free device
- * memory.  opts NULL = BF16
- * projections, defaults above.  Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED (mode
- * without its pack), DD_ERR_OOM, DD_ERR_DEVICE.
+ * server's device memory: a fixed reserve held from creation to destroy (the
+ * batch buffers and the scratch of a projection of max_batch states, which the
+ * batch projections carve every temporary buffer from, so they allocate
+ * nothing), plus the summed footprint of admitted solves (their P_C buffers and
+ * states), plus the K^-1 inverses the server forms (from admission of the solve
+ * that needs one, and for as long as the dataset's cache keeps it); an inverse
+ * is formed on a builder thread while the other solves go on, and a solve whose
+ * inverse cannot fit next to it even on an idle server is run by CG (dd_solve's
+ * DD_SOLVE_CG trajectory); 0 = half of the free device memory.  opts NULL =
+ * BF16 projections, defaults above.  Errors: DD_ERR_ARG, DD_ERR_UNSUPPORTED
+ * (mode without its pack), DD_ERR_TOO_LARGE (the reserve alone exceeds the
+ * budget: lower max_batch), DD_ERR_OOM, DD_ERR_DEVICE.
  */
 dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_bytes,
                            const dd_server_opts* opts, dd_server** out);

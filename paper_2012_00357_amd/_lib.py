@@ -404,7 +404,8 @@ class dd_server_statistics(ctypes.Structure):
                  "batches", "queries", "peak_active", "peak_bytes", "budget_bytes")] + \
                [(k, ctypes.c_double) for k in
                 ("proj_p50_ms", "proj_p99_ms", "solve_p50_ms", "solve_p99_ms", "queue_p50_ms",
-                 "queue_p99_ms", "queries_per_s", "elapsed_s")]
+                 "queue_p99_ms", "queries_per_s", "elapsed_s")] + \
+               [("reserve_bytes", ctypes.c_int64)]
 
 
 _lib.dd_server_create.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(dd_server_opts),

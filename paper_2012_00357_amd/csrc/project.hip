@@ -14,16 +14,26 @@ namespace {
 
 // Device scratch of one call, carved from one of the dataset's arenas (see
 // ScratchArena); what does not fit is allocated stream-ordered and freed when
-// the call ends.
+// the call ends.  With a caller's arena (`fixed`) the call carves from that
+// block only and fails with DD_ERR_TOO_LARGE rather than allocate: the FP64
+// and direct scans then take as many data splits as the block holds.
 struct Scratch {
   const Dataset& D;
   hipStream_t st;
   std::unique_ptr<ScratchArena> a;
+  ScratchArena* fixed = nullptr;
   size_t off = 0;    // bytes carved from the block
   size_t need = 0;   // bytes requested by the call
   std::vector<void*> extra;
-  Scratch(const Dataset& d, hipStream_t s) : D(d), st(s) {}
+  Scratch(const Dataset& d, hipStream_t s, ScratchArena* f = nullptr) : D(d), st(s), fixed(f) {}
+  ScratchArena* arena() const { return fixed ? fixed : a.get(); }
+  // bytes left in a caller's block; SIZE_MAX with the dataset's arenas
+  size_t room() const { return fixed ? fixed->bytes - off : SIZE_MAX; }
   dd_status open() {
+    if (fixed) {
+      DD_HIP(hipStreamWaitEvent(st, fixed->done, 0));
+      return DD_OK;
+    }
     {
       std::lock_guard<std::mutex> lk(D.arena_mu);
       if (!D.arenas.empty()) {
@@ -43,16 +53,19 @@ struct Scratch {
     return DD_OK;
   }
   // word i of the arena's pinned host memory
-  uint32_t* host_word(int i) const { return a->pinned + i; }
+  uint32_t* host_word(int i) const { return arena()->pinned + i; }
   template <class T>
   dd_status get(T*& out, size_t n) {
     const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
     need += bytes;
-    if (a->block && off + bytes <= a->bytes) {
-      out = reinterpret_cast<T*>(static_cast<char*>(a->block) + off);
+    ScratchArena* ar = arena();
+    if (ar->block && off + bytes <= ar->bytes) {
+      out = reinterpret_cast<T*>(static_cast<char*>(ar->block) + off);
       off += bytes;
       return DD_OK;
     }
+    if (fixed)
+      return set_error(DD_ERR_TOO_LARGE, "projection scratch beyond the caller's reserve");
     void* p = nullptr;
     hipError_t e = hipMallocAsync(&p, bytes, st);
     if (e != hipSuccess)
@@ -64,6 +77,10 @@ struct Scratch {
   }
   ~Scratch() {
     for (void* p : extra) (void)hipFreeAsync(p, st);
+    if (fixed) {
+      if (hipEventRecord(fixed->done, st) != hipSuccess) (void)hipStreamSynchronize(st);
+      return;
+    }
     if (!a) return;
     if (need > a->bytes && need <= kArenaKeepBytes) {
       // grow the block for the next call once the work queued on it is done
@@ -144,12 +161,55 @@ struct Counters {
   unsigned long long cand;
 };
 
+// Bytes per (query, split) of the candidate lists of the FP64 scan (four lists
+// of 16 entries, their counts, the split's bound) and of the FP32 scan (two
+// lists), and per (query, split) of the direct scan's partial results.
+constexpr size_t kCandBytes64 = 4 * 16 * (sizeof(float) + sizeof(uint32_t)) + 4 * sizeof(int) + sizeof(float);
+constexpr size_t kCandBytes32 = 2 * 16 * (sizeof(float) + sizeof(uint32_t)) + 2 * sizeof(int) + sizeof(float);
+constexpr size_t kDirectBytes = sizeof(double) + sizeof(uint32_t);
+constexpr size_t kAlignSlack = 16 * 256;   // 256-byte alignment of up to 16 pieces
+
+size_t aligned(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255; }
+
+// Scratch of exact64 over a list of len queries with S scan splits and the
+// direct fallback at one split (the least it needs).
+size_t exact64_bytes(int64_t len, int S) {
+  const size_t n = (size_t)len;
+  return 2 * aligned(n * S * 4 * 16 * 4) + aligned(n * S * 4 * sizeof(int)) +
+         aligned(n * S * sizeof(float)) + aligned(n * sizeof(int)) + aligned(n * sizeof(double)) +
+         aligned(n * sizeof(uint32_t));
+}
+
+// The plain direct scan of list L2 (h queries); from a caller's reserve its
+// partial results are carved with as many splits as the reserve holds.
+dd_status direct_from(const Dataset& D, const QueryPrep& Q, QueryList L2, int64_t h, int splits,
+                      Outputs out, Scratch& sc, hipStream_t st) {
+  if (sc.room() == SIZE_MAX) return run_direct(D, Q, L2, h, splits, out, st);
+  const size_t room = sc.room() > 1024 ? sc.room() - 1024 : 0;
+  const int S0 = splits > 0 ? splits : direct_splits(D, h);
+  const int S = (int)std::min<int64_t>(S0, (int64_t)(room / ((size_t)h * kDirectBytes)));
+  if (S < 1) return set_error(DD_ERR_TOO_LARGE, "direct scan: the projection's reserve is too small");
+  double* pd = nullptr;
+  uint32_t* po = nullptr;
+  DD_TRY(sc.get(pd, (size_t)h * S));
+  DD_TRY(sc.get(po, (size_t)h * S));
+  return run_direct(D, Q, L2, h, S, out, st, pd, po);
+}
+
 // FP64 MFMA scan over list L, merge, and the direct fallback for its overflow.
 dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len_max, int splits,
                   Outputs out, Scratch& sc, int* d_counters, hipStream_t st, int64_t* n_fallback,
                   Timing* tm) {
   int64_t qblocks = (len_max + 255) / 256;
   int S = choose_splits(qblocks, D.n_pad64 / kTile64, splits);
+  if (sc.room() != SIZE_MAX) {
+    // a caller's reserve: as many splits as it holds beside the fallback list
+    // and the direct scan's partial results at one split
+    const size_t keep = kAlignSlack + (size_t)len_max * (sizeof(int) + kDirectBytes);
+    const size_t room = sc.room() > keep ? sc.room() - keep : 0;
+    S = (int)std::min<int64_t>(S, (int64_t)(room / ((size_t)len_max * kCandBytes64)));
+    if (S < 1) return set_error(DD_ERR_TOO_LARGE, "FP64 scan: the projection's reserve is too small");
+  }
   CandBuf cb;
   DD_TRY(alloc_cands(sc, len_max, S, 4, 16, cb));
   if (tm) DD_TRY(tm->mark(1, st));
@@ -169,7 +229,7 @@ dd_status exact64(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
   if (n_fallback) *n_fallback += h;
   if (h > 0) {
     QueryList L2{fb, fb_count, h};
-    DD_TRY(run_direct(D, Q, L2, h, 0, out, st));
+    DD_TRY(direct_from(D, Q, L2, h, 0, out, sc, st));
   }
   return DD_OK;
 }
@@ -180,7 +240,15 @@ dd_status mixed32(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t len
                   Outputs out, Scratch& sc, int* d_counters, hipStream_t st, int64_t* n_fallback,
                   Timing* tm) {
   const int64_t qblocks = (len_max + 255) / 256;
-  const int S = choose_splits(qblocks, D.n_pad32 / kTile32, splits);
+  int S = choose_splits(qblocks, D.n_pad32 / kTile32, splits);
+  if (sc.room() != SIZE_MAX) {
+    // a caller's reserve: as many splits as it holds beside the fallback list
+    // and the FP64 scan of every query at one split
+    const size_t keep = kAlignSlack + aligned((size_t)len_max * sizeof(int)) + exact64_bytes(len_max, 1);
+    const size_t room = sc.room() > keep ? sc.room() - keep : 0;
+    S = (int)std::min<int64_t>(S, (int64_t)(room / ((size_t)len_max * kCandBytes32)));
+    if (S < 1) return set_error(DD_ERR_TOO_LARGE, "FP32 scan: the projection's reserve is too small");
+  }
   CandBuf cb;
   DD_TRY(alloc_cands(sc, len_max, S, 2, 16, cb));
   if (tm) DD_TRY(tm->mark(1, st));
@@ -213,7 +281,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
                           int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
                           hipStream_t st, const float* fd_q = nullptr,
-                          const int* budget_q = nullptr);
+                          const int* budget_q = nullptr, ScratchArena* fixed = nullptr);
 
 dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                        const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
@@ -222,14 +290,62 @@ dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened
                          dist_out_dev, nullptr, st);
 }
 
+// Scratch bytes a projection of up to m_max queries in `mode` carves at most
+// from a caller's reserve: its main path at the default splits (the largest
+// over the batch sizes up to m_max, as the splits follow the number of query
+// blocks), every fallback at one split.
+size_t project_scratch_need(const Dataset& D, int mode, int64_t m_max) {
+  constexpr int kNumCounters = 32 + 2 * kCounterStride * kCounterSlots;
+  auto need = [&](int64_t m) {
+    const size_t n = (size_t)std::max<int64_t>(m, 1);
+    size_t b = aligned(n * 12 * sizeof(double)) + 2 * aligned(n * sizeof(double)) +
+               2 * aligned(n * sizeof(int)) + aligned(kNumCounters * sizeof(int));
+    if (mode == DD_DIRECT_FP64) {
+      const int S = direct_splits(D, m);
+      b += aligned(n * S * sizeof(double)) + aligned(n * S * sizeof(uint32_t));
+    } else if (mode == DD_EXACT_FP64) {
+      b += exact64_bytes(m, choose_splits((m + 255) / 256, D.n_pad64 / kTile64, 0));
+    } else if (mode == DD_MIXED_FP32) {
+      const int S = choose_splits((m + 255) / 256, D.n_pad32 / kTile32, 0);
+      b += 2 * aligned(n * S * 2 * 16 * 4) + aligned(n * S * 2 * sizeof(int)) +
+           aligned(n * S * sizeof(float)) + aligned(n * sizeof(int)) + exact64_bytes(m, 1);
+    } else if (walk_mode(mode)) {
+      b += aligned(n * sizeof(int)) + aligned(n * 12 * sizeof(double)) + exact64_bytes(m, 1);
+    } else {
+      const int S = choose_splits16((m + kScan16Queries - 1) / kScan16Queries, D.n_tiles, 0);
+      const size_t cap = (size_t)std::min<int64_t>(std::max<int64_t>(32 * m, 1 << 20), 1 << 26);
+      b += aligned(n * S * sizeof(float)) + aligned(cap * sizeof(WorkItem)) +
+           2 * aligned(n * 2 * 32 * 4) + aligned(n * 2 * sizeof(int)) + aligned(n * sizeof(int)) +
+           exact64_bytes(m, 1);
+    }
+    return b + kAlignSlack;
+  };
+  size_t best = need(m_max);
+  for (int64_t m = 256; m < m_max; m += 256) best = std::max(best, need(m));
+  return best;
+}
+
+// As project_impl, every temporary buffer carved from `arena` (a caller's
+// reserve, see project_scratch_need) instead of the dataset's arenas.
+dd_status project_reserved(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
+                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                           int64_t* idx_out_dev, double* dist_out_dev, ScratchArena* arena,
+                           hipStream_t st) {
+  if (!arena) return set_error(DD_ERR_ARG, "no reserve");
+  return project_impl_ex(D, states_dev, whitened, m, warm_start_idx_dev, opts, idx_out_dev,
+                         dist_out_dev, nullptr, st, nullptr, nullptr, arena);
+}
+
 // As project_impl; dist2_out_dev (exact DD_ANN only) receives the distance to
 // the second nearest point, -1 where it is not certified; fd_q / budget_q
 // (walk modes, device arrays over the m states) give each state its own
-// radius factor and leaf budget.
+// radius factor and leaf budget; `fixed` (optional) is a caller's reserve that
+// the call carves every temporary buffer from.
 dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
                           int64_t* idx_out_dev, double* dist_out_dev, double* dist2_out_dev,
-                          hipStream_t st, const float* fd_q, const int* budget_q) {
+                          hipStream_t st, const float* fd_q, const int* budget_q,
+                          ScratchArena* fixed) {
   if (m < 0 || m > 0x7FFFFFFFll) return set_error(DD_ERR_ARG, "m must be in [0, 2^31-1]");
   if (m == 0) return DD_OK;
   if (!states_dev || !idx_out_dev) return set_error(DD_ERR_ARG, "NULL states or idx_out");
@@ -277,7 +393,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
   DD_HIP(hipGetDevice(&cur_dev));
   if (cur_dev != D.device) return set_error(DD_ERR_ARG, "dataset lives on another device");
 
-  Scratch sc(D, st);
+  Scratch sc(D, st, fixed);
   DD_TRY(sc.open());
   Timing timing;
   if (opts && opts->stats) DD_TRY(timing.init(st));
@@ -305,7 +421,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
 
   if (mode == DD_DIRECT_FP64) {
     DD_TRY(timing.mark(1, st));
-    DD_TRY(run_direct(D, Q, all, m, splits, out, st));
+    DD_TRY(direct_from(D, Q, all, m, splits, out, sc, st));
     DD_TRY(timing.mark(2, st));
   } else if (mode == DD_EXACT_FP64) {
     DD_TRY(exact64(D, Q, all, m, splits, out, sc, counters, st, &n_fallback, &timing));

@@ -93,8 +93,11 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
 
 // Splits of a scan over the data (FP64 and direct scans): `requested` if > 0;
 // with fewer than 64 query blocks one round of workgroups (512), otherwise
-// about 2048; multiples of 8 keep a split's workgroups on one XCD.
+// about 2048; multiples of 8 give a grid that the scans can deal to the eight
+// XCDs split by split.
 int choose_splits(int64_t n_query_blocks, int64_t n_tiles, int requested);
+// The splits run_direct takes for a list of list_len queries when S = 0.
+int direct_splits(const Dataset& D, int64_t list_len);
 
 // Queries per workgroup of the 16-bit pass (sixteen waves of two 32-query groups).
 constexpr int kScan16Queries = 1024;

@@ -420,6 +420,10 @@ __global__ void merge_direct_kernel(QueryList L, int S, const double* __restrict
   if (out.dist) out.dist[q] = 0.5 * best;
 }
 
+int direct_splits(const Dataset& D, int64_t list_len) {
+  return choose_splits((list_len + 255) / 256, (D.N + kDirectRows - 1) / kDirectRows, 0);
+}
+
 dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t list_len_max, int S,
                      Outputs out, hipStream_t st, double* part_d, uint32_t* part_o) {
   if (list_len_max <= 0) return DD_OK;

@@ -14,8 +14,11 @@
 // solve's arithmetic is the one of dd_solve, so its result does not depend on
 // the mix it ran in.
 //
-// Device memory.  A solve is charged its solver buffers and projection scratch
-// while it is admitted.  A mesh that dd_solve would solve through a cached K^-1
+// Device memory.  The server holds a fixed reserve from creation to destroy:
+// the batch buffers and the scratch of the largest projection batch (every
+// temporary buffer of the batch's projection is carved from it, so the
+// projection allocates nothing and never exceeds it).  A solve is charged its
+// solver buffers while it is admitted.  A mesh that dd_solve would solve through a cached K^-1
 // and whose inverse the dataset does not hold yet is charged that inverse too:
 // the inverse is formed on a builder thread (the solve waits, the others go
 // on) and stays charged to the server while the dataset's cache keeps it.  A
@@ -40,9 +43,11 @@
 
 namespace dd {
 
-dd_status project_impl(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
-                       const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
-                       int64_t* idx_out_dev, double* dist_out_dev, hipStream_t st);
+size_t project_scratch_need(const Dataset& D, int mode, int64_t m_max);
+dd_status project_reserved(const Dataset& D, const double* states_dev, bool whitened, int64_t m,
+                           const int64_t* warm_start_idx_dev, const dd_project_opts* opts,
+                           int64_t* idx_out_dev, double* dist_out_dev, ScratchArena* arena,
+                           hipStream_t st);
 
 namespace {
 
@@ -50,9 +55,6 @@ using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t0, Clock::time_point t1) {
   return std::chrono::duration<double, std::milli>(t1 - t0).count();
 }
-
-// Bytes of batch buffers and projection scratch charged to a solve per material point.
-constexpr int64_t kBytesPerQuery = 1280;
 
 struct Job {
   uint64_t ticket = 0;
@@ -140,6 +142,8 @@ struct Server {
   std::string batch_error;
   hipStream_t pst = nullptr;
   DevBuf bq, bw, bi, bd;               // batch buffers: states, warm start, idx, dist
+  std::unique_ptr<ScratchArena> scratch;   // the batch projection's scratch (its own block)
+  int64_t reserve = 0;                 // batch buffers + scratch block, held throughout
 
   // statistics (under mu)
   Clock::time_point t_create, t_first_submit;
@@ -458,13 +462,13 @@ void Server::scheduler() {
         int64_t extra = 0;
         if (j->inv_bytes > 0 && !j->use_cg && !building.count(j->inv_key) &&
             !DDSolver::inverse_cached(*D, j->mesh, j->mask.data())) {
-          if (j->footprint + j->inv_bytes > budget)
+          if (reserve + j->footprint + j->inv_bytes > budget)
             j->use_cg = true;
           else
             extra = j->inv_bytes;
         }
         const int64_t held = held_bytes();
-        if (used + held + j->footprint + extra > budget) break;
+        if (reserve + used + held + j->footprint + extra > budget) break;
         queue.pop_front();
         j->t_admit = Clock::now();
         lat_queue.push_back(ms_since(j->t_submit, j->t_admit));
@@ -475,7 +479,7 @@ void Server::scheduler() {
         dd_status st = admit(j);
         if (st != DD_OK) finish(j, st, "");
         lk.lock();
-        peak_used = std::max(peak_used, used + held_bytes());
+        peak_used = std::max(peak_used, reserve + used + held_bytes());
         progress = true;
       }
     }
@@ -567,8 +571,8 @@ void Server::projector() {
       dd_project_opts o{};
       o.mode = mode;
       o.ann_budget = ann_budget;
-      st = project_impl(*D, bq.as<double>(), true, total, bw.as<int64_t>(), &o, bi.as<int64_t>(),
-                        bd.as<double>(), pst);
+      st = project_reserved(*D, bq.as<double>(), true, total, bw.as<int64_t>(), &o,
+                            bi.as<int64_t>(), bd.as<double>(), scratch.get(), pst);
     }
     if (st == DD_OK) {
       for (const Chunk& c : b) {
@@ -670,10 +674,25 @@ extern "C" dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_by
     hbm_budget_bytes = fr / 2;
   }
   s.budget = (int64_t)std::min<size_t>(hbm_budget_bytes, (size_t)INT64_MAX);
+  // the fixed reserve: batch buffers and the scratch of a full batch's projection
+  const size_t scratch_bytes = project_scratch_need(D, mode, s.max_batch);
+  s.reserve = (int64_t)(scratch_bytes + (sizeof(double) * 12 + 3 * sizeof(int64_t)) * (size_t)s.max_batch);
+  if (s.reserve > s.budget)
+    return set_error(DD_ERR_TOO_LARGE, "the server's fixed reserve (" + std::to_string(s.reserve) +
+                                           " bytes: batch buffers and projection scratch for " +
+                                           std::to_string(s.max_batch) +
+                                           " states) exceeds the budget; lower max_batch");
   DD_TRY(s.bq.alloc(sizeof(double) * 12 * (size_t)s.max_batch));
   DD_TRY(s.bw.alloc(sizeof(int64_t) * (size_t)s.max_batch));
   DD_TRY(s.bi.alloc(sizeof(int64_t) * (size_t)s.max_batch));
   DD_TRY(s.bd.alloc(sizeof(double) * (size_t)s.max_batch));
+  s.scratch.reset(new ScratchArena);
+  DD_HIP(hipEventCreateWithFlags(&s.scratch->done, hipEventDisableTiming));
+  DD_HIP(hipHostMalloc((void**)&s.scratch->pinned, sizeof(uint32_t) * kArenaPinnedWords,
+                       hipHostMallocDefault));
+  DD_HIP(hipMalloc(&s.scratch->block, scratch_bytes));
+  s.scratch->bytes = scratch_bytes;
+  s.peak_used = s.reserve;
   DD_HIP(hipStreamCreateWithFlags(&s.pst, hipStreamNonBlocking));
   s.t_create = Clock::now();
   s.sched_thr = std::thread([&s] { s.scheduler(); });
@@ -716,7 +735,7 @@ extern "C" dd_status dd_server_submit(dd_server* h, const dd_solve_request* r, u
   j->init.assign(r->init_idx, r->init_idx + j->n_mp);
   j->max_iter = r->max_iter > 0 ? r->max_iter : 500;
   j->deadline_s = r->deadline_s;
-  j->footprint = DDSolver::footprint_bytes(r->mesh) + kBytesPerQuery * j->n_mp;
+  j->footprint = DDSolver::footprint_bytes(r->mesh);
   j->inv_bytes = DDSolver::inverse_bytes(r->mesh);
   {
     dd_mesh key_mesh;
@@ -733,7 +752,7 @@ extern "C" dd_status dd_server_submit(dd_server* h, const dd_solve_request* r, u
   }
   std::lock_guard<std::mutex> lk(s.mu);
   if (s.stop) return set_error(DD_ERR_CANCELLED, "server is shutting down");
-  if (j->footprint > s.budget) {
+  if (s.reserve + j->footprint > s.budget) {
     ++s.n_rejected;
     return set_error(DD_ERR_TOO_LARGE, "solve needs " + std::to_string(j->footprint) +
                                            " device bytes, more than the server budget " +
@@ -833,6 +852,7 @@ extern "C" dd_status dd_server_stats(const dd_server* h, dd_server_statistics* o
   out->peak_active = s.peak_active;
   out->peak_bytes = s.peak_used;
   out->budget_bytes = s.budget;
+  out->reserve_bytes = s.reserve;
   out->proj_p50_ms = percentile(s.lat_proj, 50);
   out->proj_p99_ms = percentile(s.lat_proj, 99);
   out->solve_p50_ms = percentile(s.lat_solve, 50);

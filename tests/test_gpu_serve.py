@@ -136,22 +136,38 @@ def test_large_mesh_spans_batches(L, data):
         srv.close()
 
 
+def _reserve(L, ds, **kw):
+    """The fixed reserve of a server of these options (batch buffers and the
+    scratch of a full projection batch)."""
+    probe = L.DDServer(ds, **kw)
+    try:
+        return probe.stats()["reserve_bytes"]
+    finally:
+        probe.close()
+
+
 def test_admission_by_footprint(L, data):
-    """A budget that holds one solve at a time admits them one by one (all
-    finish); a solve larger than the whole budget is rejected at submit."""
+    """A budget that holds one solve at a time beside the server's reserve
+    admits them one by one (all finish); a solve larger than the whole budget
+    is rejected at submit; a budget below the reserve is refused at creation."""
     N, ds = data["N"], data["ds"]
     reqs = _requests(N, [4, 4, 4], 3)
-    # a 4^3 solve is charged about 1.2 MB (P_C buffers, states, projection
-    # scratch): a 1.9 MB budget admits one at a time
+    # a 4^3 solve's P_C buffers and states take about 0.57 MB: 0.9 MB beside the
+    # reserve admit one at a time
     big = (12, 12, 12)
-    srv = L.DDServer(ds, hbm_budget_bytes=1_900_000, mode="bf16")
+    r = _reserve(L, ds, mode="bf16", max_batch=1024)
+    assert r > 0
+    with pytest.raises(L.DDError) as ex:
+        L.DDServer(ds, hbm_budget_bytes=r - 1, mode="bf16", max_batch=1024)
+    assert ex.value.status == 6
+    srv = L.DDServer(ds, hbm_budget_bytes=r + 900_000, mode="bf16", max_batch=1024)
     try:
         tickets = [srv.submit(*r) for r in reqs]
         res = [srv.wait(t) for t in tickets]
         st = srv.stats()
         _say("budget stats", st["peak_active"], st["peak_bytes"], st["budget_bytes"])
         assert st["peak_active"] == 1 and st["completed"] == 3
-        assert st["peak_bytes"] <= st["budget_bytes"]
+        assert st["reserve_bytes"] == r and r < st["peak_bytes"] <= st["budget_bytes"]
         for r, q in zip(res, reqs):
             _same(L.dd_solve(ds, *q, mode="bf16"), r)
         mask, force = ddsynth.box_bc(12, 100.0)
@@ -164,16 +180,17 @@ def test_admission_by_footprint(L, data):
 
 
 def test_inverse_beyond_budget_runs_by_cg(L, C0):
-    """An 8^3 solve's buffers fit a 20 MB budget but its K^-1 (40 MB) does not:
-    on a dataset that has not formed that inverse, the server runs the solve
-    by CG (the trajectory of dd_solve with DD_SOLVE_CG, bit for bit) and never
-    charges more than the budget."""
+    """An 8^3 solve's buffers (3.7 MB) fit 20 MB beside the server's reserve but
+    its K^-1 (40 MB) does not: on a dataset that has not formed that inverse,
+    the server runs the solve by CG (the trajectory of dd_solve with
+    DD_SOLVE_CG, bit for bit) and never charges more than the budget."""
     N = 1 << 16
     e, s = ddsynth.data_points(N, 1030)
     ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=FP64 | BF16)
     mask, force = ddsynth.box_bc(8, 120.0)
     init = ddsynth.indices(8 * 8 ** 3, N, 31)
-    srv = L.DDServer(ds, hbm_budget_bytes=20_000_000, mode="bf16")
+    r = _reserve(L, ds, mode="bf16", max_batch=4096)
+    srv = L.DDServer(ds, hbm_budget_bytes=r + 20_000_000, mode="bf16", max_batch=4096)
     try:
         got = srv.wait(srv.submit((8, 8, 8), mask, force, init))
         st = srv.stats()
@@ -202,10 +219,33 @@ def test_inverse_formed_off_the_scheduler_and_charged(L, C0):
         srv.close()
     _say("async inverses", st["peak_bytes"], st["peak_active"])
     n_pad = (3 * 9 ** 3 + 63) // 64 * 64
-    assert st["peak_bytes"] >= 8 * n_pad * n_pad          # the 8^3 inverse was charged
+    assert st["peak_bytes"] >= st["reserve_bytes"] + 8 * n_pad * n_pad   # the 8^3 inverse was charged
     for r, g in zip(reqs, got):
         assert g["cg_iterations"] == 0
         _same(L.dd_solve(ds, *r, mode="bf16"), g)
+    ds.close()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "direct", "fp32", "bf16", "fp16", "ann", "kmeans"])
+def test_every_mode_served_from_the_reserve(L, C0, mode):
+    """In every projection mode the batch projections carve their scratch from
+    the server's fixed reserve (no allocation, and a call that needed more would
+    fail) and every served solve equals dd_solve alone."""
+    N = 1 << 14
+    e, s = ddsynth.data_points(N, 1040)
+    ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=0x1 | 0x2 | 0x4 | 0x8 | 0x10 | 0x20)
+    reqs = _requests(N, [3, 2, 4], 41)
+    alone = [L.dd_solve(ds, *r, mode=mode) for r in reqs]
+    srv = L.DDServer(ds, mode=mode, max_batch=2048)
+    try:
+        got = [srv.wait(t) for t in [srv.submit(*r) for r in reqs]]
+        st = srv.stats()
+    finally:
+        srv.close()
+    _say(f"served {mode}: reserve {st['reserve_bytes']}, peak {st['peak_bytes']}")
+    assert st["failed"] == 0 and 0 < st["reserve_bytes"] < st["peak_bytes"] <= st["budget_bytes"]
+    for a, b in zip(alone, got):
+        _same(a, b)
     ds.close()
 
 
