@@ -681,20 +681,30 @@ __global__ __launch_bounds__(256) void scan16_extract_kernel(
   const float a = (Uq + eta) * (1.0f + 0x1p-18f);
   const float sa = a * a + alpha;
   const float T = v ? (sa - o) + 0x1p-18f * (sa + fabsf(o)) + 1e-30f : -INFINITY;
-  for (int rb = 0; rb < TILE / 32; ++rb) {
-    vec_t A = __builtin_bit_cast(vec_t, src[(rb * 32 + col) * 2 + h]);
-    f32x16_t acc = VT::mfma(A, B, zero);
+  // row blocks in groups of kU: their operands are loaded together, and a row
+  // block's scores are screened one by one only when their minimum passes
+  constexpr int kU = TILE / 32 < 8 ? TILE / 32 : 8;
+  for (int rb0 = 0; rb0 < TILE / 32; rb0 += kU) {
+    vec_t A[kU];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (acc[i] <= T) {
-        const int row = rb * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-        const int64_t j = t * TILE + row;
-        const float lb = fsqrt(fmaxf(acc[i] + o - alpha, 0.0f)) * kRelDn - eta;
-        if (j < N && lb <= Uq) {
-          int k = atomicAdd(&cb.count[p * 2 + h], 1);
-          if (k < cb.K) {
-            L0[k] = lb;
-            J0[k] = (uint32_t)j;
+    for (int u = 0; u < kU; ++u) A[u] = __builtin_bit_cast(vec_t, src[((rb0 + u) * 32 + col) * 2 + h]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const f32x16_t acc = VT::mfma(A[u], B, zero);
+      if (min16(INFINITY, acc) <= T) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (acc[i] <= T) {
+            const int row = (rb0 + u) * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
+            const int64_t j = t * TILE + row;
+            const float lb = fsqrt(fmaxf(acc[i] + o - alpha, 0.0f)) * kRelDn - eta;
+            if (j < N && lb <= Uq) {
+              int k = atomicAdd(&cb.count[p * 2 + h], 1);
+              if (k < cb.K) {
+                L0[k] = lb;
+                J0[k] = (uint32_t)j;
+              }
+            }
           }
         }
       }
