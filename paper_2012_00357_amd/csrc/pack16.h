@@ -6,7 +6,7 @@
 namespace dd {
 
 // Rows per LDS tile of the FP64 and FP32 scans (padding granularity of those packs).
-constexpr int kTile64 = 128;
+constexpr int kTile64 = 256;
 constexpr int kTile32 = 256;
 
 // Coordinates of the 16-bit scans: the whitened data, tile centres, radii and

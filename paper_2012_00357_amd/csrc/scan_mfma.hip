@@ -15,6 +15,22 @@ namespace dd {
 
 __device__ static inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }   // 1 ulp
 
+// FP64 -> FP32 rounded up / down (finite or infinite inputs), in registers:
+// the nearest conversion, moved one step when it fell on the wrong side.
+__device__ inline float f32_next_up(float f) {
+  if (f == 0.0f) return 0x1p-149f;
+  const uint32_t u = __float_as_uint(f);
+  return __uint_as_float(f > 0.0f ? u + 1u : u - 1u);
+}
+__device__ inline float f32_up(double d) {
+  const float f = (float)d;
+  return (double)f < d ? f32_next_up(f) : f;
+}
+__device__ inline float f32_down(double d) {
+  const float f = (float)d;
+  return (double)f > d ? -f32_next_up(-f) : f;
+}
+
 // Running minimum over 16 new values: 17 inputs, eight 3-input minima.
 __device__ inline float min16(float run, const f32x16_t& a) {
   float m0 = fminf(fminf(a[0], a[1]), a[2]);
@@ -46,13 +62,15 @@ __device__ inline void split_qblock(int S, int& split, int64_t& qblock) {
 // FP64 MFMA scan.  v_mfma_f64_16x16x4: A (16 data rows x 4 k) one double per
 // lane (row = lane%16, k = lane/16), B (4 k x 16 queries) one double per lane
 // (query = lane%16, k = lane/16), D register i holds row lane/16 + 4 i of
-// query lane%16.  Score s_j = |x_j|^2 - 2 q.x_j over K = 12 (three MFMAs);
-// d~ = s + |q|^2.
+// query lane%16.  Score s_j = |x_j|^2 - 2 q.x_j over K = 12 (three MFMAs, the
+// stored norm as the accumulator input of the first); d~ = s + |q|^2.
 // ---------------------------------------------------------------------------
 constexpr int kG64 = 4;                                  // 16-query groups per wave
 constexpr int kQ64 = 4 * kG64 * 16;                      // queries per workgroup
+constexpr int kStage64 = kTile64 * 12 / 256;             // doubles of a tile staged per thread
+static_assert(kTile64 <= 256 && kTile64 * 12 % 256 == 0, "one staged row norm per thread");
 
-__global__ __launch_bounds__(256) void scan64_kernel(
+__global__ __launch_bounds__(256, 3) void scan64_kernel(
     const double* __restrict__ w64, const double* __restrict__ n64, int64_t n_tiles, int64_t N,
     const double* __restrict__ qw, const double* __restrict__ qn2, const double* __restrict__ u64,
     const int* __restrict__ invalid, double xmax, QueryList L, CandBuf cb) {
@@ -94,21 +112,21 @@ __global__ __launch_bounds__(256) void scan64_kernel(
   }
 
   if (t0 < t1) {
-    auto load = [&](int64_t t, double (&reg)[6], double& nreg) {
+    auto load = [&](int64_t t, double (&reg)[kStage64], double& nreg) {
       const double* src = w64 + t * kTile64 * 12;
 #pragma unroll
-      for (int r = 0; r < 6; ++r) reg[r] = src[tid + 256 * r];
+      for (int r = 0; r < kStage64; ++r) reg[r] = src[tid + 256 * r];
       nreg = (tid < kTile64) ? n64[t * kTile64 + tid] : 0.0;
     };
-    auto store = [&](int buf, const double (&reg)[6], double nreg) {
+    auto store = [&](int buf, const double (&reg)[kStage64], double nreg) {
 #pragma unroll
-      for (int r = 0; r < 6; ++r) {
+      for (int r = 0; r < kStage64; ++r) {
         int e = tid + 256 * r;
         xs[buf][e % 12][e / 12] = reg[r];
       }
       if (tid < kTile64) ns[buf][tid] = nreg;
     };
-    double reg[6], nreg;
+    double reg[kStage64], nreg;
     load(t0, reg, nreg);
     store(0, reg, nreg);
     __syncthreads();
@@ -119,25 +137,24 @@ __global__ __launch_bounds__(256) void scan64_kernel(
       double tm[kG64];
 #pragma unroll
       for (int g = 0; g < kG64; ++g) tm[g] = INFINITY;
-#pragma unroll
+#pragma unroll 2
       for (int rb = 0; rb < kTile64 / 16; ++rb) {
         const int r0 = rb * 16 + col;
         double a0 = xs[cur][kq][r0], a1 = xs[cur][4 + kq][r0], a2 = xs[cur][8 + kq][r0];
         double nr[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) nr[i] = ns[cur][rb * 16 + kq + 4 * i];
+        const f64x4_t cn = {nr[0], nr[1], nr[2], nr[3]};
 #pragma unroll
         for (int g = 0; g < kG64; ++g) {
-          f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[g][0], acc, 0, 0, 0);
+          // the rows' norms enter as the accumulator input: s = |x|^2 - 2 q.x
+          f64x4_t acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[g][0], cn, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b[g][1], acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b[g][2], acc, 0, 0, 0);
-          double m01 = fmin(acc[0] + nr[0], acc[1] + nr[1]);
-          double m23 = fmin(acc[2] + nr[2], acc[3] + nr[3]);
-          tm[g] = fmin(tm[g], fmin(m01, m23));
+          tm[g] = fmin(tm[g], fmin(fmin(acc[0], acc[1]), fmin(acc[2], acc[3])));
         }
       }
-#pragma unroll
+#pragma unroll 1   // rolled: the rare candidate logging stays out of the code of every group
       for (int g = 0; g < kG64; ++g) {
         double v = tm[g];
         v = fmin(v, __shfl_xor(v, 16));
@@ -147,11 +164,13 @@ __global__ __launch_bounds__(256) void scan64_kernel(
         bool need = valid[g] && (dmin - alpha[g] <= Un);
         U[g] = Un;
         if (__any(need)) {
-          const float Uf = __double2float_ru(U[g]);
+          const float Uf = f32_up(U[g]);
           const int64_t slot = (pos[g] * S + split) * 4 + kq;
           for (int rb = 0; rb < kTile64 / 16; ++rb) {
             const int r0 = rb * 16 + col;
-            f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+            f64x4_t acc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = ns[cur][rb * 16 + kq + 4 * i];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][kq][r0], b[g][0], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][4 + kq][r0], b[g][1], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][8 + kq][r0], b[g][2], acc, 0, 0, 0);
@@ -159,10 +178,10 @@ __global__ __launch_bounds__(256) void scan64_kernel(
             for (int i = 0; i < 4; ++i) {
               const int row = rb * 16 + kq + 4 * i;
               const int64_t j = t * kTile64 + row;
-              double d = acc[i] + ns[cur][row] + qn[g];
+              double d = acc[i] + qn[g];
               double lb = d - alpha[g];
               if (valid[g] && j < N && lb <= U[g])
-                cand_append(cb, slot, cnt[g], ovf[g], __double2float_rd(lb), (uint32_t)j, Uf);
+                cand_append(cb, slot, cnt[g], ovf[g], f32_down(lb), (uint32_t)j, Uf);
             }
           }
         }
@@ -176,7 +195,7 @@ __global__ __launch_bounds__(256) void scan64_kernel(
     if (pos[g] < len) {
       const int64_t slot = (pos[g] * S + split) * 4 + kq;
       cb.count[slot] = cnt[g] | (ovf[g] ? kOverflowBit : 0);
-      if (kq == 0) cb.U[pos[g] * S + split] = __double2float_ru(U[g]);
+      if (kq == 0) cb.U[pos[g] * S + split] = f32_up(U[g]);
     }
   }
 }
@@ -259,7 +278,7 @@ __global__ __launch_bounds__(256, 3) void scan32_kernel(
     }
     o[g] = (float)oo;
     a[g] = 0x1p-18f * qa * qa + 1e-30f;
-    U[g] = v ? __double2float_ru(u64[q]) : INFINITY;
+    U[g] = v ? f32_up(u64[q]) : INFINITY;
     cnt[g] = 0;
     ovf[g] = false;
   }
