@@ -424,7 +424,8 @@ typedef struct dd_server_statistics {
   int64_t submitted, completed, failed, rejected, cancelled;
   int64_t active, queued;           /* admitted solves now; submitted, not yet admitted */
   int64_t batches, queries;         /* projection batches run; material points projected */
-  int64_t peak_active, peak_bytes;  /* most solves admitted at once; most footprint bytes in use */
+  int64_t peak_active, peak_bytes;  /* most solves admitted at once; most bytes charged at once
+                                       (reserve, admitted solves, K^-1 inverses) */
   int64_t budget_bytes;             /* the admission budget */
   double proj_p50_ms, proj_p99_ms;  /* per projection: a solve's state ready -> association back */
   double solve_p50_ms, solve_p99_ms;  /* per solve: submit -> result ready */
@@ -455,7 +456,8 @@ dd_status dd_server_create(const dd_dataset* ds, size_t hbm_budget_bytes,
 
 /* Queue a solve (non-blocking; inputs are copied).  *ticket identifies it.
  * Errors: DD_ERR_ARG (invalid request, as dd_solve), DD_ERR_TOO_LARGE (its
- * footprint exceeds the whole budget, or the queue is full: rejected). */
+ * footprint does not fit the budget beside the server's reserve, or the queue
+ * is full: rejected). */
 dd_status dd_server_submit(dd_server* srv, const dd_solve_request* req, uint64_t* ticket);
 
 /* Wait for a solve: timeout_s < 0 waits without limit, 0 polls.  On completion
