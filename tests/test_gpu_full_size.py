@@ -2,8 +2,9 @@
 CPU oracle computes one by one (through the C ABI, in the launch configuration
 the benchmark times).
 
-* N = 2^27 data points, m = 65536 queries: BF16 scan + FP64 rerank equals the
-  FP64 MFMA scan on every query, and the oracle on a 1024-query sample (the
+* N = 2^27 data points, m = 65536 queries: the BF16, FP16 and FP32 scans with
+  FP64 rerank equal the FP64 MFMA scan on every query (indices and distances),
+  and the BF16 scan equals the oracle on a 1024-query sample (the
   oracle's whitened brute force, which equals its raw-metric brute force on
   the 4096 queries of the N = 65536 workload, a CPU test).
 * N = 10^9 data points generated on the device, 16^3 hexahedra (32768
@@ -24,7 +25,7 @@ from gpu_util import NEAR_TIE, to_dev
 
 pytestmark = pytest.mark.gpu
 
-FP64, BF16, ANN = 0x1, 0x4, 0x10
+FP64, FP32, BF16, FP16, ANN = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 def _say(*a):
@@ -68,14 +69,18 @@ def test_config2_bf16_equals_fp64_and_oracle_2e27(L, C0):
     e, s = ddsynth.data_points(N, 1002)
     qe, qs, _ = ddsynth.queries(e, s, m, 2002)
     ds = L.dd_dataset_create(torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda(), C0,
-                             packs=FP64 | BF16)
+                             packs=FP64 | FP32 | BF16 | FP16)
     torch.cuda.empty_cache()
     states = torch.from_numpy(ddsynth.states(qe, qs)).cuda()
     ib, db = L.dd_project(ds, states, mode="bf16")
     i6, d6 = L.dd_project(ds, states, mode="fp64")
     assert torch.equal(ib, i6)
     assert torch.equal(db, d6)
-    _say(f"2^27: bf16 == fp64 on all {m} queries ({time.time() - t:.0f}s)")
+    for mode in ("fp16", "fp32"):
+        im, dm = L.dd_project(ds, states, mode=mode)
+        assert torch.equal(im, i6), mode
+        assert torch.equal(dm, d6), mode
+    _say(f"2^27: bf16 == fp16 == fp32 == fp64 on all {m} queries ({time.time() - t:.0f}s)")
     rng = np.random.default_rng(11)
     sample = np.sort(rng.choice(m, 1024, replace=False))
     t1 = time.time()
