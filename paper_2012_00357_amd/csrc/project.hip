@@ -487,11 +487,20 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     DD_TRY(launch_scan16(D, fp16, c, st));
     DD_TRY(timing.mark(2, st));
     DD_TRY(launch_reduce_bounds(all, m, c.U_out, S, Q.u32, st));
+    // every (query group, tile) pair is logged at most once: when that many
+    // items fit the list and make a small grid, the extraction is launched for
+    // all of them (its waves read the logged count and the rest exit) and the
+    // count is not read back (no host round trip in small projections)
+    const int64_t max_items = (m + 31) / 32 * D.n_tiles;
+    const bool bounded = max_items <= std::min<int64_t>(c.item_cap, 1 << 16);
     uint32_t* nw = sc.host_word(2);
-    DD_HIP(hipMemcpyAsync(nw, n_items, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-    DD_HIP(hipStreamSynchronize(st));
-    unsigned ni = *nw;
-    if (ni > c.item_cap) {
+    unsigned ni = (unsigned)std::min<int64_t>(max_items, c.item_cap);
+    if (!bounded) {
+      DD_HIP(hipMemcpyAsync(nw, n_items, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+      DD_HIP(hipStreamSynchronize(st));
+      ni = *nw;
+    }
+    if (!bounded && ni > c.item_cap) {
       // too many items were logged under the running bound: mark again under
       // the final bound, which logs only tiles holding certified candidates
       DD_HIP(hipMemsetAsync(n_items, 0, sizeof(unsigned), st));
@@ -501,7 +510,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
       ni = *nw;
       if (ni > c.item_cap) return set_error(DD_ERR_TOO_LARGE, "16-bit scan work list overflow");
     }
-    n_items_host = ni;
+    n_items_host = bounded ? -1 : (int64_t)ni;   // -1: read with the statistics
     c.phase = Scan16Call::kExtract;
     c.item_cap = ni;
     DD_TRY(launch_scan16(D, fp16, c, st));
@@ -524,7 +533,10 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     unsigned long long nc = 0;
     unsigned long long slots[kCounterStride * kCounterSlots] = {};
     unsigned long long a[6] = {0, 0, 0, 0, 0, 0};
+    unsigned items = 0;
     DD_HIP(hipMemcpyAsync(&nc, counters + 2, sizeof(nc), hipMemcpyDeviceToHost, st));
+    if (n_items_host < 0)
+      DD_HIP(hipMemcpyAsync(&items, counters + 4, sizeof(items), hipMemcpyDeviceToHost, st));
     if (ann) DD_HIP(hipMemcpyAsync(slots, ann, sizeof(slots), hipMemcpyDeviceToHost, st));
     DD_TRY(timing.mark(3, st));
     DD_HIP(hipStreamSynchronize(st));
@@ -543,7 +555,7 @@ dd_status project_impl_ex(const Dataset& D, const double* states_dev, bool white
     opts->stats->nodes = (int64_t)a[5];
     opts->stats->scan_ms = scan_ms;
     opts->stats->total_ms = total_ms;
-    opts->stats->slow_tiles = n_items_host;
+    opts->stats->slow_tiles = n_items_host < 0 ? (int64_t)items : n_items_host;
   }
   return DD_OK;
 }
