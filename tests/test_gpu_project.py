@@ -165,6 +165,32 @@ def test_si_units_padded_tail_and_far_queries(L, C0, mode):
     assert np.array_equal(idx.cpu().numpy()[200:205], tail)
 
 
+@pytest.mark.parametrize("mode", MODES + ["kmeans"])
+def test_degenerate_data_sets(L, C0, mode):
+    """Degenerate data: every point the same (tiles of radius 0, so the 16-bit
+    scale is at its cap and most queries fall back), and points that differ in
+    one strain component only (a data set on a line): every mode equals the
+    oracle, ties to the lowest index."""
+    _say("degenerate", mode)
+    packs = ALL_PACKS | (0x20 if mode == "kmeans" else 0)
+    e0, s0 = ddsynth.data_points(1, 91)
+    qe, qs, _ = ddsynth.queries(*ddsynth.data_points(64, 92), 40, 93)
+    for n, make in ((3000, lambda: (np.repeat(e0, 3000, 0), np.repeat(s0, 3000, 0))),
+                    (2500, lambda: (np.repeat(e0, 2500, 0) + np.linspace(-1e-3, 1e-3, 2500)[:, None]
+                                    * np.array([[1.0, 0, 0, 0, 0, 0]]), np.repeat(s0, 2500, 0)))):
+        e, s = make()
+        q_e = np.concatenate([qe, e[[0, n // 2, n - 1]]])
+        q_s = np.concatenate([qs, s[[0, n // 2, n - 1]]])
+        oi, od, o2 = oracle.pd_raw(e, s, C0, q_e, q_s)
+        ds = L.dd_dataset_create(to_dev(e), to_dev(s), C0, packs=packs, tile=512)
+        idx, dist = L.dd_project(ds, to_dev(ddsynth.states(q_e, q_s)), mode=mode)
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        if n == 3000:
+            assert np.all(idx == 0)                       # all points tie: the lowest index
+        compare_to_oracle(idx, dist, oi, od, o2)
+        ds.close()
+
+
 def test_passes_out_of_range_is_refused(L, config0):
     for passes in (-1, 3):
         with pytest.raises(L.DDError) as ex:
