@@ -350,7 +350,7 @@ __global__ void new_frontier_kernel(int64_t S, const uint32_t* __restrict__ ccnt
 
 // Children of every split: leaves (at most 64 points) and the nodes of the next
 // round, flagged for compaction.
-__global__ void children_kernel(Segs G, int64_t S, const uint32_t* __restrict__ ccnt,
+__global__ void children_kernel(int64_t S, const uint32_t* __restrict__ ccnt,
                                 uint32_t* __restrict__ leaf_f, uint32_t* __restrict__ act_f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S * kK) return;
@@ -878,7 +878,7 @@ dd_status build_kmeans_tree(Dataset& D, hipStream_t st) {
     DD_TRY(leaf_at.alloc(4 * (size_t)SK));
     DD_TRY(act_f.alloc(4 * (size_t)SK));
     DD_TRY(act_at.alloc(4 * (size_t)SK));
-    hipLaunchKernelGGL(children_kernel, dim3(grid_of(SK, 256)), dim3(256), 0, st, G, S,
+    hipLaunchKernelGGL(children_kernel, dim3(grid_of(SK, 256)), dim3(256), 0, st, S,
                        ccnt_b.as<uint32_t>(), leaf_f.as<uint32_t>(), act_f.as<uint32_t>());
     DD_HIP(hipGetLastError());
     DD_HIP(hipMemcpyAsync(leaf_at.p, leaf_f.p, leaf_f.bytes, hipMemcpyDeviceToDevice, st));

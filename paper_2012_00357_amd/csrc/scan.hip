@@ -346,8 +346,8 @@ constexpr int kDirectRows = 128;
 
 __global__ __launch_bounds__(256) void direct_kernel(
     const double* __restrict__ w64, const float* __restrict__ w32, const uint32_t* __restrict__ perm,
-    int64_t n_tiles, int64_t N, const double* __restrict__ qw, const int* __restrict__ invalid,
-    QueryList L, int S, double* __restrict__ part_d, uint32_t* __restrict__ part_o) {
+    int64_t n_tiles, int64_t N, const double* __restrict__ qw, QueryList L, int S,
+    double* __restrict__ part_d, uint32_t* __restrict__ part_o) {
   __shared__ double xs[kDirectRows][12];
   __shared__ uint32_t os[kDirectRows];
   const int tid = threadIdx.x;
@@ -439,7 +439,7 @@ dd_status run_direct(const Dataset& D, const QueryPrep& Q, QueryList L, int64_t 
   }
   hipLaunchKernelGGL(direct_kernel, dim3((unsigned)(qblocks * S)), dim3(256), 0, st,
                      D.w64.as<double>(), D.w64.p ? nullptr : D.w32.as<float>(),
-                     D.perm.as<uint32_t>(), n_tiles, D.N, Q.qw, Q.invalid, L, S, pd, po);
+                     D.perm.as<uint32_t>(), n_tiles, D.N, Q.qw, L, S, pd, po);
   DD_HIP(hipGetLastError());
   hipLaunchKernelGGL(merge_direct_kernel, dim3(grid1(list_len_max)), dim3(256), 0, st, L, S, pd, po,
                      Q.invalid, out);

@@ -1207,7 +1207,7 @@ struct StepEvents {
 }  // namespace
 
 dd_status DDSolver::run(int max_iter, dd_solve_result* res) {
-  const int64_t nm = M.n_mp, nd = M.n_dof;
+  const int64_t nm = M.n_mp;
   auto t0 = std::chrono::steady_clock::now();
   int it = 0;
   bool converged = false;
