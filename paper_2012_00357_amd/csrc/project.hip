@@ -180,11 +180,11 @@ size_t exact64_bytes(int64_t len, int S) {
          aligned(n * sizeof(uint32_t));
 }
 
-// The plain direct scan of list L2 (h queries); from a caller's reserve its
-// partial results are carved with as many splits as the reserve holds.
+// The plain direct scan of list L2 (h queries), its per-split partial results
+// carved from the call's scratch (from a caller's reserve with as many splits
+// as the reserve holds).
 dd_status direct_from(const Dataset& D, const QueryPrep& Q, QueryList L2, int64_t h, int splits,
                       Outputs out, Scratch& sc, hipStream_t st) {
-  if (sc.room() == SIZE_MAX) return run_direct(D, Q, L2, h, splits, out, st);
   const size_t room = sc.room() > 1024 ? sc.room() - 1024 : 0;
   const int S0 = splits > 0 ? splits : direct_splits(D, h);
   const int S = (int)std::min<int64_t>(S0, (int64_t)(room / ((size_t)h * kDirectBytes)));
