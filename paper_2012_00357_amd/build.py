@@ -37,12 +37,17 @@ def _hipcc() -> str:
 # Matrix-core scan kernels: inputs are finite, so IEEE mode and NaN semantics
 # are off (min reductions need no canonicalisation) and MFMA results stay in
 # ordinary VGPRs instead of round-tripping through AGPRs.
-MFMA_FLAGS = ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+FINITE_FLAGS = ["-fno-honor-nans", "-mno-amdgpu-ieee"]
+MFMA_FLAGS = FINITE_FLAGS + ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+# The tree walks: the same for their box and ball bounds (queries with
+# non-finite coordinates leave the walk before any arithmetic).
+FINITE_SOURCES = ("ann.hip",)
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    extra = MFMA_FLAGS if src.endswith("_mfma.hip") else []
+    name = os.path.basename(src)
+    extra = MFMA_FLAGS if name.endswith("_mfma.hip") else FINITE_FLAGS if name in FINITE_SOURCES else []
     cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

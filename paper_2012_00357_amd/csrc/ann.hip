@@ -298,8 +298,12 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, float& aux, int la
 // has found (none at the start, so the first descent always reaches a leaf:
 // the warm-start point bounds no branch), and the warm-start point remains a
 // candidate, so the answer is never farther than the previous association.
+//
+// Occupancy: six waves per SIMD for the box-tree walk (80 registers, no
+// spills; its pace is set by the latency of dependent steps, which more waves
+// hide), five for the k-means walk, whose larger state would spill at six.
 template <bool TOP2, bool KMT>
-__global__ __launch_bounds__(256, 5) void ann_walk_kernel(AnnArgs A) {
+__global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
   __shared__ float s_lb[kWaves][kStack];
   __shared__ uint32_t s_cpos[kWaves][kCand];
