@@ -50,6 +50,12 @@ constexpr float kEps22 = 2.384185791015625e-07f;   // 2^-22
 constexpr float kLbShrink = 1.0f - 1.9073486328125e-06f;   // 1 - 2^-19
 constexpr float kLeafRel = (4.8828125e-04f + 2.384185791015625e-07f) * 1.001f;   // (2^-11 + 2^-22)
 
+// Square root by the bare v_sqrt_f32 (within 1 ulp; a subnormal argument may
+// give 0): the 2^-19 shrink of every box bound and the 2^-20 s~ term of the
+// point error E cover it many times over, and a distance below 2^-63 r is far
+// inside E's absolute terms.
+__device__ inline float wsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 struct AnnArgs {
   const float* box[kAnnMaxLevels];
   int64_t n[kAnnMaxLevels];
@@ -151,7 +157,7 @@ __device__ inline float leaf_point_dist(const uint16_t* __restrict__ h16, int64_
     const float t = qs[k] - x[k];
     d = fmaf(t, t, d);
   }
-  return r * __builtin_sqrtf(d);
+  return r * wsqrt(d);
 }
 
 // s~ from a point's preloaded FP16 scaled offsets.
@@ -166,7 +172,7 @@ __device__ inline float leaf_point_dist_r(const uint2 (&xr)[3], const float qs[1
     const float t = qs[k] - x[k];
     d = fmaf(t, t, d);
   }
-  return r * __builtin_sqrtf(d);
+  return r * wsqrt(d);
 }
 
 // Lower bound from a box quantised inside its parent box (plo, step), given as
@@ -185,7 +191,7 @@ __device__ __attribute__((always_inline)) inline float qbox_lb_words(const uint3
     const float g = fmaxf(fmaxf(lo - yq[a], yq[a] - hi), 0.0f);
     s = fmaf(g, g, s);
   }
-  return __builtin_sqrtf(s) * kLbShrink - slack;
+  return wsqrt(s) * kLbShrink - slack;
 }
 
 // The same with the parent box given by its corners (the step formed at use,
@@ -204,7 +210,7 @@ __device__ __attribute__((always_inline)) inline float qbox_lb_corners(
     const float g = fmaxf(fmaxf(lo - yq[a], yq[a] - hi), 0.0f);
     s = fmaf(g, g, s);
   }
-  return __builtin_sqrtf(s) * kLbShrink - slack;
+  return wsqrt(s) * kLbShrink - slack;
 }
 
 __device__ inline float qbox_lb(const uint8_t* __restrict__ q, const float plo[12],
@@ -230,7 +236,7 @@ __device__ inline float box_lb(const float* __restrict__ b, const float yq[12], 
     const float g = fmaxf(fmaxf(lo[a] - yq[a], yq[a] - hi[a]), 0.0f);
     s = fmaf(g, g, s);
   }
-  return __builtin_sqrtf(s) * kLbShrink - slack;
+  return wsqrt(s) * kLbShrink - slack;
 }
 
 // Lower bound of the whitened distance from the query to the points of a
@@ -254,7 +260,7 @@ __device__ __attribute__((always_inline)) inline float record_lb(
     s = fmaf(t, t, s);
   }
   code = __builtin_bit_cast(uint32_t, e.y);
-  dc = __builtin_sqrtf(s) * kLbShrink - slack;
+  dc = wsqrt(s) * kLbShrink - slack;
   const float ball = dc - fd * e.x;
   if (fd != 1.0f) return ball;
   const float4 f = m[4];

@@ -103,9 +103,11 @@ def test_ann_exact_without_budget(L, config0):
     compare_to_oracle(idx.cpu().numpy(), dist.cpu().numpy(), config0["oi"], config0["od"],
                       config0["o2"])
     assert st["visited"] > 0 and st["leaves"] > 0 and st["boxes"] > 0
+    assert st["overflowed"] == 0                 # no query needed the FP64 fallback
     for warm in (to_dev(config0["base"]), to_dev(np.zeros(4096, np.int64)), idx.clone()):
-        i2, d2 = L.dd_project(ds, states, warm_start_idx=warm, mode="ann")
+        i2, d2, s2 = L.dd_project(ds, states, warm_start_idx=warm, mode="ann", stats=True)
         assert torch.equal(i2, idx) and torch.equal(d2, dist)
+        assert s2["overflowed"] == 0
 
 
 def test_ann_warm_start_reduces_work(L, config0):

@@ -117,7 +117,13 @@ def test_config3_ann_equals_bf16_scan_1e9(L, config3):
     qe, qs, base = ddsynth.queries_generated(N, 1003, 32768, 2003)
     states = torch.from_numpy(ddsynth.states(qe, qs)).cuda()
     ia, da, st = L.dd_project(ds, states, mode="ann", stats=True)
-    _say(f"1e9 ann exact: {st['scan_ms']:.1f} ms walk, {st['visited'] / 32768:.0f} points/query")
+    _say(f"1e9 ann exact: {st['scan_ms']:.1f} ms walk, {st['visited'] / 32768:.0f} points/query, "
+         f"{st['candidates'] / 32768:.2f} candidates/query, {st['overflowed']} overflowed")
+    # The pruning bound is tight: no list overflows, and the certified band
+    # around the nearest distance holds few other points (1.06 per query
+    # measured).  A bound that is valid but too loose (a wrong wave minimum)
+    # keeps every answer exact through the FP64 fallback and shows only here.
+    assert st["overflowed"] == 0 and st["candidates"] <= 1.5 * 32768
     ib, db = L.dd_project(ds, states, mode="bf16")
     assert torch.equal(ia, ib) and torch.equal(da, db)
     warm = torch.from_numpy(base).cuda()

@@ -77,9 +77,11 @@ def test_kmeans_exact_equals_oracle_and_box_tree(L, config0):
     assert torch.equal(idx, ia) and torch.equal(dist, da)
     assert st["visited"] > 0 and st["leaves"] > 0 and 0 < st["leaf_boxes"] <= st["boxes"]
     assert st["nodes"] >= 1 and sa["nodes"] == 0          # k-means nodes expanded (root first)
+    assert st["overflowed"] == 0 and sa["overflowed"] == 0    # no FP64 fallback
     for warm in (to_dev(config0["base"]), to_dev(np.zeros(4096, np.int64)), idx.clone()):
         i2, d2, s2 = L.dd_project(ds, states, warm_start_idx=warm, mode="kmeans", stats=True)
         assert torch.equal(i2, idx) and torch.equal(d2, dist)
+        assert s2["overflowed"] == 0
     assert s2["visited"] <= st["visited"]          # warm start at the answer: less work
 
 
