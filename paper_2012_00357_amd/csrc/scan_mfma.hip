@@ -67,15 +67,42 @@ __device__ inline void split_qblock(int S, int& split, int64_t& qblock) {
 // ---------------------------------------------------------------------------
 constexpr int kG64 = 4;                                  // 16-query groups per wave
 constexpr int kQ64 = 4 * kG64 * 16;                      // queries per workgroup
-constexpr int kStage64 = kTile64 * 12 / 256;             // doubles of a tile staged per thread
-static_assert(kTile64 <= 256 && kTile64 * 12 % 256 == 0, "one staged row norm per thread");
+// A tile is copied from HBM to LDS in 1 KB pieces, one 16-byte load per lane
+// (global_load_lds_dwordx4: lane i's bytes land at the piece's LDS address
+// plus 16 i): the rows (96 B each, row-major as in the pack), then the norms.
+constexpr int kRowPieces64 = kTile64 * 12 * 8 / 1024;
+constexpr int kPieces64 = kRowPieces64 + kTile64 * 8 / 1024;
+static_assert(kTile64 * 8 % 1024 == 0, "whole 1 KB pieces of rows and norms");
+
+typedef __attribute__((address_space(3))) unsigned char lds_byte;
+
+// Copy a tile's rows and norms to LDS; the four waves of a workgroup take
+// every fourth piece.  The copies complete asynchronously: a wait for the
+// vector-memory counter and a barrier come before any wave reads them.
+__device__ inline void tile_to_lds64(const double* __restrict__ w64, const double* __restrict__ n64,
+                                     int64_t t, double* xs, double* ns, int wave, int lane) {
+  const unsigned char* rows = reinterpret_cast<const unsigned char*>(w64 + t * kTile64 * 12);
+  const unsigned char* norms = reinterpret_cast<const unsigned char*>(n64 + t * kTile64);
+#pragma unroll
+  for (int c = wave; c < kPieces64; c += 4) {
+    const bool r = c < kRowPieces64;
+    const unsigned char* src = (r ? rows + 1024 * c : norms + 1024 * (c - kRowPieces64)) + 16 * lane;
+    lds_byte* dst = (lds_byte*)(r ? (unsigned char*)xs + 1024 * c
+                                  : (unsigned char*)ns + 1024 * (c - kRowPieces64));
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+  }
+}
+
+// s_waitcnt vmcnt(0): every copy this wave issued has reached LDS.
+__device__ inline void wait_copies() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __global__ __launch_bounds__(256, 3) void scan64_kernel(
     const double* __restrict__ w64, const double* __restrict__ n64, int64_t n_tiles, int64_t N,
     const double* __restrict__ qw, const double* __restrict__ qn2, const double* __restrict__ u64,
     const int* __restrict__ invalid, double xmax, QueryList L, CandBuf cb) {
-  __shared__ double xs[2][12][kTile64];
-  __shared__ double ns[2][kTile64];
+  // rows as in the pack (x of row r at xs[buf][12 r + k]), then their norms
+  __shared__ __align__(16) double xs[2][kTile64 * 12];
+  __shared__ __align__(16) double ns[2][kTile64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
   const int S = cb.S;
@@ -112,35 +139,24 @@ __global__ __launch_bounds__(256, 3) void scan64_kernel(
   }
 
   if (t0 < t1) {
-    auto load = [&](int64_t t, double (&reg)[kStage64], double& nreg) {
-      const double* src = w64 + t * kTile64 * 12;
-#pragma unroll
-      for (int r = 0; r < kStage64; ++r) reg[r] = src[tid + 256 * r];
-      nreg = (tid < kTile64) ? n64[t * kTile64 + tid] : 0.0;
-    };
-    auto store = [&](int buf, const double (&reg)[kStage64], double nreg) {
-#pragma unroll
-      for (int r = 0; r < kStage64; ++r) {
-        int e = tid + 256 * r;
-        xs[buf][e % 12][e / 12] = reg[r];
-      }
-      if (tid < kTile64) ns[buf][tid] = nreg;
-    };
-    double reg[kStage64], nreg;
-    load(t0, reg, nreg);
-    store(0, reg, nreg);
+    // the wave index as a scalar, so that the copy loop and its LDS addresses are too
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    tile_to_lds64(w64, n64, t0, xs[0], ns[0], wu, lane);
+    wait_copies();
     __syncthreads();
     for (int64_t t = t0; t < t1; ++t) {
       const int cur = (int)((t - t0) & 1);
       const bool more = t + 1 < t1;
-      if (more) load(t + 1, reg, nreg);
+      // the next tile goes to the other buffer, which every wave finished
+      // reading before the barrier that ended the previous tile
+      if (more) tile_to_lds64(w64, n64, t + 1, xs[cur ^ 1], ns[cur ^ 1], wu, lane);
       double tm[kG64];
 #pragma unroll
       for (int g = 0; g < kG64; ++g) tm[g] = INFINITY;
 #pragma unroll 2
       for (int rb = 0; rb < kTile64 / 16; ++rb) {
         const int r0 = rb * 16 + col;
-        double a0 = xs[cur][kq][r0], a1 = xs[cur][4 + kq][r0], a2 = xs[cur][8 + kq][r0];
+        double a0 = xs[cur][12 * r0 + kq], a1 = xs[cur][12 * r0 + 4 + kq], a2 = xs[cur][12 * r0 + 8 + kq];
         double nr[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) nr[i] = ns[cur][rb * 16 + kq + 4 * i];
@@ -171,9 +187,9 @@ __global__ __launch_bounds__(256, 3) void scan64_kernel(
             f64x4_t acc;
 #pragma unroll
             for (int i = 0; i < 4; ++i) acc[i] = ns[cur][rb * 16 + kq + 4 * i];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][kq][r0], b[g][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][4 + kq][r0], b[g][1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][8 + kq][r0], b[g][2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][12 * r0 + kq], b[g][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][12 * r0 + 4 + kq], b[g][1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[cur][12 * r0 + 8 + kq], b[g][2], acc, 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int row = rb * 16 + kq + 4 * i;
@@ -186,7 +202,7 @@ __global__ __launch_bounds__(256, 3) void scan64_kernel(
           }
         }
       }
-      if (more) store(cur ^ 1, reg, nreg);
+      wait_copies();
       __syncthreads();
     }
   }
