@@ -98,6 +98,15 @@ struct AnnArgs {
   unsigned long long* counters;
 };
 
+// The walk reads the tree and the leaves, which no kernel writes while it runs,
+// through the constant address space where the address is the same in every
+// lane (a leaf's centre and radius, a node's box and child range): such loads
+// become scalar loads into SGPRs instead of 64 identical vector loads.
+template <class T>
+__device__ inline const __attribute__((address_space(4))) T* uniform_ptr(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
 // v from another lane of the same row of 16 (DPP control C); every lane active
 template <int C>
 __device__ inline float dpp_f(float v) {
@@ -134,13 +143,12 @@ __device__ inline float half_hi(uint32_t w) {
 // principal-axis coordinates for the box tree, whitened for the k-means tree).
 __device__ inline void leaf_query(const float* __restrict__ meta, int64_t leaf, const float qf[12],
                                   float qs[12], float& r, uint32_t& count) {
-  const float4* m = reinterpret_cast<const float4*>(meta + 16 * leaf);
-  const float4 a = m[0], b = m[1], c = m[2], e = m[3];
-  const float cc[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
-  r = e.x;
-  count = __builtin_bit_cast(uint32_t, e.z);
+  const auto* m = uniform_ptr(meta + 16 * leaf);
+  r = m[12];
+  const float inv_r = m[13];
+  count = __builtin_bit_cast(uint32_t, m[14]);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) qs[k] = (qf[k] - cc[k]) * e.y;
+  for (int k = 0; k < 12; ++k) qs[k] = (qf[k] - m[k]) * inv_r;
 }
 
 // s~ of stored point pos (FP16 scaled offsets, direct form, fixed order).
@@ -328,8 +336,10 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
   if (A.invalid[q]) {
     if (lane == 0) {
       A.out.idx[q] = -1;
-      if (A.out.dist) A.out.dist[q] = NAN;
-      if (TOP2) A.dist2[q] = NAN;
+      // a quiet NaN by its bits: this file is compiled without NaN semantics
+      const double nan64 = __builtin_bit_cast(double, 0x7FF8000000000000ull);
+      if (A.out.dist) A.out.dist[q] = nan64;
+      if (TOP2) A.dist2[q] = nan64;
     }
     return;
   }
@@ -386,7 +396,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
       // child records [c0, c0 + cnt) of k-means tree node `node`; their boxes
       // are quantised inside the node's box; val is the code
       float plo[12], phi[12], amax = 0.0f;
-      const float* pb = A.kmt_nbox + 24 * (int64_t)node;
+      const auto* pb = uniform_ptr(A.kmt_nbox + 24 * (int64_t)node);
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
         plo[a] = approx ? 0.0f : pb[a];
@@ -406,7 +416,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
       leaf_boxes += (unsigned long long)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
     } else if (lv == 0 && A.levels >= 2) {
       // leaf boxes quantised inside their parent (the node being expanded)
-      const float* pb = A.box[1] + 24 * (c0 / kAnnFan);
+      const auto* pb = uniform_ptr(A.box[1] + 24 * (c0 / kAnnFan));
       float plo[12], step[12], amax = 0.0f;
 #pragma unroll
       for (int a = 0; a < 12; ++a) {
@@ -467,7 +477,8 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
     const int64_t pos = idx * kAnnLeaf + lane;
     float qs[12], r;
     uint32_t count;
-    leaf_query(A.meta, idx, KMT ? qf : yq, qs, r, count);
+    // the leaf index is the same in every lane: say so, for scalar loads
+    leaf_query(A.meta, (int64_t)__builtin_amdgcn_readfirstlane((int)idx), KMT ? qf : yq, qs, r, count);
     const bool v = KMT ? lane < (int)count : pos < A.N;
     float s = INFINITY, E = 0.0f;
     if (v) {
@@ -531,8 +542,8 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
 
   auto expand_node = [&](uint32_t node) __attribute__((always_inline)) {
     ++nodes;
-    const int2 r = A.kmt_node[node];
-    expand(1, r.x, r.y - r.x, node);
+    const auto* r = uniform_ptr(reinterpret_cast<const int*>(A.kmt_node) + 2 * (int64_t)node);
+    expand(1, r[0], r[1] - r[0], node);
   };
   if (KMT) expand_node(0);
   else expand(A.levels - 1, 0, (int)A.n[A.levels - 1], 0);

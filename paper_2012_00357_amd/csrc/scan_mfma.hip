@@ -83,8 +83,7 @@ __device__ inline void tile_to_lds64(const double* __restrict__ w64, const doubl
                                      int64_t t, double* xs, double* ns, int wave, int lane) {
   const unsigned char* rows = reinterpret_cast<const unsigned char*>(w64 + t * kTile64 * 12);
   const unsigned char* norms = reinterpret_cast<const unsigned char*>(n64 + t * kTile64);
-#pragma unroll
-  for (int c = wave; c < kPieces64; c += 4) {
+  for (int c = wave; c < kPieces64; c += 4) {   // a scalar loop: wave is uniform
     const bool r = c < kRowPieces64;
     const unsigned char* src = (r ? rows + 1024 * c : norms + 1024 * (c - kRowPieces64)) + 16 * lane;
     lds_byte* dst = (lds_byte*)(r ? (unsigned char*)xs + 1024 * c
