@@ -313,17 +313,18 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, float& aux, int la
 // the warm-start point bounds no branch), and the warm-start point remains a
 // candidate, so the answer is never farther than the previous association.
 //
-// Occupancy: six waves per SIMD for the box-tree walk (80 registers, no
-// spills; its pace is set by the latency of dependent steps, which more waves
-// hide), five for the k-means walk, whose larger state would spill at six.
+// Occupancy: at least six waves per SIMD (at most 80 registers, no spills):
+// a walk's pace is set by the latency of its dependent steps, which more waves
+// hide.  The wave index is declared uniform, so that the query, its bounds and
+// the per-wave statistics live in scalar registers.
 template <bool TOP2, bool KMT>
-__global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
+__global__ __launch_bounds__(256, 6) void ann_walk_kernel(AnnArgs A) {
   __shared__ uint32_t s_code[kWaves][kStack];
   __shared__ float s_lb[kWaves][kStack];
   __shared__ uint32_t s_cpos[kWaves][kCand];
   __shared__ float s_clb[kWaves][kCand];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t p = (int64_t)blockIdx.x * kWaves + wv;
   if (p >= list_len(A.L)) return;
   const int64_t q = list_query(A.L, p);
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
   // push the children [c0, c0 + cnt) of level lv that may hold candidates,
   // farthest first (so the nearest is on top of the stack)
   int sp = 0;
-  unsigned long long boxes = 0, leaves = 0, visited = 0, leaf_boxes = 0;
+  uint32_t boxes = 0, leaves = 0, visited = 0, leaf_boxes = 0;   // per query: below 2^32
   uint32_t nodes = 0;
   auto expand = [&](int lv, int64_t c0, int cnt, uint32_t node) {
     float key = INFINITY;     // visiting order
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
           key = approx ? fmaxf(dc, 0.0f) : bnd;
         }
       }
-      leaf_boxes += (unsigned long long)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
+      leaf_boxes += (uint32_t)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
     } else if (lv == 0 && A.levels >= 2) {
       // leaf boxes quantised inside their parent (the node being expanded)
       const auto* pb = uniform_ptr(A.box[1] + 24 * (c0 / kAnnFan));
@@ -467,8 +468,8 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
     }
     __builtin_amdgcn_wave_barrier();
     sp += k;
-    boxes += (unsigned long long)cnt;
-    if (!KMT && lv == 0) leaf_boxes += (unsigned long long)cnt;
+    boxes += (uint32_t)cnt;
+    if (!KMT && lv == 0) leaf_boxes += (uint32_t)cnt;
   };
 
   // one leaf: 64 consecutive sorted points, one per lane, data already loaded
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
     const bool keep = v && (s - E <= U);
     const uint64_t km = __ballot(keep);
     const int cnt = __popcll(km);
-    visited += (unsigned long long)__popcll(__ballot(v));
+    visited += (uint32_t)__popcll(__ballot(v));
     ++leaves;
     if (nc + cnt > kCand) {
       // drop the candidates the bound has excluded since they were kept
@@ -537,7 +538,7 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
     }
     __builtin_amdgcn_wave_barrier();
     nc += cnt;
-    if (budget > 0 && leaves >= (unsigned long long)budget) stop = true;
+    if (budget > 0 && leaves >= (uint32_t)budget) stop = true;
   };
 
   auto expand_node = [&](uint32_t node) __attribute__((always_inline)) {
@@ -604,10 +605,10 @@ __global__ __launch_bounds__(256, KMT ? 5 : 6) void ann_walk_kernel(AnnArgs A) {
 
   if (lane == 0) {
     unsigned long long* c = A.counters + kCounterStride * (blockIdx.x % kCounterSlots);
-    atomicAdd(c + 0, visited);
-    atomicAdd(c + 1, boxes);
-    atomicAdd(c + 2, leaves);
-    atomicAdd(c + 4, leaf_boxes);
+    atomicAdd(c + 0, (unsigned long long)visited);
+    atomicAdd(c + 1, (unsigned long long)boxes);
+    atomicAdd(c + 2, (unsigned long long)leaves);
+    atomicAdd(c + 4, (unsigned long long)leaf_boxes);
     if (KMT) atomicAdd(c + 5, (unsigned long long)nodes);
   }
   if (ovf) {
