@@ -239,3 +239,67 @@ def decode_leaf_boxes(lo, hi, eps):
     dlo = ((ql * step.astype(np.float64) + plo32.astype(np.float64)).astype(np.float32) - delta).astype(np.float32)
     dhi = ((qh * step.astype(np.float64) + plo32.astype(np.float64)).astype(np.float32) + delta).astype(np.float32)
     return dlo, dhi
+
+
+def f32_ru(x):
+    """FP64 -> FP32 rounded up."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    return np.where(f.astype(np.float64) < x, np.nextafter(f, np.float32(np.inf)), f).astype(np.float32)
+
+
+def ball_bound(qf, c, r, slack, ulp=1):
+    """The k-means walk's ball bound sqrt(sum (q - c)^2) (1 - 2^-19) - slack - r
+    in FP32 (f_d = 1), the square root `ulp` units off."""
+    t = (qf[:, None, :] - c[None]).astype(np.float32)
+    ss = np.zeros(t.shape[:-1], np.float32)
+    for k in range(12):
+        tk = t[..., k].astype(np.float64)
+        ss = (ss.astype(np.float64) + tk * tk).astype(np.float32)
+    dc = (sqrt_ulp(ss, ulp) * LB_SHRINK - slack[:, None]).astype(np.float32)
+    return (dc - r[None]).astype(np.float32).astype(np.float64)
+
+
+def test_kmeans_ball_lower_bound(C0):
+    """A k-means child record bounds its points by the ball (FP32 centre c,
+    radius r = max |x - c| rounded up): |q - c| (1 - 2^-19) - 2^-22 (|q| +
+    max |x|) - r, evaluated in FP32 from the query's FP32 whitened
+    coordinates, stays below the distance to every point of the record, on
+    ordinary data shifted far from the origin and on points placed on the
+    sphere with queries just outside it along the same ray (where the true
+    distance equals the gap); without the slack and the shrink the bound exceeds
+    the distance for some of those."""
+    e, s = ddsynth.data_points(64 * 64, 4207)
+    qe, qs, _ = ddsynth.queries(e, s, 64, 4208)
+    for shift in (0.0, 40.0):
+        w = oracle.whiten(e, s, C0) + shift
+        q = oracle.whiten(qe, qs, C0) + shift
+        q = np.concatenate([q, w[::331][:8]])
+        grp = w.reshape(-1, 64, 12)
+        c = grp.mean(1).astype(np.float32)
+        r = f32_ru(np.sqrt(((grp - c[:, None, :].astype(np.float64)) ** 2).sum(2)).max(1) * (1.0 + 1e-12))
+        qnorm = np.sqrt((q ** 2).sum(1)).astype(np.float32)
+        xmax = np.float32(np.sqrt((w ** 2).sum(1)).max())
+        slack = (EPS22 * (qnorm + xmax) + np.float32(1e-30)).astype(np.float32)
+        lb = ball_bound(q.astype(np.float32), c, r, slack)
+        true = np.sqrt(((q[:, None, None, :] - grp[None]) ** 2).sum(3)).min(2)
+        assert np.all(lb <= true), (shift, float((lb - true).max()))
+    # points on a sphere, queries just outside along their rays
+    rng = np.random.default_rng(8)
+    n = 2000
+    c = rng.uniform(30.0, 50.0, (n, 12)).astype(np.float32)
+    u = rng.normal(size=(n, 12))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    rad = rng.uniform(0.5, 3.0, n)
+    gap = rng.uniform(1e-6, 1e-3, n)
+    p = c.astype(np.float64) + rad[:, None] * u                   # the record's point on the ray
+    q64 = c.astype(np.float64) + (rad + gap)[:, None] * u
+    r = f32_ru(rad * (1.0 + 1e-12))
+    qnorm = np.sqrt((q64 ** 2).sum(1)).astype(np.float32)
+    xmax = np.float32(np.sqrt((p ** 2).sum(1)).max())
+    slack = (EPS22 * (qnorm + xmax) + np.float32(1e-30)).astype(np.float32)
+    qf = q64.astype(np.float32)
+    true = np.sqrt(((q64 - p) ** 2).sum(1))
+    lb = np.diagonal(ball_bound(qf, c, r, slack))
+    assert np.all(lb <= true)
+    bare = np.diagonal(ball_bound(qf, c, r, np.zeros(n, np.float32))) / float(LB_SHRINK)
+    assert np.any(bare > true)
