@@ -306,12 +306,15 @@ __device__ inline void wave_sort64(float& key, uint32_t& val, float& aux, int la
 // candidates hold every point within the second-smallest distance.
 //
 // KMT: walk the k-means tree instead of the box tree (ball bounds, padded
-// leaf blocks addressed by slot).  With f_d < 1 the walk is the approximate
-// search of Section 4.2: siblings are visited nearest centre first, a child is
-// entered while |q - c| - f_d r stays below the best distance the walk itself
-// has found (none at the start, so the first descent always reaches a leaf:
-// the warm-start point bounds no branch), and the warm-start point remains a
-// candidate, so the answer is never farther than the previous association.
+// leaf blocks addressed by slot).  Siblings are visited nearest centre first
+// (the exact walk too: a near centre finds a small distance sooner than the
+// smallest lower bound does, so fewer branches stay open; the box tree has no
+// centres above its leaves and keeps the bound order).  With f_d < 1 the walk
+// is the approximate search of Section 4.2: a child is entered while
+// |q - c| - f_d r stays below the best distance the walk itself has found (none
+// at the start, so the first descent always reaches a leaf: the warm-start
+// point bounds no branch), and the warm-start point remains a candidate, so the
+// answer is never farther than the previous association.
 //
 // Occupancy: at least six waves per SIMD (at most 80 registers, no spills):
 // a walk's pace is set by the latency of its dependent steps, which more waves
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(256, 6) void ann_walk_kernel(AnnArgs A) {
   uint32_t nodes = 0;
   auto expand = [&](int lv, int64_t c0, int cnt, uint32_t node) {
     float key = INFINITY;     // visiting order
-    float bnd = INFINITY;     // entry test, kept on the stack (the bound itself unless approx)
+    float bnd = INFINITY;     // entry test, kept on the stack (k-means tree; the box tree's is its key)
     uint32_t val = 0;
     if (KMT) {
       // child records [c0, c0 + cnt) of k-means tree node `node`; their boxes
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256, 6) void ann_walk_kernel(AnnArgs A) {
                                    plo, phi, delta, val, dc);
         if (lb <= (approx ? Ua : U)) {
           bnd = fmaxf(lb, 0.0f);
-          key = approx ? fmaxf(dc, 0.0f) : bnd;
+          key = fmaxf(dc, 0.0f);
         }
       }
       leaf_boxes += (uint32_t)__popcll(__ballot(lane < cnt && (val >> 28) == 0));
@@ -459,11 +462,11 @@ __global__ __launch_bounds__(256, 6) void ann_walk_kernel(AnnArgs A) {
         s_lb[wv][sp + k - 1 - rank] = bnd;
       }
     } else {
-      if (approx) wave_sort64<true>(key, val, bnd, lane);
+      if (KMT) wave_sort64<true>(key, val, bnd, lane);
       else wave_sort64<false>(key, val, bnd, lane);
       if (lane < k) {
         s_code[wv][sp + k - 1 - lane] = val;
-        s_lb[wv][sp + k - 1 - lane] = approx ? bnd : key;
+        s_lb[wv][sp + k - 1 - lane] = KMT ? bnd : key;
       }
     }
     __builtin_amdgcn_wave_barrier();
