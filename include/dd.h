@@ -95,12 +95,13 @@ typedef enum dd_mode {
    * |q - c| - f_d r (with f_d = 1 also its box distance) exceeds the best
    * certified distance so far.  Same certified FP32 arithmetic, FP64 rerank,
    * budget and warm-start rules as DD_ANN; exact with ann_budget = 0 and
-   * f_d = 1 (ann_radius_discount = 0), approximate otherwise.  With f_d < 1
-   * the walk is the search of Section 4.2: siblings nearest centre first, a
-   * child entered while |q - c| - f_d r is below the best distance the walk
-   * has found itself (the first descent reaches a leaf whatever the warm
-   * start); the warm-start point stays a candidate, so the answer is never
-   * farther than it. */
+   * f_d = 1 (ann_radius_discount = 0), approximate otherwise.  Siblings are
+   * visited nearest centre first (so a budget keeps the leaves nearest the
+   * query's path of centres).  With f_d < 1 the walk is the search of
+   * Section 4.2: a child is entered while |q - c| - f_d r is below the best
+   * distance the walk has found itself (the first descent reaches a leaf
+   * whatever the warm start); the warm-start point stays a candidate, so the
+   * answer is never farther than it. */
   DD_KMEANS = 6
 } dd_mode;
 
